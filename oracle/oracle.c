@@ -1,0 +1,185 @@
+/*
+ * Oracle: plain, slow, obviously correct CPU solver for batches of
+ * independent tridiagonal systems.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline use it.  It shares no code with the GPU library.
+ *
+ * What it computes: x = A^{-1} d for every system, where A is tridiagonal
+ * with sub-diagonal a, diagonal b and super-diagonal c (the problem statement
+ * "Ax = d, N times; input a, b, c, d; output x" of the paper's Algorithms 1
+ * and 2).  The divide-and-conquer method of the paper (Sec. 2.1: decoupled
+ * solve, reduced interface solve, correction x = x~ - Y y) is a direct method
+ * that reaches exactly this x in exact arithmetic, so the oracle is that
+ * definition computed by the textbook Thomas algorithm (LU factorisation
+ * without pivoting, forward elimination then back substitution; the
+ * sequential O(n) method the paper's introduction starts from).
+ *
+ * Conventions: a[0] and c[n-1] of every system are never read (there is no
+ * x_{-1} or x_n).  Arithmetic is IEEE FP64 (or x87 80-bit long double for the
+ * *_ld variant), round to nearest, no fused multiply-add (built with
+ * -ffp-contract=off), no fast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+#define ORACLE_ENOMEM (-2)
+#define ORACLE_ESINGULAR (-4)
+
+/* Thomas algorithm, FP64.  cp/dp are caller scratch of length n.
+ * Forward:  c'_0 = c_0/b_0, d'_0 = d_0/b_0;
+ *           m_i = b_i - a_i c'_{i-1}, c'_i = c_i/m_i, d'_i = (d_i - a_i d'_{i-1})/m_i.
+ * Backward: x_{n-1} = d'_{n-1}, x_i = d'_i - c'_i x_{i+1}. */
+static int thomas_f64(int64_t n, const double *a, const double *b, const double *c,
+                      const double *d, double *x, double *cp, double *dp)
+{
+    double m = b[0];
+    if (m == 0.0 || !isfinite(m)) return ORACLE_ESINGULAR;
+    cp[0] = (n > 1) ? c[0] / m : 0.0;
+    dp[0] = d[0] / m;
+    for (int64_t i = 1; i < n; ++i) {
+        m = b[i] - a[i] * cp[i - 1];
+        if (m == 0.0 || !isfinite(m)) return ORACLE_ESINGULAR;
+        cp[i] = (i < n - 1) ? c[i] / m : 0.0;
+        dp[i] = (d[i] - a[i] * dp[i - 1]) / m;
+    }
+    x[n - 1] = dp[n - 1];
+    for (int64_t i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
+    return ORACLE_OK;
+}
+
+/* The same algorithm carried out in long double (x87 extended precision); the
+ * result is rounded to double once at the end.  Used to tell the oracle's own
+ * rounding apart from a candidate's error on ill-conditioned systems. */
+static int thomas_ld(int64_t n, const double *a, const double *b, const double *c,
+                     const double *d, double *x, long double *cp, long double *dp)
+{
+    long double m = b[0];
+    if (m == 0.0L || !isfinite((double)m)) return ORACLE_ESINGULAR;
+    cp[0] = (n > 1) ? (long double)c[0] / m : 0.0L;
+    dp[0] = (long double)d[0] / m;
+    for (int64_t i = 1; i < n; ++i) {
+        m = (long double)b[i] - (long double)a[i] * cp[i - 1];
+        if (m == 0.0L || !isfinite((double)m)) return ORACLE_ESINGULAR;
+        cp[i] = (i < n - 1) ? (long double)c[i] / m : 0.0L;
+        dp[i] = ((long double)d[i] - (long double)a[i] * dp[i - 1]) / m;
+    }
+    long double xn = dp[n - 1];
+    x[n - 1] = (double)xn;
+    /* keep the running x in long double: x_i = d'_i - c'_i x_{i+1} */
+    for (int64_t i = n - 2; i >= 0; --i) {
+        xn = dp[i] - cp[i] * xn;
+        x[i] = (double)xn;
+    }
+    return ORACLE_OK;
+}
+
+/* One contiguous system. precision: 0 = FP64, 1 = long double. */
+int oracle_thomas(int64_t n, const double *a, const double *b, const double *c,
+                  const double *d, double *x, int precision)
+{
+    if (n < 1 || !a || !b || !c || !d || !x) return ORACLE_EINVAL;
+    int rc;
+    if (precision == 0) {
+        double *w = (double *)malloc(2 * (size_t)n * sizeof(double));
+        if (!w) return ORACLE_ENOMEM;
+        rc = thomas_f64(n, a, b, c, d, x, w, w + n);
+        free(w);
+    } else {
+        long double *w = (long double *)malloc(2 * (size_t)n * sizeof(long double));
+        if (!w) return ORACLE_ENOMEM;
+        rc = thomas_ld(n, a, b, c, d, x, w, w + n);
+        free(w);
+    }
+    return rc;
+}
+
+/*
+ * A batch of systems in a strided or ragged layout.  Each system is gathered
+ * into contiguous arrays, solved by oracle_thomas, and its x scattered back.
+ *
+ * Uniform layout (offsets == NULL): system s = s0 + nsys0*s1 has row i at
+ *     s0*sys_stride0 + s1*sys_stride1 + i*row_stride        (element units)
+ * Ragged layout: system s (0 <= s < nsys0, nsys1 == 1) occupies elements
+ *     offsets[s] .. offsets[s+1]-1, one row each.
+ * coef_mode 0: a, b, c have d's layout.  coef_mode 1: a, b, c are length-n
+ *     tables shared by every system; shift (may be NULL) adds shift[s] to
+ *     every diagonal entry of system s.
+ * Systems whose solve fails are reported through status[s] (may be NULL);
+ * the return value is the number of failed systems, or a negative error.
+ * sys_begin/sys_end restrict the solve to a range of system indices.
+ */
+int64_t oracle_solve_batch(int64_t n, int64_t nsys0, int64_t nsys1, int64_t row_stride,
+                           int64_t sys_stride0, int64_t sys_stride1, const int64_t *offsets,
+                           int coef_mode, const double *a, const double *b, const double *c,
+                           const double *shift, const double *d, double *x,
+                           int precision, int64_t sys_begin, int64_t sys_end, int32_t *status)
+{
+    if (!a || !b || !c || !d || !x) return ORACLE_EINVAL;
+    if (offsets && nsys1 != 1) return ORACLE_EINVAL;
+    if (offsets && coef_mode != 0) return ORACLE_EINVAL;
+    int64_t nsys = nsys0 * nsys1;
+    if (sys_begin < 0 || sys_end > nsys || sys_begin > sys_end) return ORACLE_EINVAL;
+    int64_t nmax = n;
+    if (offsets) {
+        nmax = 0;
+        for (int64_t s = sys_begin; s < sys_end; ++s)
+            if (offsets[s + 1] - offsets[s] > nmax) nmax = offsets[s + 1] - offsets[s];
+    }
+    if (nmax < 1) return (sys_end > sys_begin) ? ORACLE_EINVAL : 0;
+    double *buf = (double *)malloc(5 * (size_t)nmax * sizeof(double));
+    int64_t *rows = (int64_t *)malloc((size_t)nmax * sizeof(int64_t));
+    if (!buf || !rows) { free(buf); free(rows); return ORACLE_ENOMEM; }
+    double *sa = buf, *sb = buf + nmax, *sc = buf + 2 * nmax, *sd = buf + 3 * nmax,
+           *sx = buf + 4 * nmax;
+    int64_t failed = 0;
+    for (int64_t s = sys_begin; s < sys_end; ++s) {
+        int64_t ns;
+        if (offsets) {
+            ns = offsets[s + 1] - offsets[s];
+            for (int64_t i = 0; i < ns; ++i) rows[i] = offsets[s] + i;
+        } else {
+            ns = n;
+            int64_t s0 = s % nsys0, s1 = s / nsys0;
+            int64_t base = s0 * sys_stride0 + s1 * sys_stride1;
+            for (int64_t i = 0; i < ns; ++i) rows[i] = base + i * row_stride;
+        }
+        for (int64_t i = 0; i < ns; ++i) {
+            sd[i] = d[rows[i]];
+            if (coef_mode == 0) {
+                sa[i] = a[rows[i]];
+                sb[i] = b[rows[i]];
+                sc[i] = c[rows[i]];
+            } else {
+                sa[i] = a[i];
+                sb[i] = shift ? b[i] + shift[s] : b[i];
+                sc[i] = c[i];
+            }
+        }
+        int rc = ns > 0 ? oracle_thomas(ns, sa, sb, sc, sd, sx, precision) : ORACLE_OK;
+        if (status) status[s] = rc;
+        if (rc != ORACLE_OK) { ++failed; continue; }
+        for (int64_t i = 0; i < ns; ++i) x[rows[i]] = sx[i];
+    }
+    free(buf);
+    free(rows);
+    return failed;
+}
+
+/* y = A x for one contiguous system (FP64, no FMA): the residual check's
+ * matrix-vector product.  a[0] and c[n-1] are not read. */
+void oracle_matvec(int64_t n, const double *a, const double *b, const double *c,
+                   const double *x, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double v = b[i] * x[i];
+        if (i > 0) v += a[i] * x[i - 1];
+        if (i < n - 1) v += c[i] * x[i + 1];
+        y[i] = v;
+    }
+}
