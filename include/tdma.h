@@ -1,0 +1,233 @@
+/*
+ * tdma.h -- C ABI of the MI355X batched divide-and-conquer tridiagonal solver.
+ *
+ * Problem (paper, Algorithms 1 and 2): "A x = d, N times; input a, b, c, d;
+ * output x", where a, b, c are the sub-, main and super-diagonals of a
+ * tridiagonal matrix A (Sec. 3.2.1).  Each system is split into P partitions;
+ * every partition is reduced by a modified Thomas sweep to two interface
+ * equations (Stage A, Sec. 2.1 step 1), the 2P-row interface system is
+ * solved (Stage B, step 3), and the interior unknowns are recovered from the
+ * interface values (Stage C, step 5: x = x~ - Y y).
+ *
+ * General rules for every entry point:
+ *  - Data pointers (a, b, c, b_shift, d, x) are DEVICE pointers owned by the
+ *    caller; the library never frees or retains them past the call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    are stream-ordered and asynchronous unless stated otherwise.
+ *  - x may alias d (in-place solve).  x must not alias a, b, c or b_shift.
+ *  - a[0] and c[n-1] of every system are never read (no x_{-1}, no x_n).
+ *  - No pivoting: results are defined for diagonally dominant systems and
+ *    M-matrices (the paper's ADI and Poisson operators, Sec. 5).
+ *  - Return value: a tdma_status.  Nothing is thrown across the ABI; details
+ *    of the last failure on the calling thread are in tdma_last_error().
+ *  - A zero or non-finite pivot met on the device sets a sticky per-device
+ *    flag, reported as TDMA_ESINGULAR by tdma_check() (which clears it).
+ *  - Element counts, strides and offsets are in ELEMENTS, not bytes.
+ */
+#ifndef TDMA_H
+#define TDMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TDMA_OK = 0,
+    TDMA_EINVAL = -1,        /* invalid argument (host-side validation)            */
+    TDMA_ENOMEM = -2,        /* device or host allocation failed                   */
+    TDMA_EHIP = -3,          /* a HIP runtime call failed                          */
+    TDMA_ESINGULAR = -4,     /* zero or non-finite pivot met on the device         */
+    TDMA_ENOCONV = -5,       /* refinement missed its tolerance (no fallback)      */
+    TDMA_EUNSUPPORTED = -6   /* valid but unsupported combination                  */
+} tdma_status;
+
+typedef enum { TDMA_F64 = 0, TDMA_F32 = 1 } tdma_dtype;
+
+typedef enum {
+    TDMA_COEF_LIKE_D = 0,    /* a, b, c are laid out exactly like d (per-row)      */
+    TDMA_COEF_SHARED = 1     /* a, b, c are length-n tables used by every system   */
+} tdma_coef_mode;
+
+/*
+ * Where the systems live.  Uniform form (offsets == NULL): system
+ * k = s0 + nsys0*s1 (0 <= s0 < nsys0, 0 <= s1 < nsys1) has its row i
+ * (0 <= i < n) at element  s0*sys_stride0 + s1*sys_stride1 + i*row_stride.
+ * This expresses the x-, y- and z-direction lines of a 3-D field (the
+ * paper's assembly/reinsertion, Sec. 8.1) without copying.
+ * Ragged form (offsets != NULL): `offsets` is a HOST array of nsys0+1
+ * non-decreasing int64 entries, nsys1 must be 1, and system k occupies the
+ * contiguous elements offsets[k] .. offsets[k+1]-1; `n` is ignored.
+ * Every system needs n >= 2 (ragged: 2 <= length <= 65536).
+ */
+typedef struct tdma_layout {
+    int64_t n;
+    int64_t nsys0, nsys1;
+    int64_t row_stride;
+    int64_t sys_stride0, sys_stride1;
+    const int64_t *offsets;
+} tdma_layout;
+
+/*
+ * The coefficients.  mode TDMA_COEF_LIKE_D: a, b, c have d's layout.
+ * mode TDMA_COEF_SHARED: a, b, c are contiguous length-n tables shared by
+ * every system -- the paper's observation that the coefficient matrix
+ * depends only on the grid spacing (Sec. 6.2.1); not allowed with offsets.
+ * b_shift (optional, either mode): one value per system (index k as above)
+ * added to every diagonal entry of that system, e.g. the -lambda of an
+ * FFT-Poisson wavenumber (Sec. 5.2).  Same dtype as d.
+ */
+typedef struct tdma_coeffs {
+    int mode;
+    const void *a, *b, *c;
+    const void *b_shift;
+} tdma_coeffs;
+
+/*
+ * tdma_solve_batched: solve every system of `layout` in one fused launch.
+ * Each system is split into P partitions held on chip (registers), reduced
+ * by the modified Thomas sweep, the 2P-row interface system is solved in
+ * FP64 by parallel cyclic reduction, and the interior is back-substituted;
+ * only the inputs are read and x written (no intermediate HBM traffic).
+ * dtype: TDMA_F64 (FP64 storage and sweeps) or TDMA_F32 (FP32 storage and
+ * sweeps, FP64 interface solve).  The partition count and tile shape come
+ * from the autotune cache if it holds this shape, else a built-in rule.
+ */
+int tdma_solve_batched(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype,
+                       const void *d, void *x, void *stream);
+
+/*
+ * Explicit tile shape of the fused path (the autotuner's handle, also used by
+ * tests).  rows_per_lane M: 4, 8, 16 (FP64) or 4, 8, 16, 32 (FP32);
+ * systems_per_tile S: a power of two; partitions P: M*P >= n.  S*P lanes form
+ * one workgroup, at most 1024 (512 when M rows of one array fill 128 bytes).
+ * Uniform layouts only.
+ */
+typedef struct tdma_tile {
+    int rows_per_lane;
+    int systems_per_tile;
+    int partitions;
+} tdma_tile;
+
+int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype,
+                             const void *d, void *x, const tdma_tile *tile, void *stream);
+
+/*
+ * Options of the split, pipelined solve.  Zero fields take defaults.
+ *  partitions  P per system (>= 1, n/P >= 2); 0 = 8.
+ *  batch       systems per pipeline batch (the paper's batch_z, Sec. 4.2.1);
+ *              0 = autotuned (cached) or 16384.
+ *  nstreams    HIP streams the pipeline uses (1..8); 0 = 4.
+ *  schedule    0 = stage roles as in Algorithm 2 (Stage A and C on one stream
+ *              role, Stage B on another, ordered by events);
+ *              1 = round-robin (batch b runs A->B->C on stream b mod nstreams).
+ */
+typedef struct tdma_part_opts {
+    int partitions;
+    int64_t batch;
+    int nstreams;
+    int schedule;
+} tdma_part_opts;
+
+/*
+ * tdma_solve_partitioned: the paper's staged method on one GPU.  Each
+ * system is split into P partitions (the paper's slabs).  Stage A streams
+ * every partition once and writes its two interface equations (6 values,
+ * the paper's "6p") to a reduced buffer; Stage B solves the 2P-row reduced
+ * systems (FP64, PCR across lanes); Stage C recomputes each partition's
+ * interior from its two interface values.  Systems are grouped into batches
+ * that are pipelined over HIP streams with events, three batches in flight
+ * (Algorithm 2), so the low-occupancy Stage B overlaps the bandwidth-bound
+ * Stages A and C.  Results do not depend on batch size, stream count or
+ * schedule (bit-identical).  opts may be NULL.  Uniform layouts only.
+ * The caller's stream waits for the whole pipeline before later work.
+ */
+int tdma_solve_partitioned(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype,
+                           const void *d, void *x, const tdma_part_opts *opts, void *stream);
+
+/*
+ * Options and report of the precision form (mixed-precision refinement).
+ *  max_iters  refinement steps after the first FP32 solve, 0..3; the default
+ *             (opts NULL) is 3.
+ *  tol        a system has converged when max|correction| <= tol*max|x|;
+ *             default 1e-15.
+ *  fallback   1 (default): systems that still miss tol are re-solved by the
+ *             FP64 path; 0: they are counted and TDMA_ENOCONV is returned.
+ */
+typedef struct tdma_refine_opts {
+    int max_iters;
+    double tol;
+    int fallback;
+} tdma_refine_opts;
+
+typedef struct tdma_refine_report {
+    int iterations;               /* refinement steps run (max over systems)       */
+    int64_t not_converged;        /* systems whose last correction exceeded tol    */
+    int64_t fallback_systems;     /* systems re-solved by the FP64 path            */
+    double max_rel_correction;    /* max over systems of the last max|dx|/max|x|   */
+} tdma_refine_report;
+
+/*
+ * tdma_solve_refined: FP64 in, FP64 out, FP32 sweeps.  Per tile, on chip:
+ * x0 = solve32(d); then up to max_iters times r = d - A x (FP64),
+ * x += solve32(r).  The interface (Stage B) solve is FP64 in every pass.
+ * Coefficients, d and x are FP64.  With report != NULL the call
+ * synchronises the stream and fills the report; with report == NULL it is
+ * asynchronous and non-converged systems are handled per `fallback`.
+ */
+int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *coeffs, const double *d,
+                       double *x, const tdma_refine_opts *opts, tdma_refine_report *report,
+                       void *stream);
+
+/*
+ * Batching form: a list of solves recorded once into a hipGraph whose body
+ * is ONE persistent kernel.  Work items are cut into tiles; tiles of an item
+ * with `after` >= 0 wait, on the device, until every tile of item `after`
+ * has finished (e.g. the y-sweep of an ADI step reads the x-sweep's output),
+ * while independent items (a ragged batch) fill the gaps.  Items use the
+ * same layout/coefficient rules as tdma_solve_batched; all items share one
+ * dtype.  Pointers are captured at creation and must stay valid.
+ */
+typedef struct tdma_work_item {
+    tdma_layout layout;
+    tdma_coeffs coeffs;
+    const void *d;
+    void *x;
+    int after;                    /* index of an earlier item this one reads, or -1 */
+} tdma_work_item;
+
+typedef struct tdma_graph tdma_graph;
+
+int tdma_graph_create(const tdma_work_item *items, int nitems, int dtype, tdma_graph **out);
+int tdma_graph_launch(tdma_graph *graph, void *stream);
+void tdma_graph_destroy(tdma_graph *graph);
+
+/*
+ * tdma_autotune: time candidate tile shapes (fused path) or batch sizes and
+ * schedules (partitioned path, using the pipeline model of Sec. 4.2.3) for
+ * this shape on the calling device, store the winner in the in-process
+ * cache (and in the JSON file named by TDMA_CACHE, if set).  Synchronous.
+ * The buffers must be valid inputs of that shape; x is overwritten.
+ * what: 0 = fused path, 1 = partitioned path (model), 2 = partitioned path
+ * (model, then measured check of the model's choice against brute force).
+ */
+int tdma_autotune(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype,
+                  const void *d, void *x, int what, void *stream);
+
+/* Synchronise `stream`; return TDMA_ESINGULAR (and clear the flag) if any
+ * kernel on this device met a zero or non-finite pivot, else TDMA_OK. */
+int tdma_check(void *stream);
+
+const char *tdma_status_string(int status);
+const char *tdma_last_error(void);
+
+/* Release every device resource the library holds (plans, workspaces,
+ * streams, events) on all devices.  Optional; safe to call more than once. */
+void tdma_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDMA_H */

@@ -1,0 +1,335 @@
+"""MI355X (gfx950) batched divide-and-conquer tridiagonal solver.
+
+Thin ctypes binding of ``libtdma.so`` (C ABI in ``include/tdma.h``).  Every
+step of the solve runs in the library's HIP kernels; this module only
+marshals arguments: torch tensors supply device pointers and the current
+HIP stream.  Before a call reaches the device it checks that every tensor is
+a GPU tensor and that the layout stays inside each tensor's storage, so a
+wrong layout is a Python exception, not an out-of-bounds access.
+
+The library must be built (``python -m paper_2509_03933_amd.build``); there is
+no fallback path.
+"""
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdma.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESINGULAR, ENOCONV, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+COEF_LIKE_D, COEF_SHARED = 0, 1
+SCHED_ROLES, SCHED_ROUND_ROBIN = 0, 1
+
+_c_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+class _Layout(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nsys0", ctypes.c_int64), ("nsys1", ctypes.c_int64),
+                ("row_stride", ctypes.c_int64), ("sys_stride0", ctypes.c_int64),
+                ("sys_stride1", ctypes.c_int64), ("offsets", _c_i64p)]
+
+
+class _Coeffs(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("a", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("c", ctypes.c_void_p), ("b_shift", ctypes.c_void_p)]
+
+
+class _Tile(ctypes.Structure):
+    _fields_ = [("rows_per_lane", ctypes.c_int), ("systems_per_tile", ctypes.c_int),
+                ("partitions", ctypes.c_int)]
+
+
+class _PartOpts(ctypes.Structure):
+    _fields_ = [("partitions", ctypes.c_int), ("batch", ctypes.c_int64),
+                ("nstreams", ctypes.c_int), ("schedule", ctypes.c_int)]
+
+
+class _RefineOpts(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int), ("tol", ctypes.c_double), ("fallback", ctypes.c_int)]
+
+
+class RefineReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("not_converged", ctypes.c_int64),
+                ("fallback_systems", ctypes.c_int64), ("max_rel_correction", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class _WorkItem(ctypes.Structure):
+    _fields_ = [("layout", _Layout), ("coeffs", _Coeffs), ("d", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("after", ctypes.c_int)]
+
+
+class TdmaError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(message)
+        self.status = status
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def lib():
+    """The loaded libtdma.so; raises if it has not been built."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is not built; run "
+                                   "`python -m paper_2509_03933_amd.build` (no fallback exists)")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i = ctypes.c_void_p, ctypes.c_int
+            L.tdma_solve_batched.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, vp, vp, vp]
+            L.tdma_solve_batched_tiled.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, vp,
+                                                   vp, ctypes.POINTER(_Tile), vp]
+            L.tdma_solve_partitioned.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, vp,
+                                                 vp, ctypes.POINTER(_PartOpts), vp]
+            L.tdma_solve_refined.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), vp, vp,
+                                             ctypes.POINTER(_RefineOpts), ctypes.POINTER(RefineReport), vp]
+            L.tdma_graph_create.argtypes = [ctypes.POINTER(_WorkItem), i, i, ctypes.POINTER(vp)]
+            L.tdma_graph_launch.argtypes = [vp, vp]
+            L.tdma_graph_destroy.argtypes = [vp]
+            L.tdma_graph_destroy.restype = None
+            L.tdma_autotune.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, vp, vp, i, vp]
+            L.tdma_check.argtypes = [vp]
+            L.tdma_status_string.argtypes = [i]
+            L.tdma_status_string.restype = ctypes.c_char_p
+            L.tdma_last_error.restype = ctypes.c_char_p
+            L.tdma_shutdown.restype = None
+            for f in ("tdma_solve_batched", "tdma_solve_batched_tiled", "tdma_solve_partitioned", "tdma_solve_refined",
+                      "tdma_graph_create", "tdma_graph_launch", "tdma_autotune", "tdma_check"):
+                getattr(L, f).restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+EXPORTED_SYMBOLS = ("tdma_solve_batched", "tdma_solve_batched_tiled", "tdma_solve_partitioned", "tdma_solve_refined",
+                    "tdma_graph_create", "tdma_graph_launch", "tdma_graph_destroy",
+                    "tdma_autotune", "tdma_check", "tdma_status_string", "tdma_last_error",
+                    "tdma_shutdown")
+
+
+def _raise(status):
+    if status != OK:
+        msg = lib().tdma_last_error().decode() or lib().tdma_status_string(status).decode()
+        raise TdmaError(status, msg)
+
+
+def status_string(status):
+    return lib().tdma_status_string(status).decode()
+
+
+# ---------------------------------------------------------------------------
+# argument marshalling and bounds checks
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _extent(layout):
+    """Elements spanned by an array in this layout (max index + 1)."""
+    if getattr(layout, "offsets", None) is not None:
+        off = np.asarray(layout.offsets)
+        return int(off.max()) if off.size else 0
+    nsys = layout.nsys0 * layout.nsys1
+    if nsys == 0:
+        return 0
+    return 1 + (layout.n - 1) * layout.row_stride + (layout.nsys0 - 1) * layout.sys_stride0 \
+        + (layout.nsys1 - 1) * layout.sys_stride1
+
+
+def _room(t):
+    """Elements addressable from t.data_ptr() inside t's storage."""
+    st = t.untyped_storage()
+    return (st.nbytes() - t.storage_offset() * t.element_size()) // t.element_size()
+
+
+def _check_tensor(name, t, need, dtype=None):
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if need > _room(t):
+        raise ValueError(f"{name}: layout reaches element {need - 1} but the tensor holds {_room(t)}")
+
+
+def _make_layout(layout, keep):
+    L = _Layout()
+    offs = getattr(layout, "offsets", None)
+    L.n = int(layout.n)
+    L.nsys0 = int(layout.nsys0)
+    L.nsys1 = int(getattr(layout, "nsys1", 1))
+    L.row_stride = int(getattr(layout, "row_stride", 1))
+    L.sys_stride0 = int(getattr(layout, "sys_stride0", 0))
+    L.sys_stride1 = int(getattr(layout, "sys_stride1", 0))
+    if offs is not None:
+        arr = np.ascontiguousarray(offs, dtype=np.int64)
+        if arr.size != L.nsys0 + 1:
+            raise ValueError("offsets must have nsys0 + 1 entries")
+        keep.append(arr)
+        L.offsets = arr.ctypes.data_as(_c_i64p)
+    else:
+        L.offsets = None
+    return L
+
+
+def _make_coeffs(layout, coeffs, d, need):
+    """coeffs: dict(mode=, a=, b=, c=, shift=) of torch tensors."""
+    mode = int(coeffs.get("mode", COEF_LIKE_D))
+    a, b, c = coeffs.get("a"), coeffs.get("b"), coeffs.get("c")
+    shift = coeffs.get("shift")
+    if mode == COEF_LIKE_D:
+        for nm, t in (("a", a), ("b", b), ("c", c)):
+            _check_tensor(nm, t, need, d.dtype)
+    elif mode == COEF_SHARED:
+        for nm, t in (("a", a), ("b", b), ("c", c)):
+            _check_tensor(nm, t, int(layout.n), d.dtype)
+    else:
+        raise ValueError(f"unknown coefficient mode {mode}")
+    nsys = int(layout.nsys0) * int(getattr(layout, "nsys1", 1))
+    if shift is not None:
+        _check_tensor("shift", shift, nsys, d.dtype)
+    C = _Coeffs()
+    C.mode = mode
+    C.a, C.b, C.c = a.data_ptr(), b.data_ptr(), c.data_ptr()
+    C.b_shift = shift.data_ptr() if shift is not None else None
+    return C
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _prepare(layout, coeffs, d, x):
+    keep = []
+    need = _extent(layout)
+    _check_tensor("d", d, need)
+    _check_tensor("x", x, need, d.dtype)
+    L = _make_layout(layout, keep)
+    C = _make_coeffs(layout, coeffs, d, need)
+    return L, C, keep
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI, without the tdma_ prefix)
+
+def solve_batched(layout, coeffs, d, x, stream=None):
+    """Fused on-chip solve of every system (tdma_solve_batched)."""
+    L, C, keep = _prepare(layout, coeffs, d, x)
+    _raise(lib().tdma_solve_batched(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),
+                                    ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                    _stream_handle(stream)))
+
+
+def solve_batched_tiled(layout, coeffs, d, x, M, S, P, stream=None):
+    """Fused solve with an explicit tile shape (tdma_solve_batched_tiled)."""
+    L, C, keep = _prepare(layout, coeffs, d, x)
+    t = _Tile(int(M), int(S), int(P))
+    _raise(lib().tdma_solve_batched_tiled(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),
+                                          ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.byref(t), _stream_handle(stream)))
+
+
+def solve_partitioned(layout, coeffs, d, x, partitions=0, batch=0, nstreams=0, schedule=0,
+                      stream=None):
+    """Staged A/B/C solve pipelined over HIP streams (tdma_solve_partitioned)."""
+    L, C, keep = _prepare(layout, coeffs, d, x)
+    o = _PartOpts(int(partitions), int(batch), int(nstreams), int(schedule))
+    _raise(lib().tdma_solve_partitioned(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),
+                                        ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.byref(o), _stream_handle(stream)))
+
+
+def solve_refined(layout, coeffs, d, x, max_iters=3, tol=1e-15, fallback=1, report=True,
+                  stream=None):
+    """FP32 sweeps with FP64 refinement (tdma_solve_refined).  Returns the
+    report as a dict when report=True (the call then synchronises)."""
+    import torch
+    if d.dtype != torch.float64:
+        raise TypeError("tdma_solve_refined takes FP64 d and x")
+    L, C, keep = _prepare(layout, coeffs, d, x)
+    o = _RefineOpts(int(max_iters), float(tol), int(fallback))
+    rep = RefineReport()
+    _raise(lib().tdma_solve_refined(ctypes.byref(L), ctypes.byref(C), ctypes.c_void_p(d.data_ptr()),
+                                    ctypes.c_void_p(x.data_ptr()), ctypes.byref(o),
+                                    ctypes.byref(rep) if report else None, _stream_handle(stream)))
+    return rep.as_dict() if report else None
+
+
+class Graph:
+    """A recorded batching-form launch (tdma_graph_*)."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _raise(lib().tdma_graph_launch(self._h, _stream_handle(stream)))
+
+    def destroy(self):
+        if self._h:
+            lib().tdma_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def graph_create(items):
+    """items: list of dict(layout=, coeffs=, d=, x=, after=-1)."""
+    keep = []
+    arr = (_WorkItem * len(items))()
+    dtype = None
+    for k, it in enumerate(items):
+        d, x = it["d"], it["x"]
+        L, C, kk = _prepare(it["layout"], it["coeffs"], d, x)
+        keep.extend(kk)
+        keep.extend([d, x])
+        dc = _dtype_code(d)
+        if dtype is not None and dc != dtype:
+            raise TypeError("all graph items must share one dtype")
+        dtype = dc
+        arr[k].layout = L
+        arr[k].coeffs = C
+        arr[k].d = d.data_ptr()
+        arr[k].x = x.data_ptr()
+        arr[k].after = int(it.get("after", -1))
+    h = ctypes.c_void_p()
+    _raise(lib().tdma_graph_create(arr, len(items), dtype if dtype is not None else F64,
+                                   ctypes.byref(h)))
+    return Graph(h, keep)
+
+
+def autotune(layout, coeffs, d, x, what=0, stream=None):
+    L, C, keep = _prepare(layout, coeffs, d, x)
+    _raise(lib().tdma_autotune(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),
+                               ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(x.data_ptr()), int(what),
+                               _stream_handle(stream)))
+
+
+def check(stream=None):
+    """Synchronise and raise TdmaError(ESINGULAR) if a kernel met a bad pivot."""
+    _raise(lib().tdma_check(_stream_handle(stream)))
+
+
+def shutdown():
+    lib().tdma_shutdown()

@@ -1,0 +1,424 @@
+// Host side of the C ABI: argument validation, per-device state, planning of
+// tile shapes, dispatch, and the sticky device error flag.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "api_internal.h"
+
+namespace tdma {
+
+// ---------------------------------------------------------------------------
+// error state
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = std::string(tdma_status_string(status)) + ": " + buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(TDMA_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_last_error.clear(); }
+
+// ---------------------------------------------------------------------------
+// per-device state
+
+static std::mutex g_mutex;
+static std::map<int, std::unique_ptr<DeviceCtx>> g_ctx;
+
+DeviceCtx::~DeviceCtx() { release(); }
+
+void DeviceCtx::release() {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(dev);
+    for (auto &kv : ragged_cache) {
+        if (kv.second.d_offsets) (void)hipFree(kv.second.d_offsets);
+        if (kv.second.d_list) (void)hipFree(kv.second.d_list);
+    }
+    ragged_cache.clear();
+    for (auto &w : workspaces) (void)hipFree(w.ptr);
+    workspaces.clear();
+    for (auto e : events) (void)hipEventDestroy(e);
+    events.clear();
+    for (auto s : streams) (void)hipStreamDestroy(s);
+    streams.clear();
+    if (d_err) (void)hipFree(d_err);
+    d_err = nullptr;
+    if (cur >= 0) (void)hipSetDevice(cur);
+}
+
+int get_ctx(DeviceCtx **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_mutex);
+    auto it = g_ctx.find(dev);
+    if (it == g_ctx.end()) {
+        auto c = std::make_unique<DeviceCtx>();
+        c->dev = dev;
+        e = hipMalloc(&c->d_err, 4 * sizeof(int));
+        if (e != hipSuccess) return fail(TDMA_ENOMEM, "device error flag: %s", hipGetErrorString(e));
+        e = hipMemset(c->d_err, 0, 4 * sizeof(int));
+        if (e != hipSuccess) return hip_fail(e, "hipMemset");
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) c->num_cus = prop.multiProcessorCount;
+        it = g_ctx.emplace(dev, std::move(c)).first;
+    }
+    *out = it->second.get();
+    return TDMA_OK;
+}
+
+std::mutex &ctx_mutex(DeviceCtx *) { return g_mutex; }
+
+// Device workspace of at least `bytes`, tagged by `slot` (kept across calls).
+int DeviceCtx::workspace(int slot, size_t bytes, void **out) {
+    for (auto &w : workspaces) {
+        if (w.slot == slot) {
+            if (w.bytes >= bytes) { *out = w.ptr; return TDMA_OK; }
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+            (void)hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.bytes = 0;
+            e = hipMalloc(&w.ptr, bytes);
+            if (e != hipSuccess) return fail(TDMA_ENOMEM, "workspace of %zu bytes", bytes);
+            w.bytes = bytes;
+            *out = w.ptr;
+            return TDMA_OK;
+        }
+    }
+    Workspace w;
+    w.slot = slot;
+    hipError_t e = hipMalloc(&w.ptr, bytes);
+    if (e != hipSuccess) return fail(TDMA_ENOMEM, "workspace of %zu bytes", bytes);
+    w.bytes = bytes;
+    workspaces.push_back(w);
+    *out = w.ptr;
+    return TDMA_OK;
+}
+
+int DeviceCtx::get_streams(int count, hipStream_t **out) {
+    while ((int)streams.size() < count) {
+        hipStream_t s;
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        streams.push_back(s);
+    }
+    *out = streams.data();
+    return TDMA_OK;
+}
+
+int DeviceCtx::get_events(int count, hipEvent_t **out) {
+    while ((int)events.size() < count) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        events.push_back(ev);
+    }
+    *out = events.data();
+    return TDMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+
+int validate(const tdma_layout *L, const tdma_coeffs *C, int dtype, const void *d, const void *x) {
+    if (!L) return fail(TDMA_EINVAL, "layout is NULL");
+    if (!C) return fail(TDMA_EINVAL, "coeffs is NULL");
+    if (dtype != TDMA_F64 && dtype != TDMA_F32) return fail(TDMA_EINVAL, "unknown dtype %d", dtype);
+    if (!d || !x) return fail(TDMA_EINVAL, "d and x must be non-NULL");
+    if (!C->a || !C->b || !C->c) return fail(TDMA_EINVAL, "a, b and c must be non-NULL");
+    if (C->mode != TDMA_COEF_LIKE_D && C->mode != TDMA_COEF_SHARED)
+        return fail(TDMA_EINVAL, "unknown coefficient mode %d", C->mode);
+    if (x == C->a || x == C->b || x == C->c || (C->b_shift && x == C->b_shift))
+        return fail(TDMA_EINVAL, "x must not alias the coefficients");
+    if (L->nsys0 < 0 || L->nsys1 < 0) return fail(TDMA_EINVAL, "negative system count");
+    if (L->nsys1 > 0 && L->nsys0 > INT64_MAX / L->nsys1) return fail(TDMA_EINVAL, "nsys overflows");
+    if (L->offsets) {
+        if (L->nsys1 != 1) return fail(TDMA_EINVAL, "ragged layout needs nsys1 == 1");
+        if (C->mode != TDMA_COEF_LIKE_D)
+            return fail(TDMA_EINVAL, "ragged layout needs per-row (LIKE_D) coefficients");
+        for (int64_t k = 0; k < L->nsys0; ++k) {
+            const int64_t len = L->offsets[k + 1] - L->offsets[k];
+            if (len < 2) return fail(TDMA_EINVAL, "ragged system %lld has %lld rows (< 2)",
+                                     (long long)k, (long long)len);
+            if (len > kMaxRaggedRows)
+                return fail(TDMA_EUNSUPPORTED, "ragged system %lld has %lld rows (> %lld)",
+                            (long long)k, (long long)len, (long long)kMaxRaggedRows);
+        }
+        if (L->offsets[0] < 0) return fail(TDMA_EINVAL, "negative offset");
+        return TDMA_OK;
+    }
+    if (L->nsys0 * L->nsys1 == 0) return TDMA_OK;
+    if (L->n < 2) return fail(TDMA_EINVAL, "n = %lld (< 2)", (long long)L->n);
+    if (L->row_stride == 0 && L->n > 1) return fail(TDMA_EINVAL, "row_stride is 0");
+    if (L->row_stride < 0 || L->sys_stride0 < 0 || L->sys_stride1 < 0)
+        return fail(TDMA_EINVAL, "negative stride");
+    return TDMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// planning of the fused path
+
+static int ilog2_floor(int64_t v) {
+    int r = 0;
+    while ((int64_t)1 << (r + 1) <= v) ++r;
+    return r;
+}
+
+// Built-in tile rule for uniform layouts (the autotune cache overrides it).
+// Strided systems: S consecutive systems per tile so that each row load is a
+// full 128-byte line (S = 16 in FP64, 32 in FP32); P partitions of M rows so
+// that P*M covers n.  Contiguous rows: the tile is staged through LDS.
+bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *out) {
+    const int esz = dtype == TDMA_F64 ? 8 : 4;
+    const int Ms_f64[] = {16, 8, 4};
+    const int Ms_f32[] = {16, 32, 8, 4};
+    const int *Ms = dtype == TDMA_F64 ? Ms_f64 : Ms_f32;
+    const int nM = dtype == TDMA_F64 ? 3 : 4;
+    for (int mi = 0; mi < nM; ++mi) {
+        const int M = Ms[mi];
+        const int64_t P = (n + M - 1) / M;
+        if (P > 1024) continue;
+        TileShape sh;
+        sh.M = M;
+        sh.P = (int)P;
+        sh.contig = contig;
+        int S_log2 = contig ? ilog2_floor(std::max<int64_t>(1, 256 / P)) : ilog2_floor(128 / esz);
+        const int maxt = fused_max_threads(dtype, M);
+        while (S_log2 > 0 && ((int64_t)1 << S_log2) * P > maxt) --S_log2;
+        // a tile larger than the number of systems only wastes lanes
+        while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= nsys) --S_log2;
+        sh.S_log2 = S_log2;
+        if (((int64_t)1 << S_log2) * P > maxt) continue;
+        if (contig && fused_lds_bytes(dtype, sh) > 96 * 1024) continue;
+        *out = sh;
+        return true;
+    }
+    return false;
+}
+
+// Ragged layout: systems are bucketed by the power-of-two partition count
+// they need; one launch per non-empty bucket (contiguous rows, LDS-staged).
+int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, hipStream_t st,
+                const RaggedPlan **out) {
+    const int64_t nsys = L->nsys0;
+    uint64_t h = 1469598103934665603ull;
+    for (int64_t k = 0; k <= nsys; ++k) {
+        h ^= (uint64_t)L->offsets[k];
+        h *= 1099511628211ull;
+    }
+    h ^= (uint64_t)dtype * 0x9E3779B97F4A7C15ull;
+    auto it = ctx->ragged_cache.find(h);
+    if (it != ctx->ragged_cache.end() && it->second.nsys == nsys) {
+        *out = &it->second;
+        return TDMA_OK;
+    }
+    const int M = dtype == TDMA_F64 ? 16 : 32;
+    std::map<int, std::vector<int32_t>> buckets;
+    for (int64_t k = 0; k < nsys; ++k) {
+        const int64_t len = L->offsets[k + 1] - L->offsets[k];
+        int64_t P = (len + M - 1) / M;
+        int64_t Pp = 1;
+        while (Pp < P) Pp <<= 1;
+        buckets[(int)Pp].push_back((int32_t)k);
+    }
+    RaggedPlan rp;
+    rp.nsys = nsys;
+    std::vector<int32_t> all;
+    for (auto &kv : buckets) {
+        RaggedBucket b;
+        b.shape.M = M;
+        b.shape.P = kv.first;
+        b.shape.contig = true;
+        int S_log2 = ilog2_floor(std::max(1, 256 / kv.first));
+        while (S_log2 > 0 && (kv.first << S_log2) > fused_max_threads(dtype, M)) --S_log2;
+        b.shape.S_log2 = S_log2;
+        b.first = (int64_t)all.size();
+        b.count = (int64_t)kv.second.size();
+        all.insert(all.end(), kv.second.begin(), kv.second.end());
+        rp.buckets.push_back(b);
+    }
+    hipError_t e = hipMalloc(&rp.d_offsets, (nsys + 1) * sizeof(int64_t));
+    if (e != hipSuccess) return fail(TDMA_ENOMEM, "ragged offsets");
+    e = hipMalloc(&rp.d_list, std::max<size_t>(1, all.size()) * sizeof(int32_t));
+    if (e != hipSuccess) { (void)hipFree(rp.d_offsets); return fail(TDMA_ENOMEM, "ragged list"); }
+    e = hipMemcpyAsync(rp.d_offsets, L->offsets, (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(rp.d_list, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(rp.d_offsets);
+        (void)hipFree(rp.d_list);
+        return hip_fail(e, "upload ragged plan");
+    }
+    if (ctx->ragged_cache.size() >= 8) {
+        for (auto &kv : ctx->ragged_cache) { (void)hipFree(kv.second.d_offsets); (void)hipFree(kv.second.d_list); }
+        ctx->ragged_cache.clear();
+    }
+    auto res = ctx->ragged_cache.emplace(h, rp);
+    *out = &res.first->second;
+    return TDMA_OK;
+}
+
+SysMap make_map(const tdma_layout *L) {
+    SysMap m;
+    m.n = L->n;
+    m.nsys = L->nsys0 * L->nsys1;
+    m.nsys0 = std::max<int64_t>(1, L->nsys0);
+    m.row_stride = L->row_stride;
+    m.sys_stride0 = L->sys_stride0;
+    m.sys_stride1 = L->sys_stride1;
+    m.offsets = nullptr;
+    m.sys_list = nullptr;
+    return m;
+}
+
+Coef make_coef(const tdma_coeffs *C) {
+    Coef c;
+    c.mode = C->mode;
+    c.a = C->a;
+    c.b = C->b;
+    c.c = C->c;
+    c.shift = C->b_shift;
+    return c;
+}
+
+int run_fused(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dtype, const void *d,
+              void *x, hipStream_t st, const TileShape *force) {
+    const Coef coef = make_coef(C);
+    if (L->offsets) {
+        const RaggedPlan *rp = nullptr;
+        int rc = plan_ragged(ctx, L, dtype, st, &rp);
+        if (rc != TDMA_OK) return rc;
+        for (const auto &b : rp->buckets) {
+            SysMap m = make_map(L);
+            m.n = (int64_t)b.shape.P * b.shape.M;
+            m.nsys = b.count;
+            m.offsets = rp->d_offsets;
+            m.sys_list = rp->d_list + b.first;
+            hipError_t e = launch_fused(dtype, m, coef, b.shape, d, x, ctx->d_err, st);
+            if (e != hipSuccess) return hip_fail(e, "fused launch (ragged)");
+        }
+        return TDMA_OK;
+    }
+    const SysMap m = make_map(L);
+    if (m.nsys == 0) return TDMA_OK;
+    TileShape sh;
+    if (force) {
+        sh = *force;
+    } else if (!lookup_tuned(ctx->dev, L, C, dtype, &sh)) {
+        if (!default_shape(dtype, L->n, m.nsys, L->row_stride == 1, &sh))
+            return fail(TDMA_EUNSUPPORTED, "n = %lld is too long for the fused path (use "
+                        "tdma_solve_partitioned)", (long long)L->n);
+    }
+    if (!fused_supported(dtype, sh) || (int64_t)sh.P * sh.M < L->n)
+        return fail(TDMA_EINVAL, "tile shape M=%d P=%d S=%d does not cover n=%lld", sh.M, sh.P,
+                    1 << sh.S_log2, (long long)L->n);
+    hipError_t e = launch_fused(dtype, m, coef, sh, d, x, ctx->d_err, st);
+    if (e != hipSuccess) return hip_fail(e, "fused launch");
+    return TDMA_OK;
+}
+
+}  // namespace tdma
+
+using namespace tdma;
+
+extern "C" {
+
+const char *tdma_status_string(int status) {
+    switch (status) {
+        case TDMA_OK: return "TDMA_OK";
+        case TDMA_EINVAL: return "TDMA_EINVAL (invalid argument)";
+        case TDMA_ENOMEM: return "TDMA_ENOMEM (allocation failed)";
+        case TDMA_EHIP: return "TDMA_EHIP (HIP runtime error)";
+        case TDMA_ESINGULAR: return "TDMA_ESINGULAR (zero or non-finite pivot)";
+        case TDMA_ENOCONV: return "TDMA_ENOCONV (refinement did not converge)";
+        case TDMA_EUNSUPPORTED: return "TDMA_EUNSUPPORTED (unsupported combination)";
+        default: return "unknown tdma status";
+    }
+}
+
+const char *tdma_last_error(void) { return g_last_error.c_str(); }
+
+int tdma_solve_batched(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype,
+                       const void *d, void *x, void *stream) {
+    clear_error();
+    int rc = validate(layout, coeffs, dtype, d, x);
+    if (rc != TDMA_OK) return rc;
+    DeviceCtx *ctx = nullptr;
+    rc = get_ctx(&ctx);
+    if (rc != TDMA_OK) return rc;
+    return run_fused(ctx, layout, coeffs, dtype, d, x, (hipStream_t)stream, nullptr);
+}
+
+int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype,
+                             const void *d, void *x, const tdma_tile *tile, void *stream) {
+    clear_error();
+    int rc = validate(layout, coeffs, dtype, d, x);
+    if (rc != TDMA_OK) return rc;
+    if (!tile) return fail(TDMA_EINVAL, "tile is NULL");
+    if (layout->offsets) return fail(TDMA_EINVAL, "explicit tiles need a uniform layout");
+    const int S = tile->systems_per_tile;
+    if (S < 1 || (S & (S - 1)) != 0) return fail(TDMA_EINVAL, "systems_per_tile must be a power of two");
+    TileShape sh;
+    sh.M = tile->rows_per_lane;
+    sh.P = tile->partitions;
+    sh.S_log2 = 0;
+    while ((1 << sh.S_log2) < S) ++sh.S_log2;
+    sh.contig = layout->row_stride == 1;
+    if (!fused_supported(dtype, sh)) return fail(TDMA_EINVAL, "unsupported tile M=%d S=%d P=%d",
+                                                 sh.M, S, sh.P);
+    if ((int64_t)sh.M * sh.P < layout->n) return fail(TDMA_EINVAL, "tile covers %lld rows < n = %lld",
+                                                      (long long)sh.M * sh.P, (long long)layout->n);
+    if (sh.contig && fused_lds_bytes(dtype, sh) > 160 * 1024)
+        return fail(TDMA_EINVAL, "tile needs %zu bytes of LDS", fused_lds_bytes(dtype, sh));
+    DeviceCtx *ctx = nullptr;
+    rc = get_ctx(&ctx);
+    if (rc != TDMA_OK) return rc;
+    return run_fused(ctx, layout, coeffs, dtype, d, x, (hipStream_t)stream, &sh);
+}
+
+int tdma_check(void *stream) {
+    clear_error();
+    DeviceCtx *ctx = nullptr;
+    int rc = get_ctx(&ctx);
+    if (rc != TDMA_OK) return rc;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    int flag[4] = {0, 0, 0, 0};
+    e = hipMemcpy(flag, ctx->d_err, sizeof flag, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read error flag");
+    if (flag[0]) {
+        e = hipMemset(ctx->d_err, 0, 4 * sizeof(int));
+        if (e != hipSuccess) return hip_fail(e, "clear error flag");
+        return fail(TDMA_ESINGULAR, "a kernel met a zero or non-finite pivot");
+    }
+    return TDMA_OK;
+}
+
+void tdma_shutdown(void) {
+    std::lock_guard<std::mutex> g(g_mutex);
+    g_ctx.clear();
+    clear_tuned();
+}
+
+}  // extern "C"

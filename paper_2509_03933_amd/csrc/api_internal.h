@@ -1,0 +1,66 @@
+// Host-side internals shared by the API translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "tdma_internal.h"
+
+namespace tdma {
+
+constexpr int64_t kMaxRaggedRows = 65536;
+
+struct RaggedBucket {
+    TileShape shape;
+    int64_t first = 0;   // index into the device system list
+    int64_t count = 0;
+};
+
+struct RaggedPlan {
+    int64_t nsys = 0;
+    int64_t *d_offsets = nullptr;
+    int32_t *d_list = nullptr;
+    std::vector<RaggedBucket> buckets;
+};
+
+struct Workspace {
+    int slot = 0;
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct DeviceCtx {
+    int dev = 0;
+    int num_cus = 256;
+    int *d_err = nullptr;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    std::vector<Workspace> workspaces;
+    std::map<uint64_t, RaggedPlan> ragged_cache;
+    ~DeviceCtx();
+    void release();
+    int workspace(int slot, size_t bytes, void **out);
+    int get_streams(int count, hipStream_t **out);
+    int get_events(int count, hipEvent_t **out);
+};
+
+int fail(int status, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+int get_ctx(DeviceCtx **out);
+int validate(const tdma_layout *L, const tdma_coeffs *C, int dtype, const void *d, const void *x);
+SysMap make_map(const tdma_layout *L);
+Coef make_coef(const tdma_coeffs *C);
+bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *out);
+int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, hipStream_t st,
+                const RaggedPlan **out);
+int run_fused(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dtype, const void *d,
+              void *x, hipStream_t st, const TileShape *force);
+
+// autotune cache (autotune.cpp)
+bool lookup_tuned(int dev, const tdma_layout *L, const tdma_coeffs *C, int dtype, TileShape *out);
+void clear_tuned();
+
+}  // namespace tdma

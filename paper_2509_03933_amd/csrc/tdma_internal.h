@@ -1,0 +1,49 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/tdma.h"
+
+namespace tdma {
+
+// Where one launch's systems live.  System number k (0 <= k < nsys) maps to
+// a system id (sys_list ? sys_list[k] : k).  Uniform layout: id = s0 + nsys0*s1
+// starts at s0*sys_stride0 + s1*sys_stride1, rows row_stride apart.  Ragged:
+// id starts at offsets[id] with offsets[id+1]-offsets[id] rows, row stride 1.
+struct SysMap {
+    int64_t n;              // rows per system (uniform); upper bound when ragged
+    int64_t nsys;           // systems covered by this launch
+    int64_t nsys0;
+    int64_t row_stride, sys_stride0, sys_stride1;
+    const int64_t *offsets; // device, ragged form only
+    const int32_t *sys_list;// device, optional
+};
+
+struct Coef {
+    int mode;               // TDMA_COEF_LIKE_D or TDMA_COEF_SHARED
+    const void *a, *b, *c;
+    const void *shift;      // per-system diagonal shift or null
+};
+
+// Tile shape of the fused kernel: S systems x P partitions x M rows per lane.
+struct TileShape {
+    int M = 8;
+    int S_log2 = 4;
+    int P = 4;
+    bool contig = false;    // stage loads/stores through LDS (row_stride == 1)
+    int threads() const { return (1 << S_log2) * P; }
+};
+
+enum class Layout { Strided = 0, Contig = 1 };
+
+// launchers (fused.hip)
+hipError_t launch_fused(int dtype, const SysMap &map, const Coef &coef, const TileShape &shape,
+                        const void *d, void *x, int *err_flag, hipStream_t stream);
+bool fused_supported(int dtype, const TileShape &shape);
+int fused_max_threads(int dtype, int M);
+size_t fused_lds_bytes(int dtype, const TileShape &shape);
+
+}  // namespace tdma

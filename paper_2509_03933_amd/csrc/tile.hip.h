@@ -1,0 +1,183 @@
+// Device building blocks of the on-chip partitioned solve (gfx950).
+//
+// A tile is S systems x P partitions; lane (p, s) = threadIdx.x = p*S + s holds
+// rows p*M .. p*M+M-1 of system s in registers.  Consecutive lanes hold the
+// same row of consecutive systems, so for y/z lines (systems adjacent in
+// memory) every row load is one contiguous S-element segment.
+//
+// Math (the paper's Stage A / B / C of Sec. 2.1, reduced form with 2P
+// interface rows):
+//  Stage A, per partition with local rows j = 0..m-1 and neighbours x_{-1}
+//  (end of the previous partition) and x_m (start of the next):
+//    row 0 is normalised and set aside:  x_0 + a^_0 x_{-1} + c^_0 x_1 = d^_0;
+//    rows j >= 1 are eliminated keeping x_0 as a parameter:
+//      x_j + a^_j x_0 + c^_j x_{j+1} = d^_j,
+//      j = 1: (a^, c^, d^) = (a, c, d)/b;   j >= 2: r = 1/(b_j - a_j c^_{j-1}),
+//      a^_j = -r a_j a^_{j-1},  c^_j = r c_j,  d^_j = r (d_j - a_j d^_{j-1}).
+//    Row m-1 is the partition's "last" interface equation.  Expressing x_1
+//    through x_0 and x_{m-1} (back recurrence, accumulated forward with
+//    running products pi_j = prod_{i<j} (-c^_i)) and substituting into row 0
+//    gives the "first" interface equation.  Both have unit diagonal.
+//  Stage B: the 2P interface rows of a system form a tridiagonal system
+//    (first/last rows of partition p are rows 2p and 2p+1), solved in FP64
+//    by parallel cyclic reduction: log2(2P) steps, each eliminating the
+//    couplings at distance h and renormalising the diagonal to one.
+//  Stage C: x_{m-1}, x_0 are interface unknowns; the interior follows from
+//    x_j = d^_j - a^_j x_0 - c^_j x_{j+1}, j = m-2 .. 1.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tdma_internal.h"
+
+namespace tdma {
+namespace dev {
+
+template <typename T>
+__device__ __forceinline__ bool bad_pivot(T v) {
+    // zero, NaN or infinite pivot (NaN fails both comparisons)
+    const T av = v < T(0) ? -v : v;
+    return !(av > T(0) && av < T(__builtin_huge_val()));
+}
+
+struct LaneSys {
+    int64_t base;
+    int64_t nrows;
+    int64_t id;
+    bool valid;
+};
+
+__device__ __forceinline__ LaneSys lane_system(const SysMap &m, int64_t k) {
+    LaneSys r;
+    r.valid = k < m.nsys;
+    const int64_t kk = r.valid ? k : 0;
+    const int64_t id = m.sys_list ? (int64_t)m.sys_list[kk] : kk;
+    r.id = id;
+    if (m.offsets) {
+        r.base = m.offsets[id];
+        r.nrows = m.offsets[id + 1] - r.base;
+    } else {
+        const int64_t s1 = id / m.nsys0;
+        const int64_t s0 = id - s1 * m.nsys0;
+        r.base = s0 * m.sys_stride0 + s1 * m.sys_stride1;
+        r.nrows = m.n;
+    }
+    if (!r.valid) r.nrows = 0;
+    return r;
+}
+
+// Interface rows of one partition (unit diagonal): first row couples
+// (X_{2p-1}, X_{2p}, X_{2p+1}), last row couples (X_{2p}, X_{2p+1}, X_{2p+2}).
+struct Iface {
+    double fa, fc, fd;
+    double la, lc, ld;
+};
+
+// Stage A on M register rows.  On return av/cv/dv hold a^, c^, d^ for rows
+// 1..M-1 (row 0 values are folded into the first interface row).
+template <typename T, int M>
+__device__ __forceinline__ Iface reduce_partition(T (&av)[M], const T (&bv)[M], T (&cv)[M],
+                                                  T (&dv)[M], bool &bad) {
+    static_assert(M >= 2, "a partition needs at least two rows");
+    T piv = bv[0];
+    bad |= bad_pivot(piv);
+    T ib = T(1) / piv;
+    const T a0 = av[0] * ib, c0 = cv[0] * ib, d0 = dv[0] * ib;
+    piv = bv[1];
+    bad |= bad_pivot(piv);
+    ib = T(1) / piv;
+    av[1] *= ib;
+    cv[1] *= ib;
+    dv[1] *= ib;
+#pragma unroll
+    for (int j = 2; j < M; ++j) {
+        piv = bv[j] - av[j] * cv[j - 1];
+        bad |= bad_pivot(piv);
+        ib = T(1) / piv;
+        const T ra = av[j] * ib;
+        dv[j] = (dv[j] - av[j] * dv[j - 1]) * ib;
+        cv[j] = cv[j] * ib;
+        av[j] = -ra * av[j - 1];
+    }
+    // x_1 = dt1 - at1 x_0 - ct1 x_{M-1}:  dt1 = sum_j pi_j d^_j, at1 = sum_j pi_j a^_j,
+    // ct1 = -pi_{M-1}, with pi_1 = 1, pi_{j+1} = -c^_j pi_j, j = 1..M-2.
+    T pi = T(1), dt1 = T(0), at1 = T(0);
+#pragma unroll
+    for (int j = 1; j <= M - 2; ++j) {
+        dt1 += pi * dv[j];
+        at1 += pi * av[j];
+        pi = -cv[j] * pi;
+    }
+    const T ct1 = -pi;
+    Iface f;
+    const double den = 1.0 - (double)c0 * (double)at1;
+    bad |= bad_pivot(den);
+    const double rho = 1.0 / den;
+    f.fa = rho * (double)a0;
+    f.fc = -rho * (double)c0 * (double)ct1;
+    f.fd = rho * ((double)d0 - (double)c0 * (double)dt1);
+    f.la = (double)av[M - 1];
+    f.lc = (double)cv[M - 1];
+    f.ld = (double)dv[M - 1];
+    return f;
+}
+
+// Stage C on M register rows: dv becomes x.
+template <typename T, int M>
+__device__ __forceinline__ void substitute_partition(const T (&av)[M], const T (&cv)[M], T (&dv)[M],
+                                                     double x_first, double x_last) {
+    const T xf = (T)x_first;
+    dv[M - 1] = (T)x_last;
+#pragma unroll
+    for (int j = M - 2; j >= 1; --j) dv[j] = dv[j] - av[j] * xf - cv[j] * dv[j + 1];
+    dv[0] = xf;
+}
+
+// Stage B: PCR over the 2P interface rows of the S systems of a tile, in LDS.
+// Row i of system s lives at i*S + s of each of the three arrays (unit
+// diagonal kept implicit).  Lane (p, s) owns rows 2p and 2p+1; every thread
+// of the block must call this.  Returns X_{2p} and X_{2p+1}.
+__device__ __forceinline__ void pcr_interface(double *lds, int S, int s, int p, int P, Iface f,
+                                              double &x_first, double &x_last, bool &bad) {
+    const int R2 = 2 * P;
+    double *ra = lds, *rc = lds + R2 * S, *rd = lds + 2 * R2 * S;
+    const int i0 = 2 * p, i1 = 2 * p + 1;
+    double a0 = f.fa, c0 = f.fc, d0 = f.fd, a1 = f.la, c1 = f.lc, d1 = f.ld;
+    __syncthreads();
+    ra[i0 * S + s] = a0; rc[i0 * S + s] = c0; rd[i0 * S + s] = d0;
+    ra[i1 * S + s] = a1; rc[i1 * S + s] = c1; rd[i1 * S + s] = d1;
+    __syncthreads();
+    for (int h = 1; h < R2; h <<= 1) {
+        double am0 = 0, cm0 = 0, dm0 = 0, ap0 = 0, cp0 = 0, dp0 = 0;
+        double am1 = 0, cm1 = 0, dm1 = 0, ap1 = 0, cp1 = 0, dp1 = 0;
+        if (i0 - h >= 0) { const int q = (i0 - h) * S + s; am0 = ra[q]; cm0 = rc[q]; dm0 = rd[q]; }
+        if (i0 + h < R2) { const int q = (i0 + h) * S + s; ap0 = ra[q]; cp0 = rc[q]; dp0 = rd[q]; }
+        if (i1 - h >= 0) { const int q = (i1 - h) * S + s; am1 = ra[q]; cm1 = rc[q]; dm1 = rd[q]; }
+        if (i1 + h < R2) { const int q = (i1 + h) * S + s; ap1 = ra[q]; cp1 = rc[q]; dp1 = rd[q]; }
+        {
+            const double beta = 1.0 - a0 * cm0 - c0 * ap0;
+            bad |= bad_pivot(beta);
+            const double ib = 1.0 / beta;
+            const double na = -a0 * am0, nc = -c0 * cp0, nd = d0 - a0 * dm0 - c0 * dp0;
+            a0 = na * ib; c0 = nc * ib; d0 = nd * ib;
+        }
+        {
+            const double beta = 1.0 - a1 * cm1 - c1 * ap1;
+            bad |= bad_pivot(beta);
+            const double ib = 1.0 / beta;
+            const double na = -a1 * am1, nc = -c1 * cp1, nd = d1 - a1 * dm1 - c1 * dp1;
+            a1 = na * ib; c1 = nc * ib; d1 = nd * ib;
+        }
+        if (2 * h < R2) {
+            __syncthreads();
+            ra[i0 * S + s] = a0; rc[i0 * S + s] = c0; rd[i0 * S + s] = d0;
+            ra[i1 * S + s] = a1; rc[i1 * S + s] = c1; rd[i1 * S + s] = d1;
+            __syncthreads();
+        }
+    }
+    x_first = d0;
+    x_last = d1;
+}
+
+}  // namespace dev
+}  // namespace tdma

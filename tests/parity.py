@@ -1,0 +1,60 @@
+"""Helpers for GPU-vs-oracle parity tests.
+
+Inputs come from ``workloads`` (seeded, host), the expected values from
+``oracle`` (plain C FP64 Thomas), the candidate from the HIP library through
+its C ABI.  Errors are per system: max_i |x_i - x^_i| / max_i |x^_i|.
+"""
+import numpy as np
+
+import oracle
+from workloads import configs
+
+TOL_F64 = 1e-12      # FP64 bar (relative, per system, infinity norm)
+TOL_F32 = 1e-5       # plain FP32 bar
+TOL_REFINED = 1e-12  # FP32 sweeps + FP64 refinement
+
+
+def gather_rows(layout, arr):
+    """(nsys, n) view of a uniform layout (copy), or list of arrays (ragged)."""
+    if layout.ragged:
+        off = layout.offsets
+        return [arr[off[s]:off[s + 1]] for s in range(layout.nsys)]
+    s = np.arange(layout.nsys, dtype=np.int64)
+    base = (s % layout.nsys0) * layout.sys_stride0 + (s // layout.nsys0) * layout.sys_stride1
+    idx = base[:, None] + np.arange(layout.n, dtype=np.int64)[None, :] * layout.row_stride
+    return arr[idx]
+
+
+def per_system_error(layout, x, ref):
+    if layout.ragged:
+        xs, rs = gather_rows(layout, x), gather_rows(layout, ref)
+        return np.array([np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+                         for a, b in zip(xs, rs)])
+    X = gather_rows(layout, x)
+    R = gather_rows(layout, ref)
+    return np.max(np.abs(X - R), axis=1) / np.maximum(np.max(np.abs(R), axis=1), 1e-300)
+
+
+def host_problem(p, dtype=np.float64):
+    """Full host arrays of a problem and the coefficient dict for the oracle."""
+    a, b, c, d = configs.full_arrays(p)
+    return a, b, c, d
+
+
+def oracle_solution(p, a, b, c, d, precision=oracle.F64):
+    return oracle.solve_batch(p.layout, p.mode, a, b, c, d, shift=p.shift, precision=precision)
+
+
+def to_device(arrs, dtype):
+    import torch
+    return [None if v is None else torch.from_numpy(np.ascontiguousarray(v)).to("cuda", dtype)
+            for v in arrs]
+
+
+def device_coeffs(p, a, b, c, dtype):
+    import torch
+    ta, tb, tc = to_device([a, b, c], dtype)
+    shift = None
+    if p.shift is not None:
+        shift = torch.from_numpy(p.shift).to("cuda", dtype)
+    return dict(mode=p.mode, a=ta, b=tb, c=tc, shift=shift)

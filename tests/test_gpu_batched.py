@@ -1,0 +1,136 @@
+"""GPU parity of the fused on-chip solve (tdma_solve_batched) against the oracle."""
+import numpy as np
+import pytest
+
+from tests import parity
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _run(p, dtype=np.float64, inplace=False, shape=None):
+    import paper_2509_03933_amd as tdma
+    tt = torch.float64 if dtype == np.float64 else torch.float32
+    a, b, c, d = parity.host_problem(p)
+    if dtype == np.float32:
+        # the FP32 path solves the FP32-rounded problem; the oracle sees the same values
+        a, b, c, d = [None if v is None else v.astype(np.float32).astype(np.float64)
+                      for v in (a, b, c, d)]
+    ref = parity.oracle_solution(p, a, b, c, d)
+    coeffs = parity.device_coeffs(p, a, b, c, tt)
+    if p.shift is not None and dtype == np.float32:
+        pass
+    (td,) = parity.to_device([d], tt)
+    tx = td if inplace else torch.full_like(td, float("nan"))
+    if shape is None:
+        tdma.solve_batched(p.layout, coeffs, td, tx)
+    else:
+        tdma.solve_batched_tiled(p.layout, coeffs, td, tx, **shape)
+    tdma.check()
+    x = tx.double().cpu().numpy()
+    return parity.per_system_error(p.layout, x, ref), x, d
+
+
+def test_plain_contiguous_fp64():
+    """64 contiguous systems of n = 256, random dominant rows, FP64."""
+    err, _, _ = _run(configs.plain())
+    assert err.max() <= parity.TOL_F64, err.max()
+
+
+def test_plain_contiguous_fp32():
+    err, _, _ = _run(configs.plain(), np.float32)
+    assert err.max() <= parity.TOL_F32, err.max()
+
+
+@pytest.mark.parametrize("grid", [(64, 32, 256), (48, 20, 256)])
+def test_adi_zsweep_fp64(grid):
+    """Strided z-lines, shared tanh-grid operator; 48*20 systems leave a ragged last tile."""
+    err, _, _ = _run(configs.adi(*grid))
+    assert err.max() <= parity.TOL_F64, err.max()
+
+
+def test_adi_zsweep_full_size_fp64():
+    """The full 256^3 ADI z-sweep, every system compared."""
+    err, _, _ = _run(configs.adi(256, 256, 256))
+    assert err.max() <= parity.TOL_F64, err.max()
+
+
+def test_adi_zsweep_fp32():
+    err, _, _ = _run(configs.adi(64, 32, 256), np.float32)
+    assert err.max() <= parity.TOL_F32, err.max()
+
+
+@pytest.mark.parametrize("nz", [1024, 1000, 333])
+def test_perrow_zsystems_fp64(nz):
+    """Per-row random law along z (n = 1024 and lengths not divisible by the tile)."""
+    err, _, _ = _run(configs.partitioned(20, 16, nz))
+    assert err.max() <= parity.TOL_F64, err.max()
+
+
+def test_poisson_shift_fp64():
+    """Shared Poisson operator plus per-mode shift (bulk modes except the pinned one)."""
+    p = configs.poisson(32, 16, 512)
+    err, _, _ = _run(p)
+    # mode (0, 0) carries a placeholder shift in the bulk call; every mode is checked
+    assert err.max() <= parity.TOL_F64, err.max()
+
+
+def test_in_place():
+    err, _, _ = _run(configs.adi(32, 16, 128), inplace=True)
+    assert err.max() <= parity.TOL_F64
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 17, 63, 64, 65, 255])
+def test_short_systems(n):
+    err, _, _ = _run(configs.plain(nsys=37, n=n))
+    assert err.max() <= parity.TOL_F64, (n, err.max())
+    err, _, _ = _run(configs.partitioned(17, 3, n))
+    assert err.max() <= parity.TOL_F64, (n, err.max())
+
+
+def test_single_system():
+    err, _, _ = _run(configs.partitioned(1, 1, 700))
+    assert err.max() <= parity.TOL_F64
+
+
+def test_ragged_fp64():
+    r = configs.ragged(nsys=300, nmin=2, nmax=5000)
+    err, _, _ = _run(r)
+    assert err.max() <= parity.TOL_F64, err.max()
+
+
+def test_ragged_fp32():
+    r = configs.ragged(nsys=200, nmin=2, nmax=3000)
+    err, _, _ = _run(r, np.float32)
+    assert err.max() <= parity.TOL_F32, err.max()
+
+
+SHAPES_F64 = [dict(M=4, S=16, P=16), dict(M=8, S=16, P=8), dict(M=16, S=16, P=4),
+              dict(M=8, S=8, P=32), dict(M=4, S=64, P=8), dict(M=16, S=1, P=16)]
+
+
+@pytest.mark.parametrize("shape", SHAPES_F64, ids=lambda s: "M%d_S%d_P%d" % (s["M"], s["S"], s["P"]))
+def test_tile_shapes_fp64(shape):
+    """Every register-tile size gives the oracle's answer (n = 64 fits all shapes)."""
+    err, _, _ = _run(configs.partitioned(40, 2, 64), shape=shape)
+    assert err.max() <= parity.TOL_F64, err.max()
+    err, _, _ = _run(configs.plain(nsys=9, n=64), shape=shape)
+    assert err.max() <= parity.TOL_F64, err.max()
+
+
+def test_singular_flagged():
+    import paper_2509_03933_amd as tdma
+    n, nsys = 8, 16
+    a = torch.zeros(n * nsys, dtype=torch.float64, device="cuda")
+    b = torch.zeros_like(a)        # zero diagonal: first pivot is 0
+    c = torch.zeros_like(a)
+    d = torch.ones_like(a)
+    x = torch.empty_like(a)
+    lay = configs.Layout(n=n, nsys0=nsys, row_stride=1, sys_stride0=n)
+    tdma.solve_batched(lay, dict(mode=0, a=a, b=b, c=c), d, x)
+    with pytest.raises(tdma.TdmaError) as ei:
+        tdma.check()
+    assert ei.value.status == tdma.ESINGULAR
+    tdma.check()   # flag was cleared
