@@ -59,7 +59,8 @@ typedef enum {
  * Ragged form (offsets != NULL): `offsets` is a HOST array of nsys0+1
  * non-decreasing int64 entries, nsys1 must be 1, and system k occupies the
  * contiguous elements offsets[k] .. offsets[k+1]-1; `n` is ignored.
- * Every system needs n >= 2 (ragged: 2 <= length <= 65536).
+ * Every system needs n >= 2.  Ragged systems hold 2 .. 8192 rows in FP64 and
+ * 2 .. 16384 in FP32 (longer systems: TDMA_EUNSUPPORTED).
  */
 typedef struct tdma_layout {
     int64_t n;

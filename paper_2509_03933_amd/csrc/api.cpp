@@ -241,6 +241,10 @@ int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, hipStream_t st,
         while (Pp < P) Pp <<= 1;
         buckets[(int)Pp].push_back((int32_t)k);
     }
+    for (auto &kv : buckets)
+        if (kv.first > fused_max_threads(dtype, M))
+            return fail(TDMA_EUNSUPPORTED, "a ragged system needs %d partitions of %d rows (max %d)",
+                        kv.first, M, fused_max_threads(dtype, M));
     RaggedPlan rp;
     rp.nsys = nsys;
     std::vector<int32_t> all;

@@ -10,7 +10,7 @@
 
 namespace tdma {
 
-constexpr int64_t kMaxRaggedRows = 65536;
+constexpr int64_t kMaxRaggedRows = 16384;   // FP64 ragged systems stop at 8192
 
 struct RaggedBucket {
     TileShape shape;

@@ -108,7 +108,7 @@ def test_ragged_fp32():
 
 
 SHAPES_F64 = [dict(M=4, S=16, P=16), dict(M=8, S=16, P=8), dict(M=16, S=16, P=4),
-              dict(M=8, S=8, P=32), dict(M=4, S=64, P=8), dict(M=16, S=1, P=16)]
+              dict(M=8, S=8, P=32), dict(M=4, S=64, P=16), dict(M=16, S=1, P=16)]
 
 
 @pytest.mark.parametrize("shape", SHAPES_F64, ids=lambda s: "M%d_S%d_P%d" % (s["M"], s["S"], s["P"]))
