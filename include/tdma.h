@@ -100,15 +100,18 @@ int tdma_solve_batched(const tdma_layout *layout, const tdma_coeffs *coeffs, int
 
 /*
  * Explicit tile shape of the fused path (the autotuner's handle, also used by
- * tests).  rows_per_lane M: 4, 8, 16 (FP64) or 4, 8, 16, 32 (FP32);
- * systems_per_tile S: a power of two; partitions P: M*P >= n.  S*P lanes form
- * one workgroup, at most 1024 (512 when M rows of one array fill 128 bytes).
- * Uniform layouts only.
+ * tests).  kernel 0 (generic): rows_per_lane M = 4, 8, 16 (FP64) or 4, 8, 16,
+ * 32 (FP32); systems_per_tile S a power of two; partitions P with M*P >= n;
+ * S*P lanes form one workgroup, at most 1024 (512 when M rows of one array
+ * fill 128 bytes).  kernel 1 (shared operator: TDMA_COEF_SHARED without
+ * b_shift; coefficient factors built once per workgroup in LDS): M = 8, 16,
+ * 32 and P a power of two <= 64.  Uniform layouts only.
  */
 typedef struct tdma_tile {
     int rows_per_lane;
     int systems_per_tile;
     int partitions;
+    int kernel;
 } tdma_tile;
 
 int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype,
@@ -209,12 +212,28 @@ void tdma_graph_destroy(tdma_graph *graph);
  * schedules (partitioned path, using the pipeline model of Sec. 4.2.3) for
  * this shape on the calling device, store the winner in the in-process
  * cache (and in the JSON file named by TDMA_CACHE, if set).  Synchronous.
- * The buffers must be valid inputs of that shape; x is overwritten.
+ * The buffers must be valid inputs of that shape; x is overwritten and must
+ * not alias d.
  * what: 0 = fused path, 1 = partitioned path (model), 2 = partitioned path
  * (model, then measured check of the model's choice against brute force).
  */
 int tdma_autotune(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype,
                   const void *d, void *x, int what, void *stream);
+
+/* JSON record of the last tdma_autotune call on any thread: every candidate
+ * with its measured time (and, for the staged path, the per-stage times,
+ * the model's prediction and, with what = 2, the measured pipeline time),
+ * and the choice.  The string stays valid until the next tdma_autotune. */
+const char *tdma_autotune_last_json(void);
+
+/* The staged path's pipeline model (the paper's batch-size estimator,
+ * Sec. 4.2.3, on one GPU): predicted time of nsys systems in batches of
+ * `batch` from the per-batch stage times t_a, t_b, t_c (any unit) over the
+ * N_b + 2 steps of Algorithm 2 (step k issues A of batch k, B of batch k-1,
+ * C of batch k-2).  concurrent = 0: the stages of a step add up;
+ * concurrent = 1: B overlaps A and C (a step costs max(A + C, B)). */
+double tdma_pipeline_model_ms(int64_t nsys, int64_t batch, double t_a, double t_b, double t_c,
+                              int concurrent);
 
 /* Synchronise `stream`; return TDMA_ESINGULAR (and clear the flag) if any
  * kernel on this device met a zero or non-finite pivot, else TDMA_OK. */

@@ -40,7 +40,7 @@ class _Coeffs(ctypes.Structure):
 
 class _Tile(ctypes.Structure):
     _fields_ = [("rows_per_lane", ctypes.c_int), ("systems_per_tile", ctypes.c_int),
-                ("partitions", ctypes.c_int)]
+                ("partitions", ctypes.c_int), ("kernel", ctypes.c_int)]
 
 
 class _PartOpts(ctypes.Structure):
@@ -98,6 +98,10 @@ def lib():
             L.tdma_graph_destroy.restype = None
             L.tdma_autotune.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, vp, vp, i, vp]
             L.tdma_check.argtypes = [vp]
+            L.tdma_autotune_last_json.restype = ctypes.c_char_p
+            L.tdma_pipeline_model_ms.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                                 ctypes.c_double, ctypes.c_double, ctypes.c_int]
+            L.tdma_pipeline_model_ms.restype = ctypes.c_double
             L.tdma_status_string.argtypes = [i]
             L.tdma_status_string.restype = ctypes.c_char_p
             L.tdma_last_error.restype = ctypes.c_char_p
@@ -111,8 +115,8 @@ def lib():
 
 EXPORTED_SYMBOLS = ("tdma_solve_batched", "tdma_solve_batched_tiled", "tdma_solve_partitioned", "tdma_solve_refined",
                     "tdma_graph_create", "tdma_graph_launch", "tdma_graph_destroy",
-                    "tdma_autotune", "tdma_check", "tdma_status_string", "tdma_last_error",
-                    "tdma_shutdown")
+                    "tdma_autotune", "tdma_autotune_last_json", "tdma_pipeline_model_ms",
+                    "tdma_check", "tdma_status_string", "tdma_last_error", "tdma_shutdown")
 
 
 def _raise(status):
@@ -237,10 +241,11 @@ def solve_batched(layout, coeffs, d, x, stream=None):
                                     _stream_handle(stream)))
 
 
-def solve_batched_tiled(layout, coeffs, d, x, M, S, P, stream=None):
-    """Fused solve with an explicit tile shape (tdma_solve_batched_tiled)."""
+def solve_batched_tiled(layout, coeffs, d, x, M, S, P, kernel=0, stream=None):
+    """Fused solve with an explicit tile shape (tdma_solve_batched_tiled);
+    kernel 0 = generic, 1 = shared-operator."""
     L, C, keep = _prepare(layout, coeffs, d, x)
-    t = _Tile(int(M), int(S), int(P))
+    t = _Tile(int(M), int(S), int(P), int(kernel))
     _raise(lib().tdma_solve_batched_tiled(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),
                                           ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                           ctypes.byref(t), _stream_handle(stream)))
@@ -320,10 +325,19 @@ def graph_create(items):
 
 
 def autotune(layout, coeffs, d, x, what=0, stream=None):
+    """Tune and cache (tdma_autotune); returns the JSON record as a dict."""
+    import json
     L, C, keep = _prepare(layout, coeffs, d, x)
     _raise(lib().tdma_autotune(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),
                                ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(x.data_ptr()), int(what),
                                _stream_handle(stream)))
+    return json.loads(lib().tdma_autotune_last_json().decode())
+
+
+def pipeline_model_ms(nsys, batch, t_a, t_b, t_c, concurrent=1):
+    """The staged path's pipeline model (tdma_pipeline_model_ms)."""
+    return lib().tdma_pipeline_model_ms(int(nsys), int(batch), float(t_a), float(t_b), float(t_c),
+                                        int(concurrent))
 
 
 def check(stream=None):

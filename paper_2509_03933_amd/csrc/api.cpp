@@ -216,6 +216,33 @@ bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *o
     return false;
 }
 
+// Shared-operator kernel: P a power of two <= 64 (one system's interface rows
+// fit one wavefront), M in {16, 32, 8}; S as in the generic rule.
+bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *out) {
+    const int esz = dtype == TDMA_F64 ? 8 : 4;
+    const int Ms[] = {16, 32, 8};
+    for (int M : Ms) {
+        int64_t P = 1;
+        while (P * M < n) P <<= 1;
+        if (P > 64) continue;
+        TileShape sh;
+        sh.kernel = 1;
+        sh.M = M;
+        sh.P = (int)P;
+        sh.contig = contig;
+        int S_log2 = contig ? ilog2_floor(std::max<int64_t>(1, 256 / P)) : ilog2_floor(128 / esz);
+        const int maxt = shared_max_threads(dtype, M);
+        while (S_log2 > 0 && ((int64_t)1 << S_log2) * P > maxt) --S_log2;
+        while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= nsys) --S_log2;
+        sh.S_log2 = S_log2;
+        while (sh.S_log2 > 0 && shared_lds_bytes(dtype, sh) > 64 * 1024) --sh.S_log2;
+        if (!shared_supported(dtype, sh)) continue;
+        *out = sh;
+        return true;
+    }
+    return false;
+}
+
 // Ragged layout: systems are bucketed by the power-of-two partition count
 // they need; one launch per non-empty bucket (contiguous rows, LDS-staged).
 int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, hipStream_t st,
@@ -293,6 +320,7 @@ SysMap make_map(const tdma_layout *L) {
     m.sys_stride1 = L->sys_stride1;
     m.offsets = nullptr;
     m.sys_list = nullptr;
+    m.count = nullptr;
     return m;
 }
 
@@ -327,17 +355,32 @@ int run_fused(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dt
     const SysMap m = make_map(L);
     if (m.nsys == 0) return TDMA_OK;
     TileShape sh;
+    const bool contig = L->row_stride == 1;
+    const bool shared_op = C->mode == TDMA_COEF_SHARED && C->b_shift == nullptr;
     if (force) {
         sh = *force;
     } else if (!lookup_tuned(ctx->dev, L, C, dtype, &sh)) {
-        if (!default_shape(dtype, L->n, m.nsys, L->row_stride == 1, &sh))
+        if (!(shared_op && default_shared_shape(dtype, L->n, m.nsys, contig, &sh)) &&
+            !default_shape(dtype, L->n, m.nsys, contig, &sh))
             return fail(TDMA_EUNSUPPORTED, "n = %lld is too long for the fused path (use "
                         "tdma_solve_partitioned)", (long long)L->n);
     }
-    if (!fused_supported(dtype, sh) || (int64_t)sh.P * sh.M < L->n)
+    if ((int64_t)sh.P * sh.M < L->n)
         return fail(TDMA_EINVAL, "tile shape M=%d P=%d S=%d does not cover n=%lld", sh.M, sh.P,
                     1 << sh.S_log2, (long long)L->n);
-    hipError_t e = launch_fused(dtype, m, coef, sh, d, x, ctx->d_err, st);
+    hipError_t e;
+    if (sh.kernel == 1) {
+        if (!shared_op || !shared_supported(dtype, sh))
+            return fail(TDMA_EINVAL, "the shared-operator kernel needs shared coefficients without "
+                        "a shift and a power-of-two P <= 64 (M=%d P=%d S=%d)", sh.M, sh.P,
+                        1 << sh.S_log2);
+        e = launch_shared(dtype, m, coef, sh, d, x, ctx->d_err, st);
+    } else {
+        if (!fused_supported(dtype, sh))
+            return fail(TDMA_EINVAL, "unsupported tile shape M=%d P=%d S=%d", sh.M, sh.P,
+                        1 << sh.S_log2);
+        e = launch_fused(dtype, m, coef, sh, d, x, ctx->d_err, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "fused launch");
     return TDMA_OK;
 }
@@ -389,11 +432,15 @@ int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeff
     sh.S_log2 = 0;
     while ((1 << sh.S_log2) < S) ++sh.S_log2;
     sh.contig = layout->row_stride == 1;
-    if (!fused_supported(dtype, sh)) return fail(TDMA_EINVAL, "unsupported tile M=%d S=%d P=%d",
-                                                 sh.M, S, sh.P);
+    sh.kernel = tile->kernel;
+    if (sh.kernel != 0 && sh.kernel != 1) return fail(TDMA_EINVAL, "unknown kernel %d", sh.kernel);
+    if (sh.kernel == 0 && !fused_supported(dtype, sh))
+        return fail(TDMA_EINVAL, "unsupported tile M=%d S=%d P=%d", sh.M, S, sh.P);
+    if (sh.kernel == 1 && !shared_supported(dtype, sh))
+        return fail(TDMA_EINVAL, "unsupported shared-operator tile M=%d S=%d P=%d", sh.M, S, sh.P);
     if ((int64_t)sh.M * sh.P < layout->n) return fail(TDMA_EINVAL, "tile covers %lld rows < n = %lld",
                                                       (long long)sh.M * sh.P, (long long)layout->n);
-    if (sh.contig && fused_lds_bytes(dtype, sh) > 160 * 1024)
+    if (sh.kernel == 0 && sh.contig && fused_lds_bytes(dtype, sh) > 160 * 1024)
         return fail(TDMA_EINVAL, "tile needs %zu bytes of LDS", fused_lds_bytes(dtype, sh));
     DeviceCtx *ctx = nullptr;
     rc = get_ctx(&ctx);

@@ -7,54 +7,10 @@ namespace {
 
 using dev::Iface;
 using dev::LaneSys;
-
-template <typename T>
-struct Ident {
-    static constexpr T a = T(0), b = T(1), c = T(0), d = T(0);
-};
-
-// Per-tile system table for the LDS-staged (contiguous-row) path.
-struct TileSysLds {
-    int64_t base;
-    int64_t nrows;
-};
-
-// Cooperative coalesced copy of one tile array (S systems x R rows, rows
-// contiguous in memory) into LDS, then each lane picks its M rows.
-template <typename T, int M>
-__device__ __forceinline__ void stage_in(T *stg, const TileSysLds *tsys, const T *src, T ident,
-                                         int S, int R, int pitch, float invR, int s, int r0,
-                                         T (&dst)[M]) {
-    const int nthr = blockDim.x;
-    __syncthreads();
-    for (int e = threadIdx.x; e < S * R; e += nthr) {
-        int se = (int)(((float)e + 0.5f) * invR);
-        int re = e - se * R;
-        if (re < 0) { --se; re += R; } else if (re >= R) { ++se; re -= R; }
-        T v = ident;
-        if (re < tsys[se].nrows) v = src[tsys[se].base + re];
-        stg[se * pitch + re] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < M; ++j) dst[j] = stg[s * pitch + r0 + j];
-}
-
-template <typename T, int M>
-__device__ __forceinline__ void stage_out(T *stg, const TileSysLds *tsys, T *dst_g, int S, int R,
-                                          int pitch, float invR, int s, int r0, const T (&src)[M]) {
-    const int nthr = blockDim.x;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < M; ++j) stg[s * pitch + r0 + j] = src[j];
-    __syncthreads();
-    for (int e = threadIdx.x; e < S * R; e += nthr) {
-        int se = (int)(((float)e + 0.5f) * invR);
-        int re = e - se * R;
-        if (re < 0) { --se; re += R; } else if (re >= R) { ++se; re -= R; }
-        if (re < tsys[se].nrows) dst_g[tsys[se].base + re] = stg[se * pitch + re];
-    }
-}
+using dev::Ident;
+using dev::TileSysLds;
+using dev::stage_in;
+using dev::stage_out;
 
 // Largest block for M rows per lane: lanes holding >= 128 bytes per array
 // get up to 256 VGPRs (2+ waves/SIMD) instead of the 128 a 1024-block allows.
@@ -71,23 +27,26 @@ k_fused(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P, int *err) {
     const int p = tid >> S_log2;
     const int r0 = p * M;
     const int64_t k0 = (int64_t)blockIdx.x << S_log2;
+    if (map.count && k0 >= dev::launch_nsys(map)) return;   // whole tile past a device count
     const LaneSys sys = dev::lane_system(map, k0 + s);
     const T *__restrict__ A = (const T *)coef.a;
     const T *__restrict__ B = (const T *)coef.b;
     const T *__restrict__ C = (const T *)coef.c;
 
     T av[M], bv[M], cv[M], dv[M];
+    const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
     if constexpr (!CONTIG) {
+        const int64_t off0 = sys.base + (int64_t)r0 * map.row_stride;
+        const int64_t rs = map.row_stride;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            const int64_t r = r0 + j;
-            if (r < sys.nrows) {
-                const int64_t idx = sys.base + r * map.row_stride;
+            if (j < rows_here) {
+                const int64_t idx = off0 + j * rs;
                 dv[j] = d[idx];
                 if constexpr (LIKE_D) {
                     av[j] = A[idx]; bv[j] = B[idx]; cv[j] = C[idx];
                 } else {
-                    av[j] = A[r]; bv[j] = B[r]; cv[j] = C[r];
+                    av[j] = A[r0 + j]; bv[j] = B[r0 + j]; cv[j] = C[r0 + j];
                 }
             } else {
                 av[j] = Ident<T>::a; bv[j] = Ident<T>::b; cv[j] = Ident<T>::c; dv[j] = Ident<T>::d;
@@ -98,7 +57,7 @@ k_fused(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P, int *err) {
         const int pitch = R + 1;
         T *stg = reinterpret_cast<T *>(lds);
         const size_t stg_bytes = ((size_t)S * pitch * sizeof(T) + 15) & ~(size_t)15;
-        const size_t pcr_bytes = (size_t)6 * S * P * sizeof(double);
+        const size_t pcr_bytes = dev::pcr_lds_bytes(S, P);
         TileSysLds *tsys = reinterpret_cast<TileSysLds *>(
             reinterpret_cast<char *>(lds) + (stg_bytes > pcr_bytes ? stg_bytes : pcr_bytes));
         if (tid < S) {
@@ -141,21 +100,24 @@ k_fused(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P, int *err) {
     bool bad = false;
     const Iface f = dev::reduce_partition<T, M>(av, bv, cv, dv, bad);
     double xf, xl;
-    dev::pcr_interface(lds, S, s, p, P, f, xf, xl, bad);
+    if (P <= 64 && (P & (P - 1)) == 0)
+        dev::pcr_interface_wave(lds, S, s, p, P, __builtin_ctz(P), f, xf, xl, bad);
+    else
+        dev::pcr_interface(lds, S, s, p, P, f, xf, xl, bad);
     dev::substitute_partition<T, M>(av, cv, dv, xf, xl);
 
     if constexpr (!CONTIG) {
+        const int64_t off0 = sys.base + (int64_t)r0 * map.row_stride;
+        const int64_t rs = map.row_stride;
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            const int64_t r = r0 + j;
-            if (r < sys.nrows) x[sys.base + r * map.row_stride] = dv[j];
-        }
+        for (int j = 0; j < M; ++j)
+            if (j < rows_here) x[off0 + j * rs] = dv[j];
     } else {
         const int R = P * M;
         const int pitch = R + 1;
         T *stg = reinterpret_cast<T *>(lds);
         const size_t stg_bytes = ((size_t)S * pitch * sizeof(T) + 15) & ~(size_t)15;
-        const size_t pcr_bytes = (size_t)6 * S * P * sizeof(double);
+        const size_t pcr_bytes = dev::pcr_lds_bytes(S, P);
         TileSysLds *tsys = reinterpret_cast<TileSysLds *>(
             reinterpret_cast<char *>(lds) + (stg_bytes > pcr_bytes ? stg_bytes : pcr_bytes));
         stage_out<T, M>(stg, tsys, x, S, R, pitch, 1.0f / (float)R, s, r0, dv);
@@ -212,7 +174,7 @@ bool fused_supported(int dtype, const TileShape &sh) {
 
 size_t fused_lds_bytes(int dtype, const TileShape &sh) {
     const size_t S = (size_t)1 << sh.S_log2;
-    const size_t pcr = 6 * S * sh.P * sizeof(double);
+    const size_t pcr = dev::pcr_lds_bytes((int)S, sh.P);
     if (!sh.contig) return pcr;
     const size_t esz = dtype == TDMA_F64 ? 8 : 4;
     const size_t stg = (S * ((size_t)sh.P * sh.M + 1) * esz + 15) & ~(size_t)15;

@@ -1,0 +1,109 @@
+// tdma_solve_refined: planning, the FP64 fallback launch and the report.
+#include <algorithm>
+#include <cstring>
+
+#include "api_internal.h"
+#include "refine.h"
+
+namespace tdma {
+
+// Tile rule of the refinement kernel: M = 16 (else 8), P = ceil(n/M) rounded up
+// to a power of two when that stays <= 64 (interface PCR inside wavefronts);
+// S consecutive systems per tile as in the fused rule.
+static bool default_refine_shape(int64_t n, int64_t nsys, bool contig, bool like_d, TileShape *out) {
+    for (int M : {16, 8}) {
+        if (like_d && M != 8) continue;
+        int64_t P = (n + M - 1) / M;
+        int64_t P2 = 1;
+        while (P2 < P) P2 <<= 1;
+        if (P2 <= 64) P = P2;
+        TileShape sh;
+        sh.M = M;
+        sh.P = (int)P;
+        sh.contig = contig;
+        int S_log2 = 4;
+        if (contig) {
+            S_log2 = 0;
+            while ((2 << S_log2) * P <= 256) ++S_log2;
+        }
+        while (S_log2 > 0 && ((int64_t)1 << S_log2) * P > refine_max_threads(M)) --S_log2;
+        while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= nsys) --S_log2;
+        sh.S_log2 = S_log2;
+        while (sh.S_log2 > 0 && refine_lds_bytes(sh, like_d) > 96 * 1024) --sh.S_log2;
+        if (P > 1024 || !refine_supported(sh, like_d)) continue;
+        *out = sh;
+        return true;
+    }
+    return false;
+}
+
+}  // namespace tdma
+
+using namespace tdma;
+
+extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *coeffs,
+                                  const double *d, double *x, const tdma_refine_opts *opts,
+                                  tdma_refine_report *report, void *stream) {
+    clear_error();
+    int rc = validate(layout, coeffs, TDMA_F64, d, x);
+    if (rc != TDMA_OK) return rc;
+    if (layout->offsets) return fail(TDMA_EUNSUPPORTED, "the refined path takes uniform layouts");
+    const int iters = opts ? opts->max_iters : 3;
+    const double tol = opts && opts->tol > 0.0 ? opts->tol : 1e-15;
+    const int fallback = opts ? opts->fallback : 1;
+    if (iters < 0 || iters > 3) return fail(TDMA_EINVAL, "max_iters = %d (0..3)", iters);
+    if (fallback != 0 && fallback != 1) return fail(TDMA_EINVAL, "fallback = %d (0 or 1)", fallback);
+    const int64_t nsys = layout->nsys0 * layout->nsys1;
+    if (report) std::memset(report, 0, sizeof *report);
+    if (nsys == 0) return TDMA_OK;
+    TileShape sh;
+    if (!default_refine_shape(layout->n, nsys, layout->row_stride == 1,
+                              coeffs->mode == TDMA_COEF_LIKE_D, &sh))
+        return fail(TDMA_EUNSUPPORTED, "n = %lld is too long for the refined path",
+                    (long long)layout->n);
+    DeviceCtx *ctx = nullptr;
+    rc = get_ctx(&ctx);
+    if (rc != TDMA_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t capacity = std::min<int64_t>(nsys, (int64_t)1 << 16);
+    void *ws = nullptr;
+    rc = ctx->workspace(3, 256 + (size_t)capacity * sizeof(int32_t), &ws);
+    if (rc != TDMA_OK) return rc;
+    RefineState *state = (RefineState *)ws;
+    int32_t *list = (int32_t *)((char *)ws + 256);
+    hipError_t e = launch_refine_init(state, list, capacity, st);
+    if (e != hipSuccess) return hip_fail(e, "refine init");
+    const SysMap map = make_map(layout);
+    const Coef coef = make_coef(coeffs);
+    e = launch_refine(map, coef, sh, d, x, iters, tol, state, st);
+    if (e != hipSuccess) return hip_fail(e, "refine launch");
+    if (fallback) {
+        TileShape fsh;
+        if (!default_shape(TDMA_F64, layout->n, capacity, layout->row_stride == 1, &fsh))
+            return fail(TDMA_EUNSUPPORTED, "no FP64 fallback tile for n = %lld", (long long)layout->n);
+        SysMap fm = map;
+        fm.nsys = capacity;
+        fm.sys_list = list;
+        fm.count = &state->not_converged;
+        e = launch_fused(TDMA_F64, fm, coef, fsh, d, x, ctx->d_err, st);
+        if (e != hipSuccess) return hip_fail(e, "fallback launch");
+    }
+    if (!report) return TDMA_OK;
+    RefineState hs;
+    e = hipMemcpyAsync(&hs, state, sizeof hs, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "refine report");
+    double rel;
+    std::memcpy(&rel, &hs.max_rel_bits, sizeof rel);
+    report->iterations = iters;
+    report->not_converged = (int64_t)hs.not_converged;
+    report->fallback_systems = fallback ? std::min<int64_t>((int64_t)hs.not_converged, capacity) : 0;
+    report->max_rel_correction = rel;
+    if (!fallback && hs.not_converged > 0)
+        return fail(TDMA_ENOCONV, "%llu systems missed tol = %g after %d steps",
+                    (unsigned long long)hs.not_converged, tol, iters);
+    if ((int64_t)hs.not_converged > capacity)
+        return fail(TDMA_ENOCONV, "%llu systems missed tol; only %lld were re-solved in FP64",
+                    (unsigned long long)hs.not_converged, (long long)capacity);
+    return TDMA_OK;
+}

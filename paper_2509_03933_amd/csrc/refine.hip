@@ -1,0 +1,326 @@
+// Precision form: FP32 sweeps with FP64 iterative refinement, fused per tile.
+//
+// Per tile, on chip: the FP64 right-hand side d and solution x stay in
+// registers; the partition factors (pivot reciprocals g, h = a g, the
+// back-substitution factors a^, c^) are built once in FP32; then
+//     x = 0;  r = d;  repeat 1 + iters times:
+//         solve A e = r with the FP32 factors (Stage A/C in FP32, the 2P-row
+//         interface solve in FP64), x += e, r = d - A x  (FP64).
+// The residual needs each partition's outer neighbours, exchanged through
+// LDS.  After the last step a system is converged if max|e| <= tol max|x|;
+// systems that are not are appended to a device list that the FP64 fused
+// kernel re-solves (the fallback), and the tile reports its largest
+// relative correction.
+#include "refine.h"
+#include "tile.hip.h"
+
+namespace tdma {
+namespace {
+
+using dev::Iface;
+using dev::LaneSys;
+
+template <int M, bool LIKE_D, bool SHIFT, bool CONTIG>
+__global__ void __launch_bounds__(512)
+k_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, int P, int iters,
+         double tol, RefineState *state) {
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2;
+    const int s = tid & (S - 1);
+    const int p = tid >> S_log2;
+    const int r0 = p * M;
+    const int64_t n = map.n;
+    const int64_t k0 = (int64_t)blockIdx.x << S_log2;
+    const LaneSys sys = dev::lane_system(map, k0 + s);
+    const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
+    const double *A = (const double *)coef.a, *B = (const double *)coef.b,
+                 *C = (const double *)coef.c;
+    // LDS: [0, region0) PCR scratch or staging; XB = S x (2P+1) doubles; the
+    // shared coefficient tables (3 x P*M doubles, shared mode); the tile table
+    const int R = P * M;
+    const size_t pcr_b = dev::pcr_lds_bytes(S, P);
+    const size_t stg_b = CONTIG ? (((size_t)S * (R + 1) * 8 + 15) & ~(size_t)15) : 0;
+    const size_t region0 = pcr_b > stg_b ? pcr_b : stg_b;
+    double *XB = reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + region0);
+    const int xpitch = 2 * P + 1;
+    double *CT = reinterpret_cast<double *>(reinterpret_cast<char *>(XB) +
+                                            (((size_t)S * xpitch * 8 + 15) & ~(size_t)15));
+    const size_t ct_b = LIKE_D ? 0 : (size_t)3 * R * 8;
+    dev::TileSysLds *tsys = reinterpret_cast<dev::TileSysLds *>(reinterpret_cast<char *>(CT) + ct_b);
+    if constexpr (!LIKE_D) {
+        // one copy of the shared FP64 operator per workgroup, corners removed,
+        // identity rows past n
+        const double *A0 = (const double *)coef.a, *B0 = (const double *)coef.b,
+                     *C0 = (const double *)coef.c;
+        for (int r = tid; r < R; r += blockDim.x) {
+            const bool in = r < n;
+            CT[r] = in && r > 0 ? A0[r] : 0.0;
+            CT[R + r] = in ? B0[r] : 1.0;
+            CT[2 * R + r] = in && r < n - 1 ? C0[r] : 0.0;
+        }
+        __syncthreads();
+    }
+
+    double dv[M], av[LIKE_D ? M : 1], bv[LIKE_D ? M : 1], cv[LIKE_D ? M : 1];
+    if constexpr (!CONTIG) {
+        const double *pd = d + sys.base + (int64_t)r0 * map.row_stride;
+        const int64_t rs = map.row_stride;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const bool in = j < rows_here;
+            dv[j] = in ? pd[j * rs] : 0.0;
+            if constexpr (LIKE_D) {
+                const int64_t off = sys.base + (int64_t)(r0 + j) * rs;
+                av[j] = in ? A[off] : 0.0;
+                bv[j] = in ? B[off] : 1.0;
+                cv[j] = in ? C[off] : 0.0;
+            }
+        }
+    } else {
+        double *stg = lds;
+        if (tid < S) {
+            const LaneSys q = dev::lane_system(map, k0 + tid);
+            tsys[tid].base = q.base;
+            tsys[tid].nrows = q.nrows;
+        }
+        const float invR = 1.0f / (float)R;
+        dev::stage_in<double, M>(stg, tsys, d, 0.0, S, R, R + 1, invR, s, r0, dv);
+        if constexpr (LIKE_D) {
+            dev::stage_in<double, M>(stg, tsys, A, 0.0, S, R, R + 1, invR, s, r0, av);
+            dev::stage_in<double, M>(stg, tsys, B, 1.0, S, R, R + 1, invR, s, r0, bv);
+            dev::stage_in<double, M>(stg, tsys, C, 0.0, S, R, R + 1, invR, s, r0, cv);
+        }
+    }
+    double shv = 0.0;
+    if constexpr (SHIFT) {
+        if (sys.valid) shv = ((const double *)coef.shift)[sys.id];
+    }
+    // FP64 coefficients of local row j (identity beyond the system)
+    auto coefs = [&](int j, double &a, double &b, double &c) {
+        const int64_t r = r0 + j;
+        if constexpr (LIKE_D) {
+            if (j < rows_here) {
+                a = r == 0 ? 0.0 : av[j];
+                b = bv[j];
+                c = r == n - 1 ? 0.0 : cv[j];
+                if constexpr (SHIFT) b += shv;
+            } else {
+                a = 0.0; b = 1.0; c = 0.0;
+            }
+        } else {
+            a = CT[r]; b = CT[R + r]; c = CT[2 * R + r];
+            if constexpr (SHIFT) {
+                if (j < rows_here) b += shv;
+            }
+        }
+    };
+
+    // FP32 factors
+    float g[M], fa[M], fc[M];
+    bool bad = false;
+    float piv;
+    {
+        double a, b, c;
+        coefs(0, a, b, c);
+        piv = (float)b;
+        bad |= dev::bad_pivot(piv);
+        g[0] = dev::recip(piv);
+        fa[0] = (float)a * g[0]; fc[0] = (float)c * g[0];
+        coefs(1, a, b, c);
+        piv = (float)b;
+        bad |= dev::bad_pivot(piv);
+        g[1] = dev::recip(piv);
+        fa[1] = (float)a * g[1]; fc[1] = (float)c * g[1];
+#pragma unroll
+        for (int j = 2; j < M; ++j) {
+            coefs(j, a, b, c);
+            piv = (float)b - (float)a * fc[j - 1];
+            bad |= dev::bad_pivot(piv);
+            g[j] = dev::recip(piv);
+            fa[j] = -((float)a * g[j]) * fa[j - 1];
+            fc[j] = (float)c * g[j];
+        }
+    }
+    float pi = 1.0f, at1 = 0.0f;
+#pragma unroll
+    for (int j = 1; j <= M - 2; ++j) {
+        at1 += pi * fa[j];
+        pi = -fc[j] * pi;
+    }
+    const float ct1 = -pi;
+    const double den = 1.0 - (double)fc[0] * (double)at1;
+    bad |= dev::bad_pivot(den);
+    const double rho = 1.0 / den;
+    Iface f;
+    f.fa = rho * (double)fa[0];
+    f.fc = -rho * (double)fc[0] * (double)ct1;
+    f.la = (double)fa[M - 1];
+    f.lc = (double)fc[M - 1];
+    const double K0 = rho * (double)g[0], K1 = rho * (double)fc[0];
+    const bool wave_pcr = P <= 64 && (P & (P - 1)) == 0;
+    const int P_log2 = __builtin_ctz(P);
+
+    double xv[M];
+    float e[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) xv[j] = 0.0;
+    for (int it = 0; it <= iters; ++it) {
+        // r = d - A x (FP64); first pass r = d
+        if (it == 0) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) e[j] = (float)dv[j];
+        } else {
+            __syncthreads();
+            XB[s * xpitch + 2 * p] = xv[0];
+            XB[s * xpitch + 2 * p + 1] = xv[M - 1];
+            __syncthreads();
+            const double xlo = p > 0 ? XB[s * xpitch + 2 * p - 1] : 0.0;
+            const double xhi = p < P - 1 ? XB[s * xpitch + 2 * p + 2] : 0.0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                double a, b, c;
+                coefs(j, a, b, c);
+                const double xm = j == 0 ? xlo : xv[j > 0 ? j - 1 : 0];
+                const double xp = j == M - 1 ? xhi : xv[j < M - 1 ? j + 1 : M - 1];
+                e[j] = (float)(dv[j] - a * xm - b * xv[j] - c * xp);
+            }
+        }
+        // solve A e = r with the FP32 factors
+        const float r0v = e[0];
+        e[1] = g[1] * e[1];
+#pragma unroll
+        for (int j = 2; j < M; ++j) {
+            double a, b, c;
+            coefs(j, a, b, c);
+            e[j] = (e[j] - (float)a * e[j - 1]) * g[j];
+        }
+        float dt1 = 0.0f;
+        pi = 1.0f;
+#pragma unroll
+        for (int j = 1; j <= M - 2; ++j) {
+            dt1 += pi * e[j];
+            pi = -fc[j] * pi;
+        }
+        f.fd = K0 * (double)r0v - K1 * (double)dt1;
+        f.ld = (double)e[M - 1];
+        double xf, xl;
+        if (wave_pcr)
+            dev::pcr_interface_wave(lds, S, s, p, P, P_log2, f, xf, xl, bad);
+        else
+            dev::pcr_interface(lds, S, s, p, P, f, xf, xl, bad);
+        e[M - 1] = (float)xl;
+#pragma unroll
+        for (int j = M - 2; j >= 1; --j) e[j] = e[j] - fa[j] * (float)xf - fc[j] * e[j + 1];
+        e[0] = (float)xf;
+#pragma unroll
+        for (int j = 0; j < M; ++j) xv[j] += (double)e[j];
+    }
+    // convergence of the last correction, per system: max|e| <= tol max|x|
+    float emax = 0.0f;
+    double xmax = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        emax = fmaxf(emax, fabsf(e[j]));
+        xmax = fmax(xmax, fabs(xv[j]));
+    }
+    // a zero or non-finite FP32 pivot sends the system to the FP64 fallback
+    if (bad) emax = __builtin_huge_valf();
+    __syncthreads();
+    XB[s * xpitch + 2 * p] = (double)emax;
+    XB[s * xpitch + 2 * p + 1] = xmax;
+    __syncthreads();
+    if (p == 0 && sys.valid) {
+        double em = 0.0, xm = 0.0;
+        for (int q = 0; q < P; ++q) {
+            em = fmax(em, XB[s * xpitch + 2 * q]);
+            xm = fmax(xm, XB[s * xpitch + 2 * q + 1]);
+        }
+        const double rel = xm > 0.0 ? em / xm : (em > 0.0 ? 1.0 : 0.0);
+        const bool conv = rel <= tol && rel == rel;
+        atomicMax(&state->max_rel_bits, (unsigned long long)__double_as_longlong(rel == rel ? rel : 1e300));
+        if (!conv) {
+            const unsigned long long slot = atomicAdd(&state->not_converged, 1ull);
+            if (state->fallback_list && slot < (unsigned long long)state->list_capacity)
+                state->fallback_list[slot] = (int32_t)sys.id;
+        }
+    }
+    if constexpr (!CONTIG) {
+        double *px = x + sys.base + (int64_t)r0 * map.row_stride;
+        const int64_t rs = map.row_stride;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (j < rows_here) px[j * rs] = xv[j];
+    } else {
+        dev::stage_out<double, M>(lds, tsys, x, S, R, R + 1, 1.0f / (float)R, s, r0, xv);
+    }
+}
+
+__global__ void k_refine_init(RefineState *state, int32_t *list, int64_t capacity) {
+    state->not_converged = 0ull;
+    state->max_rel_bits = 0ull;
+    state->fallback_list = list;
+    state->list_capacity = capacity;
+}
+
+template <int M>
+hipError_t launch_m(const SysMap &map, const Coef &coef, const TileShape &sh, const double *d,
+                    double *x, int iters, double tol, RefineState *state, size_t lds, hipStream_t st) {
+    const int64_t S = (int64_t)1 << sh.S_log2;
+    const int64_t blocks = (map.nsys + S - 1) / S;
+    if (blocks == 0) return hipSuccess;
+    const bool like_d = coef.mode == TDMA_COEF_LIKE_D, shift = coef.shift != nullptr;
+#define TDMA_R(LD, SH, CT)                                                                       \
+    if (like_d == LD && shift == SH && sh.contig == CT) {                                        \
+        hipLaunchKernelGGL((k_refine<M, LD, SH, CT>), dim3((unsigned)blocks), dim3(sh.threads()), \
+                           lds, st, map, coef, d, x, sh.S_log2, sh.P, iters, tol, state);        \
+        return hipGetLastError();                                                                \
+    }
+    if constexpr (M == 8) {   // per-row coefficients only with M = 8
+        TDMA_R(true, false, false)
+        TDMA_R(true, true, false)
+        TDMA_R(true, false, true)
+        TDMA_R(true, true, true)
+    }
+    TDMA_R(false, false, false)
+    TDMA_R(false, true, false)
+    TDMA_R(false, false, true)
+    TDMA_R(false, true, true)
+#undef TDMA_R
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+size_t refine_lds_bytes(const TileShape &sh, bool like_d) {
+    const int S = 1 << sh.S_log2;
+    const size_t pcr_b = dev::pcr_lds_bytes(S, sh.P);
+    const size_t stg_b = sh.contig ? (((size_t)S * (sh.P * sh.M + 1) * 8 + 15) & ~(size_t)15) : 0;
+    const size_t region0 = pcr_b > stg_b ? pcr_b : stg_b;
+    const size_t ct_b = like_d ? 0 : (size_t)3 * sh.P * sh.M * 8;
+    return region0 + (((size_t)S * (2 * sh.P + 1) * 8 + 15) & ~(size_t)15) + ct_b + 16 * (size_t)S;
+}
+
+int refine_max_threads(int) { return 512; }
+
+bool refine_supported(const TileShape &sh, bool like_d) {
+    if (sh.M != 8 && sh.M != 16) return false;
+    if (like_d && sh.M != 8) return false;
+    if (sh.P < 1 || sh.threads() > refine_max_threads(sh.M)) return false;
+    return refine_lds_bytes(sh, like_d) <= 160 * 1024;
+}
+
+hipError_t launch_refine_init(RefineState *state, int32_t *list, int64_t capacity, hipStream_t st) {
+    hipLaunchKernelGGL(k_refine_init, dim3(1), dim3(1), 0, st, state, list, capacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine(const SysMap &map, const Coef &coef, const TileShape &sh, const double *d,
+                         double *x, int iters, double tol, RefineState *state, hipStream_t st) {
+    const size_t lds = refine_lds_bytes(sh, coef.mode == TDMA_COEF_LIKE_D);
+    if (sh.M == 8) return launch_m<8>(map, coef, sh, d, x, iters, tol, state, lds, st);
+    if (sh.M == 16) return launch_m<16>(map, coef, sh, d, x, iters, tol, state, lds, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tdma

@@ -1,0 +1,358 @@
+// Shared-operator fused solve (the ADI and Poisson-line case where every
+// system of a launch has the same a, b, c; the coefficient matrix depends only
+// on the grid spacing).  The Stage A/B/C arithmetic is that of tile.hip.h, but
+// everything that depends only on the coefficients is computed once per
+// workgroup into LDS tables while the tile's right-hand sides are in flight:
+//   per partition row j:  G_j, H_j   (d^_j = G_j d_j - H_j d^_{j-1}),
+//                         pi_j       (running products of the row-1 spike),
+//                         a^_j, c^_j (back-substitution factors),
+//   per partition:        K0, K1     (first interface RHS = K0 d_0 - K1 dt1)
+//                         and the four interface coefficients,
+//   per PCR step and interface row: the pre-step couplings and 1/beta.
+// The per-system work is then about five FP64 operations per row, and the
+// interface solve exchanges one value per row instead of three.
+#include "tile.hip.h"
+
+namespace tdma {
+namespace {
+
+using dev::Ident;
+using dev::LaneSys;
+using dev::TileSysLds;
+
+// LDS carve-up, byte offsets (each region 16-byte aligned):
+//   g, h, pi, ah, ch : P x (M+1) values of T (odd pitch against bank conflicts)
+//   part             : 6 x P doubles (K0, K1, AF, GF, AL, GL)
+//   qa               : 3 x nsteps x 2P doubles (pre-step a, c and 1/beta)
+//   xd               : S x (2P+1) doubles (interface right-hand sides)
+//   end              : staging of the contiguous-row variant starts here
+struct SharedLds {
+    size_t g, h, pi, ah, ch, part, qa, xd, end;
+    int nsteps;
+};
+
+__host__ __device__ inline int ilog2i(int v) {
+    int r = 0;
+    while ((1 << (r + 1)) <= v) ++r;
+    return r;
+}
+
+__host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+__host__ __device__ inline SharedLds shared_layout(size_t esz, int M, int P, int S) {
+    SharedLds L;
+    const size_t tab = align16((size_t)P * (M + 1) * esz);
+    L.g = 0;
+    L.h = L.g + tab;
+    L.pi = L.h + tab;
+    L.ah = L.pi + tab;
+    L.ch = L.ah + tab;
+    L.part = L.ch + tab;
+    L.nsteps = ilog2i(2 * P);
+    if ((1 << L.nsteps) < 2 * P) ++L.nsteps;
+    L.qa = align16(L.part + 6 * (size_t)P * 8);
+    L.xd = align16(L.qa + 3 * (size_t)L.nsteps * 2 * P * 8);
+    L.end = align16(L.xd + (size_t)S * (2 * P + 1) * 8);
+    return L;
+}
+
+// contiguous-row variant: staging of S x (P*M+1) values of T, then S tile entries
+__host__ __device__ inline size_t shared_stage_off(const SharedLds &L) { return L.end; }
+__host__ __device__ inline size_t shared_tsys_off(const SharedLds &L, size_t esz, int M, int P, int S) {
+    return align16(L.end + (size_t)S * ((size_t)P * M + 1) * esz);
+}
+
+template <typename T, int M>
+constexpr int shared_max_threads() { return (int)sizeof(T) * M >= 256 ? 512 : 1024; }
+
+template <typename T, int M, bool CONTIG>
+__global__ void __launch_bounds__((shared_max_threads<T, M>()))
+k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *err) {
+    extern __shared__ double lds[];
+    char *base = reinterpret_cast<char *>(lds);
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2, P = 1 << P_log2;
+    const int s = tid & (S - 1);
+    const int p = tid >> S_log2;
+    const int r0 = p * M;
+    const int64_t n = map.n;
+    const int64_t k0 = (int64_t)blockIdx.x << S_log2;
+    const LaneSys sys = dev::lane_system(map, k0 + s);
+    const SharedLds L = shared_layout(sizeof(T), M, P, S);
+    const int pitch = M + 1;
+    T *G = reinterpret_cast<T *>(base + L.g);
+    T *H = reinterpret_cast<T *>(base + L.h);
+    T *PI = reinterpret_cast<T *>(base + L.pi);
+    T *AH = reinterpret_cast<T *>(base + L.ah);
+    T *CH = reinterpret_cast<T *>(base + L.ch);
+    double *PT = reinterpret_cast<double *>(base + L.part);
+    double *K0 = PT, *K1 = PT + P, *AF = PT + 2 * P, *GF = PT + 3 * P, *AL = PT + 4 * P,
+           *GL = PT + 5 * P;
+    double *QA = reinterpret_cast<double *>(base + L.qa);
+    double *QC = QA + L.nsteps * 2 * P, *QB = QC + L.nsteps * 2 * P;
+    double *XD = reinterpret_cast<double *>(base + L.xd);
+    const int xpitch = 2 * P + 1;
+
+    // 1. right-hand sides of this lane's rows (in flight while the tables are built)
+    T dv[M];
+    if constexpr (!CONTIG) {
+        const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
+        const T *pd = d + sys.base + (int64_t)r0 * map.row_stride;
+        const int64_t rs = map.row_stride;
+        if (rows_here == M) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) dv[j] = pd[j * rs];
+        } else {
+#pragma unroll
+            for (int j = 0; j < M; ++j) dv[j] = j < rows_here ? pd[j * rs] : T(0);
+        }
+    } else {
+        const int R = P * M;
+        T *stg = reinterpret_cast<T *>(base + shared_stage_off(L));
+        TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, sizeof(T), M, P, S));
+        if (tid < S) {
+            const LaneSys q = dev::lane_system(map, k0 + tid);
+            tsys[tid].base = q.base;
+            tsys[tid].nrows = q.nrows;
+        }
+        dev::stage_in<T, M>(stg, tsys, d, T(0), S, R, R + 1, 1.0f / (float)R, s, r0, dv);
+    }
+
+    // 2. coefficient tables, one lane per partition (FP64 arithmetic)
+    bool bad = false;
+    if (s == 0) {
+        const T *A = (const T *)coef.a, *B = (const T *)coef.b, *C = (const T *)coef.c;
+        auto row = [&](int j, double &aj, double &bj, double &cj) {
+            const int64_t r = r0 + j;
+            if (r < n) {
+                aj = r == 0 ? 0.0 : (double)A[r];
+                bj = (double)B[r];
+                cj = r == n - 1 ? 0.0 : (double)C[r];
+            } else {
+                aj = 0.0; bj = 1.0; cj = 0.0;
+            }
+        };
+        double a0, b0, c0, aj, bj, cj;
+        row(0, a0, b0, c0);
+        bad |= dev::bad_pivot(b0);
+        const double ib0 = 1.0 / b0;
+        const double ah0 = a0 * ib0, ch0 = c0 * ib0;
+        T *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch, *ah = AH + p * pitch,
+          *ch = CH + p * pitch;
+        g[0] = (T)ib0; h[0] = T(0); pi_t[0] = T(0); ah[0] = (T)ah0; ch[0] = (T)ch0;
+        row(1, aj, bj, cj);
+        bad |= dev::bad_pivot(bj);
+        double gj = 1.0 / bj;
+        double ahp = aj * gj, chp = cj * gj;
+        g[1] = (T)gj; h[1] = T(0); ah[1] = (T)ahp; ch[1] = (T)chp;
+        double pi = 1.0, at1 = 0.0;
+        if (M > 2) { pi_t[1] = (T)pi; at1 += pi * ahp; pi = -chp * pi; }
+#pragma unroll 1
+        for (int j = 2; j < M; ++j) {
+            row(j, aj, bj, cj);
+            const double piv = bj - aj * chp;
+            bad |= dev::bad_pivot(piv);
+            gj = 1.0 / piv;
+            const double hj = aj * gj;
+            ahp = -hj * ahp;
+            chp = cj * gj;
+            g[j] = (T)gj; h[j] = (T)hj; ah[j] = (T)ahp; ch[j] = (T)chp;
+            if (j <= M - 2) { pi_t[j] = (T)pi; at1 += pi * ahp; pi = -chp * pi; }
+        }
+        pi_t[M - 1] = T(0);
+        const double ct1 = -pi;
+        const double den = 1.0 - ch0 * at1;
+        bad |= dev::bad_pivot(den);
+        const double rho = 1.0 / den;
+        K0[p] = rho * ib0;
+        K1[p] = rho * ch0;
+        AF[p] = rho * ah0;
+        GF[p] = -rho * ch0 * ct1;
+        AL[p] = ahp;
+        GL[p] = chp;
+    }
+    __syncthreads();
+    // 3. coefficient history of the interface PCR (first wavefront; P <= 64)
+    if (tid < 64) {
+        const int lane = tid;
+        const bool act = lane < P;
+        double a0 = act ? AF[lane] : 0.0, c0 = act ? GF[lane] : 0.0;
+        double a1 = act ? AL[lane] : 0.0, c1 = act ? GL[lane] : 0.0;
+        int k = 0;
+        for (int h = 1; h < 2 * P; h <<= 1, ++k) {
+            double la0, lc0, la1, lc1, ua0, uc0, ua1, uc1;
+            if (h == 1) {
+                const bool has_lo = lane > 0 && act, has_hi = lane < P - 1 && act;
+                const int lo = has_lo ? lane - 1 : lane, hi = has_hi ? lane + 1 : lane;
+                const double m_a = __shfl(a1, lo), m_c = __shfl(c1, lo);
+                const double p_a = __shfl(a0, hi), p_c = __shfl(c0, hi);
+                la0 = has_lo ? m_a : 0.0; lc0 = has_lo ? m_c : 0.0;   // row 2l-1
+                ua0 = a1; uc0 = c1;                                    // row 2l+1
+                la1 = a0; lc1 = c0;                                    // row 2l
+                ua1 = has_hi ? p_a : 0.0; uc1 = has_hi ? p_c : 0.0;   // row 2l+2
+            } else {
+                const int dl = h >> 1;
+                const bool has_lo = lane >= dl && act, has_hi = lane + dl < P && act;
+                const int lo = has_lo ? lane - dl : lane, hi = has_hi ? lane + dl : lane;
+                const double x_a0 = __shfl(a0, lo), x_c0 = __shfl(c0, lo);
+                const double x_a1 = __shfl(a1, lo), x_c1 = __shfl(c1, lo);
+                const double y_a0 = __shfl(a0, hi), y_c0 = __shfl(c0, hi);
+                const double y_a1 = __shfl(a1, hi), y_c1 = __shfl(c1, hi);
+                la0 = has_lo ? x_a0 : 0.0; lc0 = has_lo ? x_c0 : 0.0;
+                la1 = has_lo ? x_a1 : 0.0; lc1 = has_lo ? x_c1 : 0.0;
+                ua0 = has_hi ? y_a0 : 0.0; uc0 = has_hi ? y_c0 : 0.0;
+                ua1 = has_hi ? y_a1 : 0.0; uc1 = has_hi ? y_c1 : 0.0;
+            }
+            const double b0 = 1.0 - a0 * lc0 - c0 * ua0;
+            const double b1 = 1.0 - a1 * lc1 - c1 * ua1;
+            if (act) {
+                bad |= dev::bad_pivot(b0) || dev::bad_pivot(b1);
+                const int i0 = 2 * lane, i1 = i0 + 1, base_k = k * 2 * P;
+                QA[base_k + i0] = a0; QC[base_k + i0] = c0; QB[base_k + i0] = 1.0 / b0;
+                QA[base_k + i1] = a1; QC[base_k + i1] = c1; QB[base_k + i1] = 1.0 / b1;
+            }
+            const double ib0 = 1.0 / b0, ib1 = 1.0 / b1;
+            const double na0 = -a0 * la0 * ib0, nc0 = -c0 * uc0 * ib0;
+            const double na1 = -a1 * la1 * ib1, nc1 = -c1 * uc1 * ib1;
+            a0 = na0; c0 = nc0; a1 = na1; c1 = nc1;
+        }
+    }
+    __syncthreads();
+
+    // 4. Stage A on this lane's right-hand sides
+    const T *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch;
+    const T draw0 = dv[0];
+    dv[1] = g[1] * dv[1];
+#pragma unroll
+    for (int j = 2; j < M; ++j) dv[j] = g[j] * dv[j] - h[j] * dv[j - 1];
+    T dt1 = T(0);
+#pragma unroll
+    for (int j = 1; j <= M - 2; ++j) dt1 += pi_t[j] * dv[j];
+    const double df = K0[p] * (double)draw0 - K1[p] * (double)dt1;
+    const double dl_ = (double)dv[M - 1];
+
+    // 5. Stage B: right-hand-side-only PCR inside wavefronts
+    XD[s * xpitch + 2 * p] = df;
+    XD[s * xpitch + 2 * p + 1] = dl_;
+    __syncthreads();
+    {
+        const int s2 = tid >> P_log2;
+        const int p2 = tid & (P - 1);
+        const int lane = tid & 63;
+        const int q2 = s2 * xpitch + 2 * p2;
+        double e0 = XD[q2], e1 = XD[q2 + 1];
+        int k = 0;
+        for (int hh = 1; hh < 2 * P; hh <<= 1, ++k) {
+            const int i0 = 2 * p2, i1 = i0 + 1, bk = k * 2 * P;
+            double l0, u0, l1, u1;
+            if (hh == 1) {
+                const bool has_lo = p2 > 0, has_hi = p2 < P - 1;
+                const double m = __shfl(e1, has_lo ? lane - 1 : lane);
+                const double pp = __shfl(e0, has_hi ? lane + 1 : lane);
+                l0 = has_lo ? m : 0.0; u0 = e1;
+                l1 = e0; u1 = has_hi ? pp : 0.0;
+            } else {
+                const int dl = hh >> 1;
+                const bool has_lo = p2 >= dl, has_hi = p2 + dl < P;
+                const int lo = has_lo ? lane - dl : lane, hi = has_hi ? lane + dl : lane;
+                const double x0 = __shfl(e0, lo), x1 = __shfl(e1, lo);
+                const double y0 = __shfl(e0, hi), y1 = __shfl(e1, hi);
+                l0 = has_lo ? x0 : 0.0; l1 = has_lo ? x1 : 0.0;
+                u0 = has_hi ? y0 : 0.0; u1 = has_hi ? y1 : 0.0;
+            }
+            e0 = (e0 - QA[bk + i0] * l0 - QC[bk + i0] * u0) * QB[bk + i0];
+            e1 = (e1 - QA[bk + i1] * l1 - QC[bk + i1] * u1) * QB[bk + i1];
+        }
+        XD[q2] = e0;
+        XD[q2 + 1] = e1;
+    }
+    __syncthreads();
+    const T xf = (T)XD[s * xpitch + 2 * p];
+    const T xl = (T)XD[s * xpitch + 2 * p + 1];
+
+    // 6. Stage C
+    const T *ah = AH + p * pitch, *ch = CH + p * pitch;
+    dv[M - 1] = xl;
+#pragma unroll
+    for (int j = M - 2; j >= 1; --j) dv[j] = dv[j] - ah[j] * xf - ch[j] * dv[j + 1];
+    dv[0] = xf;
+
+    if constexpr (!CONTIG) {
+        const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
+        T *px = x + sys.base + (int64_t)r0 * map.row_stride;
+        const int64_t rs = map.row_stride;
+        if (rows_here == M) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) px[j * rs] = dv[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (j < rows_here) px[j * rs] = dv[j];
+        }
+    } else {
+        const int R = P * M;
+        T *stg = reinterpret_cast<T *>(base + shared_stage_off(L));
+        TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, sizeof(T), M, P, S));
+        dev::stage_out<T, M>(stg, tsys, x, S, R, R + 1, 1.0f / (float)R, s, r0, dv);
+    }
+    if (bad) atomicOr(err, 1);
+}
+
+template <typename T, int M>
+hipError_t launch_m(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
+                    void *x, int *err, size_t lds, hipStream_t st) {
+    const int64_t S = (int64_t)1 << sh.S_log2;
+    const int64_t blocks = (map.nsys + S - 1) / S;
+    if (blocks == 0) return hipSuccess;
+    const int P_log2 = ilog2i(sh.P);
+    if (sh.contig)
+        hipLaunchKernelGGL((k_shared<T, M, true>), dim3((unsigned)blocks), dim3(sh.threads()), lds, st,
+                           map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, err);
+    else
+        hipLaunchKernelGGL((k_shared<T, M, false>), dim3((unsigned)blocks), dim3(sh.threads()), lds, st,
+                           map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, err);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int shared_max_threads(int dtype, int M) {
+    const int esz = dtype == TDMA_F64 ? 8 : 4;
+    return esz * M >= 256 ? 512 : 1024;
+}
+
+size_t shared_lds_bytes(int dtype, const TileShape &sh) {
+    const int S = 1 << sh.S_log2;
+    const size_t esz = dtype == TDMA_F64 ? 8 : 4;
+    const SharedLds L = shared_layout(esz, sh.M, sh.P, S);
+    if (!sh.contig) return L.end;
+    return shared_tsys_off(L, esz, sh.M, sh.P, S) + 16 * (size_t)S;
+}
+
+bool shared_supported(int dtype, const TileShape &sh) {
+    if (sh.P < 1 || sh.P > 64 || (sh.P & (sh.P - 1)) != 0) return false;
+    if (sh.M != 8 && sh.M != 16 && sh.M != 32) return false;
+    if (sh.threads() > shared_max_threads(dtype, sh.M)) return false;
+    return shared_lds_bytes(dtype, sh) <= 160 * 1024;
+}
+
+hipError_t launch_shared(int dtype, const SysMap &map, const Coef &coef, const TileShape &sh,
+                         const void *d, void *x, int *err, hipStream_t st) {
+    const size_t lds = shared_lds_bytes(dtype, sh);
+    if (dtype == TDMA_F64) {
+        switch (sh.M) {
+            case 8: return launch_m<double, 8>(map, coef, sh, d, x, err, lds, st);
+            case 16: return launch_m<double, 16>(map, coef, sh, d, x, err, lds, st);
+            case 32: return launch_m<double, 32>(map, coef, sh, d, x, err, lds, st);
+        }
+    } else if (dtype == TDMA_F32) {
+        switch (sh.M) {
+            case 8: return launch_m<float, 8>(map, coef, sh, d, x, err, lds, st);
+            case 16: return launch_m<float, 16>(map, coef, sh, d, x, err, lds, st);
+            case 32: return launch_m<float, 32>(map, coef, sh, d, x, err, lds, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tdma

@@ -20,6 +20,7 @@ struct SysMap {
     int64_t row_stride, sys_stride0, sys_stride1;
     const int64_t *offsets; // device, ragged form only
     const int32_t *sys_list;// device, optional
+    const unsigned long long *count;  // device, optional: systems actually listed (<= nsys)
 };
 
 struct Coef {
@@ -34,6 +35,7 @@ struct TileShape {
     int S_log2 = 4;
     int P = 4;
     bool contig = false;    // stage loads/stores through LDS (row_stride == 1)
+    int kernel = 0;         // 0: generic fused kernel, 1: shared-operator kernel
     int threads() const { return (1 << S_log2) * P; }
 };
 
@@ -45,5 +47,12 @@ hipError_t launch_fused(int dtype, const SysMap &map, const Coef &coef, const Ti
 bool fused_supported(int dtype, const TileShape &shape);
 int fused_max_threads(int dtype, int M);
 size_t fused_lds_bytes(int dtype, const TileShape &shape);
+
+// shared-operator launchers (shared.hip)
+hipError_t launch_shared(int dtype, const SysMap &map, const Coef &coef, const TileShape &shape,
+                         const void *d, void *x, int *err_flag, hipStream_t stream);
+bool shared_supported(int dtype, const TileShape &shape);
+int shared_max_threads(int dtype, int M);
+size_t shared_lds_bytes(int dtype, const TileShape &shape);
 
 }  // namespace tdma

@@ -40,6 +40,25 @@ __device__ __forceinline__ bool bad_pivot(T v) {
     return !(av > T(0) && av < T(__builtin_huge_val()));
 }
 
+// Reciprocal from the hardware estimate plus Newton steps y <- y + y(1 - x y):
+// two steps in FP64, one in FP32, leaving about one ulp of error (the
+// compiler's IEEE division adds scaling and fix-up steps these well-scaled
+// pivots do not need).  A zero pivot gives a non-finite result and is flagged
+// separately.
+__device__ __forceinline__ double recip(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+
+__device__ __forceinline__ float recip(float x) {
+    const float y = __builtin_amdgcn_rcpf(x);
+    const float e = __builtin_fmaf(-x, y, 1.0f);
+    return __builtin_fmaf(y, e, y);
+}
+
 struct LaneSys {
     int64_t base;
     int64_t nrows;
@@ -47,9 +66,16 @@ struct LaneSys {
     bool valid;
 };
 
+// Systems covered by a launch: nsys, or the device-side count when given.
+__device__ __forceinline__ int64_t launch_nsys(const SysMap &m) {
+    if (!m.count) return m.nsys;
+    const int64_t c = (int64_t)*m.count;
+    return c < m.nsys ? c : m.nsys;
+}
+
 __device__ __forceinline__ LaneSys lane_system(const SysMap &m, int64_t k) {
     LaneSys r;
-    r.valid = k < m.nsys;
+    r.valid = k < launch_nsys(m);
     const int64_t kk = r.valid ? k : 0;
     const int64_t id = m.sys_list ? (int64_t)m.sys_list[kk] : kk;
     r.id = id;
@@ -64,6 +90,12 @@ __device__ __forceinline__ LaneSys lane_system(const SysMap &m, int64_t k) {
     }
     if (!r.valid) r.nrows = 0;
     return r;
+}
+
+// LDS bytes of Stage B for S systems x P partitions: three arrays (a, c, d)
+// of 2P rows per system plus one pad row (both PCR variants fit in this).
+__host__ __device__ constexpr size_t pcr_lds_bytes(int S, int P) {
+    return (size_t)3 * S * (2 * P + 1) * sizeof(double);
 }
 
 // Interface rows of one partition (unit diagonal): first row couples
@@ -81,11 +113,11 @@ __device__ __forceinline__ Iface reduce_partition(T (&av)[M], const T (&bv)[M], 
     static_assert(M >= 2, "a partition needs at least two rows");
     T piv = bv[0];
     bad |= bad_pivot(piv);
-    T ib = T(1) / piv;
+    T ib = recip(piv);
     const T a0 = av[0] * ib, c0 = cv[0] * ib, d0 = dv[0] * ib;
     piv = bv[1];
     bad |= bad_pivot(piv);
-    ib = T(1) / piv;
+    ib = recip(piv);
     av[1] *= ib;
     cv[1] *= ib;
     dv[1] *= ib;
@@ -93,7 +125,7 @@ __device__ __forceinline__ Iface reduce_partition(T (&av)[M], const T (&bv)[M], 
     for (int j = 2; j < M; ++j) {
         piv = bv[j] - av[j] * cv[j - 1];
         bad |= bad_pivot(piv);
-        ib = T(1) / piv;
+        ib = recip(piv);
         const T ra = av[j] * ib;
         dv[j] = (dv[j] - av[j] * dv[j - 1]) * ib;
         cv[j] = cv[j] * ib;
@@ -112,7 +144,7 @@ __device__ __forceinline__ Iface reduce_partition(T (&av)[M], const T (&bv)[M], 
     Iface f;
     const double den = 1.0 - (double)c0 * (double)at1;
     bad |= bad_pivot(den);
-    const double rho = 1.0 / den;
+    const double rho = recip(den);
     f.fa = rho * (double)a0;
     f.fc = -rho * (double)c0 * (double)ct1;
     f.fd = rho * ((double)d0 - (double)c0 * (double)dt1);
@@ -157,14 +189,14 @@ __device__ __forceinline__ void pcr_interface(double *lds, int S, int s, int p, 
         {
             const double beta = 1.0 - a0 * cm0 - c0 * ap0;
             bad |= bad_pivot(beta);
-            const double ib = 1.0 / beta;
+            const double ib = recip(beta);
             const double na = -a0 * am0, nc = -c0 * cp0, nd = d0 - a0 * dm0 - c0 * dp0;
             a0 = na * ib; c0 = nc * ib; d0 = nd * ib;
         }
         {
             const double beta = 1.0 - a1 * cm1 - c1 * ap1;
             bad |= bad_pivot(beta);
-            const double ib = 1.0 / beta;
+            const double ib = recip(beta);
             const double na = -a1 * am1, nc = -c1 * cp1, nd = d1 - a1 * dm1 - c1 * dp1;
             a1 = na * ib; c1 = nc * ib; d1 = nd * ib;
         }
@@ -177,6 +209,128 @@ __device__ __forceinline__ void pcr_interface(double *lds, int S, int s, int p, 
     }
     x_first = d0;
     x_last = d1;
+}
+
+// One PCR elimination step on a unit-diagonal row (a, c, d) with its
+// neighbours at distance h below (al, cl, dl) and above (au, cu, du); the
+// result is renormalised to unit diagonal.  Missing neighbours are zero rows.
+__device__ __forceinline__ void pcr_row(double &a, double &c, double &d, double al, double cl,
+                                        double dl, double au, double cu, double du, bool &bad) {
+    const double beta = 1.0 - a * cl - c * au;
+    bad |= bad_pivot(beta);
+    const double ib = recip(beta);
+    const double na = -a * al, nc = -c * cu, nd = d - a * dl - c * du;
+    a = na * ib;
+    c = nc * ib;
+    d = nd * ib;
+}
+
+// Stage B inside wavefronts: the tile's interface rows go through LDS once,
+// then P consecutive lanes (P a power of two <= 64, so one system never spans
+// two wavefronts) each hold two rows of one system and run the PCR steps with
+// cross-lane shuffles; the solution goes back through LDS.  Two barriers in
+// total instead of two per step.
+__device__ __forceinline__ void pcr_interface_wave(double *lds, int S, int s, int p, int P,
+                                                   int P_log2, Iface f, double &x_first,
+                                                   double &x_last, bool &bad) {
+    const int R2 = 2 * P;
+    const int pitch = R2 + 1;           // odd pitch: consecutive systems hit different banks
+    const int nsys_rows = S * pitch;
+    double *ra = lds, *rc = lds + nsys_rows, *rd = lds + 2 * nsys_rows;
+    __syncthreads();
+    {
+        const int q = s * pitch + 2 * p;
+        ra[q] = f.fa; rc[q] = f.fc; rd[q] = f.fd;
+        ra[q + 1] = f.la; rc[q + 1] = f.lc; rd[q + 1] = f.ld;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int s2 = t >> P_log2;
+    const int p2 = t & (P - 1);
+    const int q2 = s2 * pitch + 2 * p2;
+    double a0 = ra[q2], c0 = rc[q2], d0 = rd[q2];
+    double a1 = ra[q2 + 1], c1 = rc[q2 + 1], d1 = rd[q2 + 1];
+    const int lane = t & 63;
+    {
+        // h = 1: row 2p2 meets row 2p2-1 (lane-1) and its own row 2p2+1;
+        // row 2p2+1 meets its own row 2p2 and row 2p2+2 (lane+1).
+        const bool has_lo = p2 > 0, has_hi = p2 < P - 1;
+        const int lo = has_lo ? lane - 1 : lane, hi = has_hi ? lane + 1 : lane;
+        double am = __shfl(a1, lo), cm = __shfl(c1, lo), dm = __shfl(d1, lo);
+        double ap = __shfl(a0, hi), cp = __shfl(c0, hi), dp = __shfl(d0, hi);
+        if (!has_lo) { am = 0.0; cm = 0.0; dm = 0.0; }
+        if (!has_hi) { ap = 0.0; cp = 0.0; dp = 0.0; }
+        const double oa0 = a0, oc0 = c0, od0 = d0;
+        pcr_row(a0, c0, d0, am, cm, dm, a1, c1, d1, bad);
+        pcr_row(a1, c1, d1, oa0, oc0, od0, ap, cp, dp, bad);
+    }
+    for (int h = 2; h < R2; h <<= 1) {
+        const int dl = h >> 1;          // rows 2p2+e +- h live in lanes p2 +- h/2
+        const bool has_lo = p2 >= dl, has_hi = p2 + dl < P;
+        const int lo = has_lo ? lane - dl : lane, hi = has_hi ? lane + dl : lane;
+        double la0 = __shfl(a0, lo), lc0 = __shfl(c0, lo), ld0 = __shfl(d0, lo);
+        double la1 = __shfl(a1, lo), lc1 = __shfl(c1, lo), ld1 = __shfl(d1, lo);
+        double ua0 = __shfl(a0, hi), uc0 = __shfl(c0, hi), ud0 = __shfl(d0, hi);
+        double ua1 = __shfl(a1, hi), uc1 = __shfl(c1, hi), ud1 = __shfl(d1, hi);
+        if (!has_lo) { la0 = lc0 = ld0 = la1 = lc1 = ld1 = 0.0; }
+        if (!has_hi) { ua0 = uc0 = ud0 = ua1 = uc1 = ud1 = 0.0; }
+        pcr_row(a0, c0, d0, la0, lc0, ld0, ua0, uc0, ud0, bad);
+        pcr_row(a1, c1, d1, la1, lc1, ld1, ua1, uc1, ud1, bad);
+    }
+    // each lane overwrites only its own two slots: no barrier needed before
+    rd[q2] = d0;
+    rd[q2 + 1] = d1;
+    __syncthreads();
+    x_first = rd[s * pitch + 2 * p];
+    x_last = rd[s * pitch + 2 * p + 1];
+}
+
+template <typename T>
+struct Ident {
+    static constexpr T a = T(0), b = T(1), c = T(0), d = T(0);
+};
+
+// Per-tile system table for the LDS-staged (contiguous-row) path.
+struct TileSysLds {
+    int64_t base;
+    int64_t nrows;
+};
+
+// Cooperative coalesced copy of one tile array (S systems x R rows, rows
+// contiguous in memory) into LDS, then each lane picks its M rows.
+template <typename T, int M>
+__device__ __forceinline__ void stage_in(T *stg, const TileSysLds *tsys, const T *src, T ident,
+                                         int S, int R, int pitch, float invR, int s, int r0,
+                                         T (&dst)[M]) {
+    const int nthr = blockDim.x;
+    __syncthreads();
+    for (int e = threadIdx.x; e < S * R; e += nthr) {
+        int se = (int)(((float)e + 0.5f) * invR);
+        int re = e - se * R;
+        if (re < 0) { --se; re += R; } else if (re >= R) { ++se; re -= R; }
+        T v = ident;
+        if (re < tsys[se].nrows) v = src[tsys[se].base + re];
+        stg[se * pitch + re] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < M; ++j) dst[j] = stg[s * pitch + r0 + j];
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void stage_out(T *stg, const TileSysLds *tsys, T *dst_g, int S, int R,
+                                          int pitch, float invR, int s, int r0, const T (&src)[M]) {
+    const int nthr = blockDim.x;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < M; ++j) stg[s * pitch + r0 + j] = src[j];
+    __syncthreads();
+    for (int e = threadIdx.x; e < S * R; e += nthr) {
+        int se = (int)(((float)e + 0.5f) * invR);
+        int re = e - se * R;
+        if (re < 0) { --se; re += R; } else if (re >= R) { ++se; re -= R; }
+        if (re < tsys[se].nrows) dst_g[tsys[se].base + re] = stg[se * pitch + re];
+    }
 }
 
 }  // namespace dev

@@ -94,7 +94,7 @@ def test_tiled_validation(tdma):
     C = tdma._Coeffs(0, 3, 4, 5, None)
 
     def tiled(M, S, P):
-        t = tdma._Tile(M, S, P)
+        t = tdma._Tile(M, S, P, 0)
         return lib.tdma_solve_batched_tiled(ctypes.byref(L), ctypes.byref(C), 0, ctypes.c_void_p(1),
                                             ctypes.c_void_p(2), ctypes.byref(t), None)
     assert tiled(8, 3, 8) == tdma.EINVAL      # S not a power of two

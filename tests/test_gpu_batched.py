@@ -134,3 +134,31 @@ def test_singular_flagged():
         tdma.check()
     assert ei.value.status == tdma.ESINGULAR
     tdma.check()   # flag was cleared
+
+
+SHAPES_SHARED = [dict(M=16, S=16, P=16, kernel=1), dict(M=8, S=16, P=32, kernel=1),
+                 dict(M=32, S=16, P=8, kernel=1), dict(M=8, S=8, P=64, kernel=1),
+                 dict(M=16, S=1, P=16, kernel=1), dict(M=16, S=16, P=16, kernel=0)]
+
+
+@pytest.mark.parametrize("shape", SHAPES_SHARED,
+                         ids=lambda s: "k%d_M%d_S%d_P%d" % (s["kernel"], s["M"], s["S"], s["P"]))
+def test_shared_operator_shapes(shape):
+    """Shared-operator kernel (tables in LDS) and the generic kernel on the same
+    ADI problem; n = 200 leaves identity padding rows in the last partition."""
+    err, _, _ = _run(configs.adi(40, 12, 200), shape=shape)
+    assert err.max() <= parity.TOL_F64, err.max()
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, parity.TOL_F64), (np.float32, parity.TOL_F32)])
+def test_adi_sweeps_all_directions(dtype, tol):
+    """x (contiguous rows, LDS-staged), y and z sweeps of one grid, shared operators."""
+    px, py, pz = configs.sweeps(96, 40, 72)
+    for p in (px, py, pz):
+        err, _, _ = _run(p, dtype)
+        assert err.max() <= tol, (p.name, err.max())
+
+
+def test_shared_fp32_padding():
+    err, _, _ = _run(configs.adi(33, 7, 100), np.float32)
+    assert err.max() <= parity.TOL_F32, err.max()

@@ -1,0 +1,86 @@
+"""GPU parity of the precision form (tdma_solve_refined): FP32 sweeps, FP64
+residual and interface solve, FP64 fallback for systems that miss the tolerance.
+The refined result must match the FP64 oracle within 1e-12 (relative, per
+system); for the ill-conditioned low Poisson modes the long-double oracle is
+the reference (even a correct FP64 solve sits near 1e-12 there)."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import parity
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _refined(p, **opts):
+    import paper_2509_03933_amd as tdma
+    a, b, c, d = parity.host_problem(p)
+    coeffs = parity.device_coeffs(p, a, b, c, torch.float64)
+    (td,) = parity.to_device([d], torch.float64)
+    tx = torch.full_like(td, float("nan"))
+    rep = tdma.solve_refined(p.layout, coeffs, td, tx, **opts)
+    tdma.check()
+    return tx.cpu().numpy(), rep, (a, b, c, d)
+
+
+@pytest.mark.parametrize("make", [lambda: configs.adi(48, 20, 256),
+                                  lambda: configs.partitioned(20, 12, 300),
+                                  lambda: configs.plain(nsys=40, n=256),
+                                  lambda: configs.sweeps(96, 24, 40)[0]],
+                         ids=["adi_shared", "perrow_strided", "perrow_contig", "shared_contig"])
+def test_refined_well_conditioned(make):
+    p = make()
+    x, rep, (a, b, c, d) = _refined(p)
+    ref = parity.oracle_solution(p, a, b, c, d)
+    err = parity.per_system_error(p.layout, x, ref)
+    assert err.max() <= parity.TOL_REFINED, err.max()
+    assert rep["iterations"] == 3
+    assert rep["not_converged"] == 0 and rep["fallback_systems"] == 0
+    assert rep["max_rel_correction"] <= 1e-15
+
+
+def test_refined_poisson_modes():
+    """Shared Poisson operator + per-mode shift: low modes are ill-conditioned;
+    every mode must end within 1e-12 of the FP64 oracle or of the long-double one."""
+    p = configs.poisson(32, 16, 512)
+    x, rep, (a, b, c, d) = _refined(p)
+    ref = parity.oracle_solution(p, a, b, c, d)
+    ref_ld = parity.oracle_solution(p, a, b, c, d, precision=oracle.LONG_DOUBLE)
+    e64 = parity.per_system_error(p.layout, x, ref)
+    eld = parity.per_system_error(p.layout, x, ref_ld)
+    assert np.minimum(e64, eld).max() <= parity.TOL_REFINED, (e64.max(), eld.max())
+    assert rep["fallback_systems"] == rep["not_converged"]
+
+
+def test_no_refinement_needs_fallback():
+    """max_iters = 0 leaves an FP32-accurate answer; every system misses 1e-15
+    and is re-solved in FP64, so the result still meets the FP64 bar."""
+    p = configs.adi(32, 8, 128)
+    x, rep, (a, b, c, d) = _refined(p, max_iters=0)
+    ref = parity.oracle_solution(p, a, b, c, d)
+    assert parity.per_system_error(p.layout, x, ref).max() <= parity.TOL_F64
+    assert rep["not_converged"] == p.layout.nsys == rep["fallback_systems"]
+
+
+def test_no_fallback_reports_enoconv():
+    import paper_2509_03933_amd as tdma
+    p = configs.adi(16, 4, 64)
+    with pytest.raises(tdma.TdmaError) as ei:
+        _refined(p, max_iters=0, fallback=0)
+    assert ei.value.status == tdma.ENOCONV
+
+
+def test_plain_fp32_accuracy_of_first_solve():
+    """A single FP32 solve without fallback is within the plain-FP32 bar."""
+    import paper_2509_03933_amd as tdma
+    p = configs.adi(32, 8, 256)
+    a, b, c, d = parity.host_problem(p)
+    coeffs = parity.device_coeffs(p, a, b, c, torch.float64)
+    (td,) = parity.to_device([d], torch.float64)
+    tx = torch.empty_like(td)
+    tdma.solve_refined(p.layout, coeffs, td, tx, max_iters=0, fallback=0, report=False)
+    torch.cuda.synchronize()
+    ref = parity.oracle_solution(p, a, b, c, d)
+    assert parity.per_system_error(p.layout, tx.cpu().numpy(), ref).max() <= parity.TOL_F32
