@@ -461,6 +461,8 @@ int tdma_check(void *stream) {
     if (flag[0]) {
         e = hipMemset(ctx->d_err, 0, 4 * sizeof(int));
         if (e != hipSuccess) return hip_fail(e, "clear error flag");
+        if (flag[0] & 2)
+            return fail(TDMA_EHIP, "a batching-form dependency wait hit its bound (results invalid)");
         return fail(TDMA_ESINGULAR, "a kernel met a zero or non-finite pivot");
     }
     return TDMA_OK;
