@@ -1,16 +1,27 @@
 """Benchmark: G unknowns/s and % of HBM roofline of the batched tridiagonal solve
 on one MI355X, beside the CPU oracle.
 
-Default workload: the ADI viscous z-sweep of a 256^3 grid (65,536 strided
-z-lines of n = 256, one shared tanh-grid operator, smooth RHS + noise), FP64,
-through tdma_solve_batched (fused on-chip Stage A/B/C).  One step = one full
-solve of the workload.  Inputs are resident in HBM before timing; the step
-cycles over several input/output buffer sets (>= 1 GiB in total) so the
-256 MB Infinity Cache cannot serve a step from the previous one.
+Default workload (``--workload adi``): the ADI viscous z-sweep of a 256^3 grid
+(65,536 strided z-lines of n = 256, one shared tanh-grid operator, smooth RHS
++ noise), FP64, through tdma_solve_batched (fused on-chip Stage A/B/C).  One
+step = one full solve of the workload.  The same workload is also timed
+through tdma_solve_refined (FP32 sweeps + FP64 refinement), reported beside
+the FP64 value.  Inputs are resident in HBM before timing; the steps cycle
+over several input/output buffer sets (>= 1 GiB in total) so the 256 MB
+Infinity Cache cannot serve a step from the previous one.
+
+Other workloads (measurement of the remaining configurations):
+  partitioned  1024^3 per-row z-lines, tdma_solve_partitioned (P = 8, 4 streams)
+  poisson      1024^2 FFT modes x n = 1024, shared operator + shift, FP64 fused
+               and FP32+refine, plus the pinned (0,0) mode
+  sweeps       768x512x1536 x->y->z ADI sweeps + 10,000 ragged systems in one
+               hipGraph-captured persistent launch
+  plain        64 contiguous systems of n = 256
 
 Prints ONE JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -23,15 +34,19 @@ if ROOT not in sys.path:
 
 METRIC = "G unknowns/s & % HBM peak: FP32+refine vs FP64 at ≤1e-12 rel err, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+CSRC = "paper_2509_03933_amd/csrc/"
+KERNEL_SOURCES = {
+    "k_shared": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
+    "k_fused": [CSRC + "fused.hip", CSRC + "fused_tile.hip.h", CSRC + "tile.hip.h"],
+    "k_refine": [CSRC + "refine.hip", CSRC + "tile.hip.h"],
+    "k_stage_a": [CSRC + "partitioned.hip", CSRC + "tile.hip.h"],
+    "k_persist": [CSRC + "persist.hip", CSRC + "fused_tile.hip.h", CSRC + "tile.hip.h"],
+}
 
 
-KERNEL_SOURCES = ["paper_2509_03933_amd/csrc/fused.hip", "paper_2509_03933_amd/csrc/tile.hip.h"]
-
-
-def profiled_traffic(profile_name, sources):
+def profiled_traffic(profile_name, kernel):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or None
     when the kernel sources changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", profile_name + ".md")
     if not os.path.exists(path):
         return None
@@ -41,7 +56,7 @@ def profiled_traffic(profile_name, sources):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for f in sources:
+    for f in KERNEL_SOURCES[kernel]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
         return None
@@ -56,9 +71,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="adi", choices=["adi"])
-    ap.add_argument("--grid", default="256,256,256")
+    ap.add_argument("--workload", default="adi",
+                    choices=["adi", "partitioned", "poisson", "sweeps", "plain"])
+    ap.add_argument("--grid", default=None, help="override the grid, e.g. 256,256,256")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--batch", type=int, default=0, help="partitioned: systems per batch")
+    ap.add_argument("--no-refine", action="store_true", help="skip the FP32+refine leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
@@ -78,6 +96,281 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "launches": 5}))
 
 
+def timed(step, steps, warmup, stream):
+    """Run `step(i)` warmup times, then time `steps` calls with HIP events on
+    the stream the library launches on.  Returns ms per step."""
+    import torch
+    import paper_2509_03933_amd as tdma
+    for i in range(warmup):
+        step(i)
+    tdma.check(stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        step(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    tdma.check(stream)
+    return e0.elapsed_time(e1) / steps
+
+
+def sampled_error(p, x_host, systems, dtype="f64", ld_fallback=False):
+    import numpy as np
+    import oracle
+    from workloads import configs
+    worst = 0.0
+    for s in systems:
+        a, b, c, d = configs.system_inputs(p, int(s))
+        if dtype == "f32":
+            a, b, c, d = [v.astype(np.float32).astype(np.float64) for v in (a, b, c, d)]
+        ref = oracle.thomas(a, b, c, d)
+        got = x_host[p.layout.sys_rows(int(s))]
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        if ld_fallback and err > 1e-12:
+            ref = oracle.thomas(a, b, c, d, oracle.LONG_DOUBLE)
+            err = min(err, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+        worst = max(worst, err)
+    return worst
+
+
+def sample_systems(nsys, k=254, seed=7):
+    import numpy as np
+    rs = np.random.default_rng(seed)
+    return np.unique(np.concatenate([[0, nsys - 1], rs.integers(0, nsys, k)]))
+
+
+def roofline(bytes_per_launch, ms, kernel, profile):
+    achieved = bytes_per_launch / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(profile, kernel),
+            "kernel": kernel, "algorithmic_bytes_per_launch": int(bytes_per_launch)}
+
+
+def rotating_sets(d0, unknown_bytes):
+    import torch
+    nsets = max(2, math.ceil((1 << 30) / unknown_bytes))
+    ds = [d0] + [d0.clone() for _ in range(nsets - 1)]
+    xs = [torch.empty_like(d0) for _ in range(nsets)]
+    return ds, xs
+
+
+# ---------------------------------------------------------------------------
+
+def bench_adi(args):
+    import torch
+    import paper_2509_03933_amd as tdma
+    from workloads import configs, device
+    nx, ny, nz = (int(v) for v in (args.grid or "256,256,256").split(","))
+    p = configs.adi(nx, ny, nz)
+    tt = torch.float64 if args.dtype == "f64" else torch.float32
+    esz = 8 if args.dtype == "f64" else 4
+    d0, coeffs = device.device_inputs(p, dtype=tt)
+    lay = p.layout
+    unknowns = lay.unknowns()
+    bytes_step = 2 * esz * unknowns + 3 * esz * lay.n
+    ds, xs = rotating_sets(d0, 2 * esz * unknowns)
+    st = torch.cuda.current_stream()
+    n = len(ds)
+    ms = timed(lambda i: tdma.solve_batched(lay, coeffs, ds[i % n], xs[i % n], stream=st),
+               args.steps, args.warmup, st)
+    x_last = xs[(args.steps - 1) % n].double().cpu().numpy()
+    samp = sample_systems(lay.nsys)
+    err = sampled_error(p, x_last, samp, args.dtype)
+    kernel = "k_shared"
+    out = {
+        "value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
+        "dtype": args.dtype,
+        "config": {"workload": f"adi_viscous_zsweep_{nx}x{ny}x{nz}", "systems": lay.nsys, "n": lay.n,
+                   "coefficients": "shared tanh-grid operator", "entry_point": "tdma_solve_batched",
+                   "buffer_sets": n},
+        "max_rel_err_vs_oracle": err,
+        "roofline": roofline(bytes_step, ms, kernel, f"{kernel}_adi{nx}x{ny}x{nz}_{args.dtype}"),
+    }
+    if args.dtype == "f64" and not args.no_refine:
+        msr = timed(lambda i: tdma.solve_refined(lay, coeffs, ds[i % n], xs[i % n], report=False,
+                                                 stream=st), args.steps, args.warmup, st)
+        rep = tdma.solve_refined(lay, coeffs, ds[0], xs[0], report=True, stream=st)
+        xr = xs[0].cpu().numpy()
+        out["fp32_refine"] = {
+            "value": round(unknowns / (msr * 1e-3) / 1e9, 3), "ms_per_step": round(msr, 6),
+            "max_rel_err_vs_oracle": sampled_error(p, xr, samp), "report": rep,
+            "entry_point": "tdma_solve_refined (3 steps, tol 1e-15, FP64 fallback)",
+            "roofline": roofline(bytes_step, msr, "k_refine", f"k_refine_adi{nx}x{ny}x{nz}_f64"),
+            "faster_than_fp64": msr < ms,
+        }
+    return p, out
+
+
+def bench_partitioned(args):
+    import torch
+    import paper_2509_03933_amd as tdma
+    from workloads import configs, device
+    nx, ny, nz = (int(v) for v in (args.grid or "1024,1024,1024").split(","))
+    p = configs.partitioned(nx, ny, nz)
+    d, coeffs = device.device_inputs(p)
+    x = torch.empty_like(d)
+    lay = p.layout
+    st = torch.cuda.current_stream()
+    steps = max(1, min(args.steps, 10))
+    ms = timed(lambda i: tdma.solve_partitioned(lay, coeffs, d, x, partitions=8, batch=args.batch,
+                                                nstreams=4, stream=st), steps, min(args.warmup, 2), st)
+    unknowns = lay.unknowns()
+    err = sampled_error(p, x.cpu().numpy(), sample_systems(lay.nsys, 62))
+    return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
+               "dtype": "f64", "steps": steps,
+               "config": {"workload": f"partitioned_zlines_{nx}x{ny}x{nz}", "systems": lay.nsys,
+                          "n": lay.n, "partitions": 8, "streams": 4, "batch": args.batch or "default",
+                          "entry_point": "tdma_solve_partitioned"},
+               "max_rel_err_vs_oracle": err,
+               "roofline": roofline(40 * unknowns, ms, "k_stage_a", f"partitioned{nx}x{ny}x{nz}_f64")}
+
+
+def bench_poisson(args):
+    import torch
+    import paper_2509_03933_amd as tdma
+    from workloads import configs, device
+    nx, ny, nz = (int(v) for v in (args.grid or "1024,1024,1024").split(","))
+    p = configs.poisson(nx, ny, nz)
+    pin = configs.poisson_pinned(p)
+    d, coeffs = device.device_inputs(p)
+    pco = dict(mode=1, a=torch.from_numpy(pin.a).cuda(), b=torch.from_numpy(pin.b).cuda(),
+               c=torch.from_numpy(pin.c).cuda())
+    x = torch.empty_like(d)
+    lay = p.layout
+    st = torch.cuda.current_stream()
+    steps = max(1, min(args.steps, 10))
+
+    def fp64(i):
+        tdma.solve_batched(lay, coeffs, d, x, stream=st)
+        tdma.solve_batched(pin.layout, pco, d, x, stream=st)
+
+    def refined(i):
+        tdma.solve_refined(lay, coeffs, d, x, report=False, stream=st)
+        tdma.solve_refined(pin.layout, pco, d, x, report=False, stream=st)
+
+    unknowns = lay.unknowns()
+    low = [(kx % nx) + nx * (ky % ny) for kx in range(-3, 4) for ky in range(-3, 4) if (kx, ky) != (0, 0)]
+    samp = sorted(set(sample_systems(lay.nsys, 30).tolist() + low) - {0})
+    ms = timed(fp64, steps, 1, st)
+    e64 = sampled_error(p, x.cpu().numpy(), samp, ld_fallback=True)
+    msr = timed(refined, steps, 1, st)
+    rep = tdma.solve_refined(lay, coeffs, d, x, report=True, stream=st)
+    tdma.solve_refined(pin.layout, pco, d, x, stream=st)
+    er = sampled_error(p, x.cpu().numpy(), samp, ld_fallback=True)
+    return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
+               "dtype": "f64", "steps": steps,
+               "config": {"workload": f"fft_poisson_lines_{nx}x{ny}x{nz}", "systems": lay.nsys,
+                          "n": lay.n, "entry_point": "tdma_solve_batched (+ pinned mode)"},
+               "max_rel_err_vs_oracle": e64,
+               "roofline": roofline(16 * unknowns, ms, "k_fused", f"k_fused_poisson{nx}x{ny}x{nz}_f64"),
+               "fp32_refine": {"value": round(unknowns / (msr * 1e-3) / 1e9, 3),
+                               "ms_per_step": round(msr, 6), "max_rel_err_vs_oracle": er,
+                               "report": rep, "faster_than_fp64": msr < ms}}
+
+
+def bench_sweeps(args):
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2509_03933_amd as tdma
+    from workloads import configs, device
+    nx, ny, nz = (int(v) for v in (args.grid or "768,512,1536").split(","))
+    px, py, pz = configs.sweeps(nx, ny, nz)
+    rg = configs.ragged()
+    R, _ = device.device_inputs(px)
+    u1, u2, u3 = (torch.empty_like(R) for _ in range(3))
+    ra, rb, rc, rd = configs.full_arrays(rg)
+    dev = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    td = dev(rd)
+    tx = torch.empty_like(td)
+    sh = lambda p: dict(mode=1, a=dev(p.a), b=dev(p.b), c=dev(p.c))
+    g = tdma.graph_create([dict(layout=px.layout, coeffs=sh(px), d=R, x=u1),
+                           dict(layout=py.layout, coeffs=sh(py), d=u1, x=u2, after=0),
+                           dict(layout=pz.layout, coeffs=sh(pz), d=u2, x=u3, after=1),
+                           dict(layout=rg.layout, coeffs=dict(mode=0, a=dev(ra), b=dev(rb), c=dev(rc)),
+                                d=td, x=tx)])
+    st = torch.cuda.current_stream()
+    steps = max(1, min(args.steps, 20))
+    ms = timed(lambda i: g.launch(st), steps, min(args.warmup, 3), st)
+    unknowns = 3 * px.layout.unknowns() + rg.layout.unknowns()
+    bytes_step = 16 * 3 * px.layout.unknowns() + 40 * rg.layout.unknowns()
+    worst = 0.0
+    for p, din, xout in ((px, R, u1), (py, u1, u2), (pz, u2, u3)):
+        for s in sample_systems(p.layout.nsys, 16):
+            rows = torch.from_numpy(p.layout.sys_rows(int(s))).cuda()
+            ref = oracle.thomas(p.a, p.b, p.c, din[rows].cpu().numpy())
+            got = xout[rows].cpu().numpy()
+            worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+    g.destroy()
+    return px, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
+                "dtype": "f64", "steps": steps,
+                "config": {"workload": f"adi_sweeps_{nx}x{ny}x{nz}_plus_10000_ragged",
+                           "entry_point": "tdma_graph_launch"},
+                "max_rel_err_vs_oracle": worst,
+                "roofline": roofline(bytes_step, ms, "k_persist", f"k_persist_sweeps{nx}x{ny}x{nz}_f64")}
+
+
+def bench_plain(args):
+    import torch
+    import paper_2509_03933_amd as tdma
+    from workloads import configs, device
+    p = configs.plain()
+    d, coeffs = device.device_inputs(p)
+    x = torch.empty_like(d)
+    st = torch.cuda.current_stream()
+    ms = timed(lambda i: tdma.solve_batched(p.layout, coeffs, d, x, stream=st), args.steps,
+               args.warmup, st)
+    unknowns = p.layout.unknowns()
+    err = sampled_error(p, x.cpu().numpy(), range(p.layout.nsys))
+    return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
+               "dtype": "f64", "config": {"workload": "plain_64x256_contiguous",
+                                          "entry_point": "tdma_solve_batched"},
+               "max_rel_err_vs_oracle": err,
+               "roofline": roofline(40 * unknowns, ms, "k_fused", "k_fused_plain64x256_f64")}
+
+
+def cpu_baseline(p, target_s, max_systems=None):
+    """The oracle (plain C FP64 Thomas, one thread) on the same workload's host
+    inputs: whole passes when they are small, else a bounded slice of the
+    systems, repeated until about target_s of CPU time."""
+    import numpy as np
+    import oracle
+    from workloads import configs
+    lay = p.layout
+    if lay.extent() <= (1 << 25):
+        a, b, c, d = configs.full_arrays(p)
+        x = None
+        t0 = time.perf_counter()
+        passes = 0
+        while True:
+            x = oracle.solve_batch(lay, p.mode, a, b, c, d, x=x)
+            passes += 1
+            el = time.perf_counter() - t0
+            if el >= target_s or passes >= 1000:
+                break
+        unknowns = lay.unknowns() * passes
+        sample = f"{passes} full pass(es) of the workload ({lay.unknowns()} unknowns each)"
+    else:
+        k = max_systems or 2048
+        systems = [configs.system_inputs(p, int(s)) for s in range(k)]
+        t0 = time.perf_counter()
+        passes = 0
+        while True:
+            for a, b, c, d in systems:
+                oracle.thomas(a, b, c, d)
+            passes += 1
+            el = time.perf_counter() - t0
+            if el >= target_s or passes >= 1000:
+                break
+        unknowns = k * lay.n * passes
+        sample = f"the first {k} systems of the workload, {passes} pass(es)"
+    return {"value": round(unknowns / el / 1e9, 4), "unit": "G unknowns/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{sample}, {el:.1f} s wall, single-threaded C Thomas (FP64)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -85,111 +378,21 @@ def main():
               "(the systems shard across GPUs with no communication; see DESIGN.md).",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
-    import torch
-
     if args.copy_calibration:
         copy_calibration()
         return
-
-    import paper_2509_03933_amd as tdma
-    from workloads import configs, device
-
-    nx, ny, nz = (int(v) for v in args.grid.split(","))
-    p = configs.adi(nx, ny, nz)
-    tt = torch.float64 if args.dtype == "f64" else torch.float32
-    esz = 8 if args.dtype == "f64" else 4
-    d0, coeffs = device.device_inputs(p, dtype=tt)
-    lay = p.layout
-    unknowns = lay.unknowns()
-    bytes_per_step = 2 * esz * unknowns + 3 * esz * lay.n     # read d, write x, shared tables
-    nsets = max(2, math.ceil((1 << 30) / (2 * esz * unknowns)))
-    ds = [d0] + [d0.clone() for _ in range(nsets - 1)]
-    xs = [torch.empty_like(d0) for _ in range(nsets)]
-    stream = torch.cuda.current_stream()
-
-    def step(i):
-        tdma.solve_batched(lay, coeffs, ds[i % nsets], xs[i % nsets], stream=stream)
-
-    for i in range(args.warmup):
-        step(i)
-    tdma.check(stream)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for i in range(args.steps):
-        step(i)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    tdma.check(stream)
-    total_ms = e0.elapsed_time(e1)
-    ms_step = total_ms / args.steps
-    value = unknowns / (ms_step * 1e-3) / 1e9
-    achieved = bytes_per_step / (ms_step * 1e-3) / 1e9
-
-    # parity spot check of the timed output against the oracle (sampled systems)
-    import oracle
-    rs = np.random.default_rng(7)
-    sample = np.unique(np.concatenate([[0, lay.nsys - 1], rs.integers(0, lay.nsys, 254)]))
-    x_last = xs[(args.steps - 1) % nsets].double().cpu().numpy()
-    worst = 0.0
-    for s in sample:
-        a, b, c, d = configs.system_inputs(p, int(s))
-        if args.dtype == "f32":
-            a, b, c, d = [v.astype(np.float32).astype(np.float64) for v in (a, b, c, d)]
-        ref = oracle.thomas(a, b, c, d)
-        got = x_last[lay.sys_rows(int(s))]
-        worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
-
-    out = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "G unknowns/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 6),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": args.dtype,
-        "data": "synthetic (seeded counter-based generator, generated in HBM)",
-        "config": {"workload": f"adi_viscous_zsweep_{nx}x{ny}x{nz}", "systems": lay.nsys,
-                   "n": lay.n, "coefficients": "shared tanh-grid operator",
-                   "entry_point": "tdma_solve_batched", "buffer_sets": nsets},
-        "max_rel_err_vs_oracle": worst,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(f"k_fused_adi{nx}x{ny}x{nz}_{args.dtype}", KERNEL_SOURCES),
-                     "kernel": "k_fused", "algorithmic_bytes_per_launch": bytes_per_step},
-    }
-
+    fn = {"adi": bench_adi, "partitioned": bench_partitioned, "poisson": bench_poisson,
+          "sweeps": bench_sweeps, "plain": bench_plain}[args.workload]
+    p, res = fn(args)
+    out = {"metric": METRIC, "value": res.pop("value"), "unit": "G unknowns/s", "n_gpus": 1,
+           "steps": res.pop("steps", args.steps), "warmup": args.warmup,
+           "ms_per_step": res.pop("ms_per_step"), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": res.pop("dtype"),
+           "data": "synthetic (seeded counter-based generator, generated in HBM)"}
+    out.update(res)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out))
-
-
-def cpu_baseline(p, target_s):
-    """The oracle (plain C FP64 Thomas, one thread) on the same workload's host
-    inputs, repeated over whole passes until about target_s of CPU time."""
-    import oracle
-    from workloads import configs
-    a, b, c, d = configs.full_arrays(p)
-    x = None
-    t0 = time.perf_counter()
-    passes = 0
-    while True:
-        x = oracle.solve_batch(p.layout, p.mode, a, b, c, d, x=x)
-        passes += 1
-        el = time.perf_counter() - t0
-        if el >= target_s or passes >= 1000:
-            break
-    unknowns = p.layout.unknowns() * passes
-    return {"value": round(unknowns / el / 1e9, 4), "unit": "G unknowns/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{passes} full pass(es) of the same workload ({p.layout.unknowns()} unknowns "
-                      f"each), {el:.1f} s wall, single-threaded C Thomas (FP64)"}
 
 
 if __name__ == "__main__":

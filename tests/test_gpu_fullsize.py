@@ -1,0 +1,151 @@
+"""Parity at the workloads' full sizes, in the launch configurations the
+benchmark uses.  Inputs are generated in HBM by the device generator; the
+oracle recomputes a sample of systems one by one from the host generator
+(first, last, seeded random picks, and for the Poisson lines every mode with
+|kx|, |ky| <= 4 plus the pinned mode).  Every output is also checked to be
+finite on the device."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import parity
+from workloads import configs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+torch = pytest.importorskip("torch")
+
+
+def _sample(nsys, k=96, seed=3):
+    rs = np.random.default_rng(seed)
+    return np.unique(np.concatenate([[0, 1, nsys - 1], rs.integers(0, nsys, k)]))
+
+
+def _check_sampled(p, x_dev, systems, tol, ld_ok=False):
+    x = x_dev.double()
+    worst = 0.0
+    for s in systems:
+        a, b, c, d = configs.system_inputs(p, int(s))
+        ref = oracle.thomas(a, b, c, d)
+        rows = torch.from_numpy(p.layout.sys_rows(int(s))).cuda()
+        got = x[rows].cpu().numpy()
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        if ld_ok and err > tol:
+            ref = oracle.thomas(a, b, c, d, oracle.LONG_DOUBLE)
+            err = min(err, np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        worst = max(worst, err)
+    assert worst <= tol, worst
+    return worst
+
+
+def test_adi_256_cubed_fp32():
+    import paper_2509_03933_amd as tdma
+    from workloads import device
+    p = configs.adi(256, 256, 256)
+    d, co = device.device_inputs(p, dtype=torch.float32)
+    x = torch.empty_like(d)
+    tdma.solve_batched(p.layout, co, d, x)
+    tdma.check()
+    assert torch.isfinite(x).all()
+    # the FP32 path solves the FP32-rounded problem
+    worst = 0.0
+    for s in _sample(p.layout.nsys, 32):
+        a, b, c, dd = configs.system_inputs(p, int(s))
+        a, b, c, dd = (v.astype(np.float32).astype(np.float64) for v in (a, b, c, dd))
+        ref = oracle.thomas(a, b, c, dd)
+        got = x.double()[torch.from_numpy(p.layout.sys_rows(int(s))).cuda()].cpu().numpy()
+        worst = max(worst, np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    assert worst <= parity.TOL_F32
+
+
+def test_partitioned_1024_cubed():
+    """1,048,576 z-systems of n = 1024, P = 8, 4 streams, default batch."""
+    import paper_2509_03933_amd as tdma
+    from workloads import device
+    p = configs.partitioned(1024, 1024, 1024)
+    d, co = device.device_inputs(p)
+    x = torch.empty_like(d)
+    tdma.solve_partitioned(p.layout, co, d, x, partitions=8, nstreams=4)
+    tdma.check()
+    assert torch.isfinite(x).all()
+    _check_sampled(p, x, _sample(p.layout.nsys), parity.TOL_F64)
+    del d, co, x
+    torch.cuda.empty_cache()
+
+
+def _poisson_sample(p):
+    nx, ny, _ = p.grid
+    low = [(kx % nx) + nx * (ky % ny) for kx in range(-4, 5) for ky in range(-4, 5)]
+    return np.unique(np.concatenate([_sample(p.layout.nsys, 32), low]))
+
+
+def test_poisson_1024_cubed_fp64_and_refined():
+    """FFT-Poisson lines: fused FP64 and the refined form; low modes are
+    ill-conditioned, so a mode also passes when within the bar of the
+    long-double oracle.  The pinned (0,0) mode is solved as its own system."""
+    import paper_2509_03933_amd as tdma
+    from workloads import device
+    p = configs.poisson(1024, 1024, 1024)
+    d, co = device.device_inputs(p)
+    pin = configs.poisson_pinned(p)
+    pin_co = dict(mode=1, a=torch.from_numpy(pin.a).cuda(), b=torch.from_numpy(pin.b).cuda(),
+                  c=torch.from_numpy(pin.c).cuda())
+    x = torch.empty_like(d)
+    tdma.solve_batched(p.layout, co, d, x)
+    tdma.solve_batched(pin.layout, pin_co, d, x)
+    tdma.check()
+    assert torch.isfinite(x).all()
+    samp = _poisson_sample(p)
+    _check_sampled(p, x, samp[samp != 0], parity.TOL_F64, ld_ok=True)
+    _check_sampled(pin, x, [0], parity.TOL_F64, ld_ok=True)
+    x.fill_(float("nan"))
+    rep = tdma.solve_refined(p.layout, co, d, x)
+    tdma.solve_refined(pin.layout, pin_co, d, x)
+    tdma.check()
+    assert torch.isfinite(x).all()
+    print("refine report", rep)
+    _check_sampled(p, x, samp[samp != 0], parity.TOL_REFINED, ld_ok=True)
+    _check_sampled(pin, x, [0], parity.TOL_REFINED, ld_ok=True)
+    del d, co, x
+    torch.cuda.empty_cache()
+
+
+def test_sweeps_and_ragged_graph_full_size():
+    """768x512x1536 x->y->z sweeps chained in one persistent launch beside the
+    10,000-system ragged batch; sampled lines of each sweep are checked
+    against the oracle applied to the GPU's own input to that sweep."""
+    import paper_2509_03933_amd as tdma
+    from workloads import device
+    px, py, pz = configs.sweeps()
+    R, _ = device.device_inputs(px)
+    u1, u2, u3 = (torch.empty_like(R) for _ in range(3))
+    rg = configs.ragged()
+    ra, rb, rc, rd = configs.full_arrays(rg)
+    dev = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    td, tx = dev(rd), torch.empty_like(dev(rd))
+    sh = lambda p: dict(mode=1, a=dev(p.a), b=dev(p.b), c=dev(p.c))
+    g = tdma.graph_create([dict(layout=px.layout, coeffs=sh(px), d=R, x=u1),
+                           dict(layout=py.layout, coeffs=sh(py), d=u1, x=u2, after=0),
+                           dict(layout=pz.layout, coeffs=sh(pz), d=u2, x=u3, after=1),
+                           dict(layout=rg.layout, coeffs=dict(mode=0, a=dev(ra), b=dev(rb), c=dev(rc)),
+                                d=td, x=tx)])
+    g.launch()
+    tdma.check()
+    g.destroy()
+    for t in (u1, u2, u3, tx):
+        assert torch.isfinite(t).all()
+    for p, din, xout in ((px, R, u1), (py, u1, u2), (pz, u2, u3)):
+        dh = din
+        worst = 0.0
+        for s in _sample(p.layout.nsys, 24):
+            rows = torch.from_numpy(p.layout.sys_rows(int(s))).cuda()
+            ref = oracle.thomas(p.a, p.b, p.c, dh[rows].cpu().numpy())
+            got = xout[rows].cpu().numpy()
+            worst = max(worst, np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        assert worst <= parity.TOL_F64, (p.name, worst)
+    lens = np.diff(rg.layout.offsets)
+    pick = np.unique(np.concatenate([np.argsort(lens)[-8:], _sample(rg.layout.nsys, 24)]))
+    xr = tx.cpu().numpy()
+    for s in pick:
+        sl = slice(rg.layout.offsets[s], rg.layout.offsets[s + 1])
+        ref = oracle.thomas(ra[sl], rb[sl], rc[sl], rd[sl])
+        assert np.max(np.abs(xr[sl] - ref)) / np.max(np.abs(ref)) <= parity.TOL_F64
