@@ -284,18 +284,20 @@ int tdma_autotune(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtyp
         // one batch worth of workspace (slot 0 of the pipeline workspace)
         const size_t fac = shared_factors ? (size_t)layout->n : (size_t)layout->n * s;
         const size_t fac_bytes = (fac * esz + 255) & ~(size_t)255;
+        const size_t dh_bytes = ((size_t)layout->n * s * esz + 255) & ~(size_t)255;
         const size_t red_bytes = ((size_t)6 * P * s * 8 + 255) & ~(size_t)255;
         const size_t x_bytes = ((size_t)2 * P * s * 8 + 255) & ~(size_t)255;
         void *ws = nullptr;
-        rc = ctx->workspace(4, 2 * fac_bytes + red_bytes + 2 * x_bytes, &ws);
+        rc = ctx->workspace(4, dh_bytes + 2 * fac_bytes + red_bytes + 2 * x_bytes, &ws);
         if (rc != TDMA_OK) return rc;
-        char *b = (char *)ws;
+        char *wd_ = (char *)ws;
+        char *b = wd_ + dh_bytes;
         void *wa = b, *wc = b + fac_bytes;
         double *red = (double *)(b + 2 * fac_bytes), *X = (double *)(b + 2 * fac_bytes + red_bytes);
         double *scr = (double *)(b + 2 * fac_bytes + red_bytes + x_bytes);
         float tA = 0, tB = 0, tC = 0;
         rc = time_median(st, 3, [&]() {
-            hipError_t e = launch_stage_a(dtype, map, coef, d, x, wa, wc, red, 0, s, P, shared_factors, ctx->d_err, st);
+            hipError_t e = launch_stage_a(dtype, map, coef, d, wd_, wa, wc, red, 0, s, P, shared_factors, ctx->d_err, st);
             return e == hipSuccess ? TDMA_OK : hip_fail(e, "stage A");
         }, &tA);
         if (rc == TDMA_OK) rc = time_median(st, 3, [&]() {
@@ -303,7 +305,7 @@ int tdma_autotune(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtyp
             return e == hipSuccess ? TDMA_OK : hip_fail(e, "stage B");
         }, &tB);
         if (rc == TDMA_OK) rc = time_median(st, 3, [&]() {
-            hipError_t e = launch_stage_c(dtype, map, x, wa, wc, X, 0, s, P, shared_factors, st);
+            hipError_t e = launch_stage_c(dtype, map, x, wd_, wa, wc, X, 0, s, P, shared_factors, st);
             return e == hipSuccess ? TDMA_OK : hip_fail(e, "stage C");
         }, &tC);
         if (rc != TDMA_OK) return rc;

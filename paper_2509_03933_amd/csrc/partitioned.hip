@@ -5,7 +5,8 @@
 //   tile.hip.h and the running products that turn the back recurrence of the
 //   row-1 spike into a forward sum.  It writes the partition's two
 //   unit-diagonal interface equations (6 values) to the reduced buffer, and
-//   the row factors (d^ into x, a^ and c^ into a workspace) that Stage C needs.
+//   the row factors d^, a^, c^ that Stage C needs to a workspace (never to x,
+//   so inputs and outputs never alias inside a kernel and loads can run ahead).
 // Stage B (k_stage_b): the 2P-row interface system of every system of the
 //   batch, FP64; parallel cyclic reduction across P consecutive lanes with
 //   wavefront shuffles (P a power of two <= 64), otherwise one lane per system
@@ -45,7 +46,8 @@ __device__ __forceinline__ size_t red_at(int v, int p, int64_t k, int P, int64_t
 
 template <typename T, bool LIKE_D, bool SHIFT, bool SHARED_FACTORS>
 __global__ void __launch_bounds__(256)
-k_stage_a(SysMap map, Coef coef, const T *d, T *x, T *ws_a, T *ws_c, double *red, int64_t k_begin,
+k_stage_a(SysMap map, Coef coef, const T *__restrict__ d, T *__restrict__ ws_d,
+          T *__restrict__ ws_a, T *__restrict__ ws_c, double *__restrict__ red, int64_t k_begin,
           int64_t nb, int P, int *err) {
     const int64_t kl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int p = blockIdx.y;
@@ -53,7 +55,9 @@ k_stage_a(SysMap map, Coef coef, const T *d, T *x, T *ws_a, T *ws_c, double *red
     const dev::LaneSys sys = dev::lane_system(map, k_begin + kl);
     const int64_t n = map.n;
     const PartRange pr = part_range(n, P, p);
-    const T *A = (const T *)coef.a, *B = (const T *)coef.b, *C = (const T *)coef.c;
+    const T *__restrict__ A = (const T *)coef.a;
+    const T *__restrict__ B = (const T *)coef.b;
+    const T *__restrict__ C = (const T *)coef.c;
     const int64_t rs = map.row_stride;
     T sh = T(0);
     if constexpr (SHIFT) sh = ((const T *)coef.shift)[sys.id];
@@ -85,10 +89,11 @@ k_stage_a(SysMap map, Coef coef, const T *d, T *x, T *ws_a, T *ws_c, double *red
     T ah = a * ib, ch = c * ib, dh = dd * ib;
     T pi = T(1), dt1 = T(0), at1 = T(0);
     const int m = pr.m;
+#pragma unroll 4
     for (int j = 1; j < m - 1; ++j) {
         // row j is final: store it, fold it into the row-1 spike, then advance
         const int64_t r = pr.start + j;
-        x[sys.base + r * rs] = dh;
+        ws_d[r * nb + kl] = dh;
         if (store_factors) {
             ws_a[r * fstride + fk] = ah;
             ws_c[r * fstride + fk] = ch;
@@ -195,8 +200,9 @@ k_stage_b_seq(const double *red, double *X, double *scratch, int64_t nb, int P, 
 
 template <typename T, bool SHARED_FACTORS>
 __global__ void __launch_bounds__(256)
-k_stage_c(SysMap map, T *x, const T *ws_a, const T *ws_c, const double *X, int64_t k_begin,
-          int64_t nb, int P) {
+k_stage_c(SysMap map, T *__restrict__ x, const T *__restrict__ ws_d, const T *__restrict__ ws_a,
+          const T *__restrict__ ws_c, const double *__restrict__ X, int64_t k_begin, int64_t nb,
+          int P) {
     const int64_t kl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int p = blockIdx.y;
     if (kl >= nb) return;
@@ -208,17 +214,17 @@ k_stage_c(SysMap map, T *x, const T *ws_a, const T *ws_c, const double *X, int64
     const int64_t fk = SHARED_FACTORS ? 0 : kl;
     const int64_t fstride = SHARED_FACTORS ? 1 : nb;
     x[sys.base + (pr.start + pr.m - 1) * rs] = xn;
+#pragma unroll 4
     for (int j = pr.m - 2; j >= 1; --j) {
         const int64_t r = pr.start + j;
-        const int64_t idx = sys.base + r * rs;
-        xn = x[idx] - ws_a[r * fstride + fk] * xf - ws_c[r * fstride + fk] * xn;
-        x[idx] = xn;
+        xn = ws_d[r * nb + kl] - ws_a[r * fstride + fk] * xf - ws_c[r * fstride + fk] * xn;
+        x[sys.base + r * rs] = xn;
     }
     x[sys.base + pr.start * rs] = xf;
 }
 
 template <typename T>
-hipError_t launch_a_t(const SysMap &map, const Coef &coef, const void *d, void *x, void *ws_a,
+hipError_t launch_a_t(const SysMap &map, const Coef &coef, const void *d, void *ws_d, void *ws_a,
                       void *ws_c, double *red, int64_t k_begin, int64_t nb, int P, bool shared_f,
                       int *err, hipStream_t st) {
     const dim3 grid((unsigned)((nb + 255) / 256), (unsigned)P);
@@ -226,7 +232,7 @@ hipError_t launch_a_t(const SysMap &map, const Coef &coef, const void *d, void *
 #define TDMA_A(LD, SH, SF)                                                                      \
     if (like_d == LD && shift == SH && shared_f == SF) {                                        \
         hipLaunchKernelGGL((k_stage_a<T, LD, SH, SF>), grid, dim3(256), 0, st, map, coef,       \
-                           (const T *)d, (T *)x, (T *)ws_a, (T *)ws_c, red, k_begin, nb, P, err); \
+                           (const T *)d, (T *)ws_d, (T *)ws_a, (T *)ws_c, red, k_begin, nb, P, err); \
         return hipGetLastError();                                                               \
     }
     TDMA_A(true, false, false)
@@ -240,15 +246,15 @@ hipError_t launch_a_t(const SysMap &map, const Coef &coef, const void *d, void *
 
 }  // namespace
 
-hipError_t launch_stage_a(int dtype, const SysMap &map, const Coef &coef, const void *d, void *x,
-                          void *ws_a, void *ws_c, double *red, int64_t k_begin, int64_t nb, int P,
-                          bool shared_factors, int *err, hipStream_t st) {
+hipError_t launch_stage_a(int dtype, const SysMap &map, const Coef &coef, const void *d,
+                          void *ws_d, void *ws_a, void *ws_c, double *red, int64_t k_begin,
+                          int64_t nb, int P, bool shared_factors, int *err, hipStream_t st) {
     if (nb <= 0) return hipSuccess;
     if (dtype == TDMA_F64)
-        return launch_a_t<double>(map, coef, d, x, ws_a, ws_c, red, k_begin, nb, P, shared_factors,
-                                  err, st);
-    return launch_a_t<float>(map, coef, d, x, ws_a, ws_c, red, k_begin, nb, P, shared_factors, err,
-                             st);
+        return launch_a_t<double>(map, coef, d, ws_d, ws_a, ws_c, red, k_begin, nb, P,
+                                  shared_factors, err, st);
+    return launch_a_t<float>(map, coef, d, ws_d, ws_a, ws_c, red, k_begin, nb, P, shared_factors,
+                             err, st);
 }
 
 hipError_t launch_stage_b(const double *red, double *X, double *scratch, int64_t nb, int P,
@@ -267,26 +273,20 @@ hipError_t launch_stage_b(const double *red, double *X, double *scratch, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_stage_c(int dtype, const SysMap &map, void *x, const void *ws_a,
-                          const void *ws_c, const double *X, int64_t k_begin, int64_t nb, int P,
-                          bool shared_factors, hipStream_t st) {
+hipError_t launch_stage_c(int dtype, const SysMap &map, void *x, const void *ws_d,
+                          const void *ws_a, const void *ws_c, const double *X, int64_t k_begin,
+                          int64_t nb, int P, bool shared_factors, hipStream_t st) {
     if (nb <= 0) return hipSuccess;
     const dim3 grid((unsigned)((nb + 255) / 256), (unsigned)P);
+#define TDMA_C(T, SF)                                                                          \
+    hipLaunchKernelGGL((k_stage_c<T, SF>), grid, dim3(256), 0, st, map, (T *)x, (const T *)ws_d, \
+                       (const T *)ws_a, (const T *)ws_c, X, k_begin, nb, P)
     if (dtype == TDMA_F64) {
-        if (shared_factors)
-            hipLaunchKernelGGL((k_stage_c<double, true>), grid, dim3(256), 0, st, map, (double *)x,
-                               (const double *)ws_a, (const double *)ws_c, X, k_begin, nb, P);
-        else
-            hipLaunchKernelGGL((k_stage_c<double, false>), grid, dim3(256), 0, st, map, (double *)x,
-                               (const double *)ws_a, (const double *)ws_c, X, k_begin, nb, P);
+        if (shared_factors) TDMA_C(double, true); else TDMA_C(double, false);
     } else {
-        if (shared_factors)
-            hipLaunchKernelGGL((k_stage_c<float, true>), grid, dim3(256), 0, st, map, (float *)x,
-                               (const float *)ws_a, (const float *)ws_c, X, k_begin, nb, P);
-        else
-            hipLaunchKernelGGL((k_stage_c<float, false>), grid, dim3(256), 0, st, map, (float *)x,
-                               (const float *)ws_a, (const float *)ws_c, X, k_begin, nb, P);
+        if (shared_factors) TDMA_C(float, true); else TDMA_C(float, false);
     }
+#undef TDMA_C
     return hipGetLastError();
 }
 

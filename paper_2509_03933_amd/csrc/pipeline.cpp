@@ -19,7 +19,7 @@
 namespace tdma {
 
 struct SlotBufs {
-    void *ws_a, *ws_c;
+    void *ws_d, *ws_a, *ws_c;
     double *red, *X, *scratch;
 };
 
@@ -41,15 +41,18 @@ int pipeline_solve(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, i
     // per-slot workspace
     const size_t fac = shared_factors ? (size_t)n : (size_t)n * batch;
     const size_t fac_bytes = (fac * esz + 255) & ~(size_t)255;
+    const size_t dh_bytes = ((size_t)n * batch * esz + 255) & ~(size_t)255;
     const size_t red_bytes = ((size_t)6 * P * batch * 8 + 255) & ~(size_t)255;
     const size_t x_bytes = ((size_t)2 * P * batch * 8 + 255) & ~(size_t)255;
-    const size_t slot_bytes = 2 * fac_bytes + red_bytes + 2 * x_bytes;
+    const size_t slot_bytes = dh_bytes + 2 * fac_bytes + red_bytes + 2 * x_bytes;
     void *ws = nullptr;
     int rc = ctx->workspace(1, slot_bytes * nslots, &ws);
     if (rc != TDMA_OK) return rc;
     std::vector<SlotBufs> slots(nslots);
     for (int i = 0; i < nslots; ++i) {
         char *b = (char *)ws + slot_bytes * i;
+        slots[i].ws_d = b;
+        b += dh_bytes;
         slots[i].ws_a = b;
         slots[i].ws_c = b + fac_bytes;
         slots[i].red = (double *)(b + 2 * fac_bytes);
@@ -79,8 +82,8 @@ int pipeline_solve(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, i
 
     auto stage_a = [&](int64_t b, hipStream_t s) {
         const SlotBufs &sb = slots[b % nslots];
-        return launch_stage_a(dtype, map, coef, d, x, sb.ws_a, sb.ws_c, sb.red, b * batch, nb_of(b),
-                              P, shared_factors, ctx->d_err, s);
+        return launch_stage_a(dtype, map, coef, d, sb.ws_d, sb.ws_a, sb.ws_c, sb.red, b * batch,
+                              nb_of(b), P, shared_factors, ctx->d_err, s);
     };
     auto stage_b = [&](int64_t b, hipStream_t s) {
         const SlotBufs &sb = slots[b % nslots];
@@ -88,7 +91,7 @@ int pipeline_solve(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, i
     };
     auto stage_c = [&](int64_t b, hipStream_t s) {
         const SlotBufs &sb = slots[b % nslots];
-        return launch_stage_c(dtype, map, x, sb.ws_a, sb.ws_c, sb.X, b * batch, nb_of(b), P,
+        return launch_stage_c(dtype, map, x, sb.ws_d, sb.ws_a, sb.ws_c, sb.X, b * batch, nb_of(b), P,
                               shared_factors, s);
     };
 

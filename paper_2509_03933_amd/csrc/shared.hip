@@ -25,9 +25,10 @@ using dev::TileSysLds;
 //   part             : 6 x P doubles (K0, K1, AF, GF, AL, GL)
 //   qa               : 3 x nsteps x 2P doubles (pre-step a, c and 1/beta)
 //   xd               : S x (2P+1) doubles (interface right-hand sides)
+//   co               : 3 x P*M doubles (the tile's a, b, c rows, corners removed)
 //   end              : staging of the contiguous-row variant starts here
 struct SharedLds {
-    size_t g, h, pi, ah, ch, part, qa, xd, end;
+    size_t g, h, pi, ah, ch, part, qa, xd, co, end;
     int nsteps;
 };
 
@@ -52,7 +53,8 @@ __host__ __device__ inline SharedLds shared_layout(size_t esz, int M, int P, int
     if ((1 << L.nsteps) < 2 * P) ++L.nsteps;
     L.qa = align16(L.part + 6 * (size_t)P * 8);
     L.xd = align16(L.qa + 3 * (size_t)L.nsteps * 2 * P * 8);
-    L.end = align16(L.xd + (size_t)S * (2 * P + 1) * 8);
+    L.co = align16(L.xd + (size_t)S * (2 * P + 1) * 8);
+    L.end = align16(L.co + 3 * (size_t)P * M * 8);
     return L;
 }
 
@@ -118,31 +120,41 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
         dev::stage_in<T, M>(stg, tsys, d, T(0), S, R, R + 1, 1.0f / (float)R, s, r0, dv);
     }
 
-    // 2. coefficient tables, one lane per partition (FP64 arithmetic)
+    // 2. coefficient tables, one lane per partition (FP64 arithmetic), from a
+    //    coalesced copy of the tile's coefficient rows in LDS
     bool bad = false;
-    if (s == 0) {
+    {
         const T *A = (const T *)coef.a, *B = (const T *)coef.b, *C = (const T *)coef.c;
+        double *CO = reinterpret_cast<double *>(base + L.co);
+        const int R = P * M;
+        for (int r = tid; r < R; r += blockDim.x) {
+            const bool in = r < n;
+            CO[r] = in && r > 0 ? (double)A[r] : 0.0;
+            CO[R + r] = in ? (double)B[r] : 1.0;
+            CO[2 * R + r] = in && r < n - 1 ? (double)C[r] : 0.0;
+        }
+        __syncthreads();
+    }
+    if (s == 0) {
+        const double *CO = reinterpret_cast<const double *>(base + L.co);
+        const int R = P * M;
         auto row = [&](int j, double &aj, double &bj, double &cj) {
-            const int64_t r = r0 + j;
-            if (r < n) {
-                aj = r == 0 ? 0.0 : (double)A[r];
-                bj = (double)B[r];
-                cj = r == n - 1 ? 0.0 : (double)C[r];
-            } else {
-                aj = 0.0; bj = 1.0; cj = 0.0;
-            }
+            const int r = r0 + j;
+            aj = CO[r];
+            bj = CO[R + r];
+            cj = CO[2 * R + r];
         };
         double a0, b0, c0, aj, bj, cj;
         row(0, a0, b0, c0);
         bad |= dev::bad_pivot(b0);
-        const double ib0 = 1.0 / b0;
+        const double ib0 = dev::recip(b0);
         const double ah0 = a0 * ib0, ch0 = c0 * ib0;
         T *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch, *ah = AH + p * pitch,
           *ch = CH + p * pitch;
         g[0] = (T)ib0; h[0] = T(0); pi_t[0] = T(0); ah[0] = (T)ah0; ch[0] = (T)ch0;
         row(1, aj, bj, cj);
         bad |= dev::bad_pivot(bj);
-        double gj = 1.0 / bj;
+        double gj = dev::recip(bj);
         double ahp = aj * gj, chp = cj * gj;
         g[1] = (T)gj; h[1] = T(0); ah[1] = (T)ahp; ch[1] = (T)chp;
         double pi = 1.0, at1 = 0.0;
@@ -152,7 +164,7 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
             row(j, aj, bj, cj);
             const double piv = bj - aj * chp;
             bad |= dev::bad_pivot(piv);
-            gj = 1.0 / piv;
+            gj = dev::recip(piv);
             const double hj = aj * gj;
             ahp = -hj * ahp;
             chp = cj * gj;
@@ -163,7 +175,7 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
         const double ct1 = -pi;
         const double den = 1.0 - ch0 * at1;
         bad |= dev::bad_pivot(den);
-        const double rho = 1.0 / den;
+        const double rho = dev::recip(den);
         K0[p] = rho * ib0;
         K1[p] = rho * ch0;
         AF[p] = rho * ah0;
@@ -205,13 +217,13 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
             }
             const double b0 = 1.0 - a0 * lc0 - c0 * ua0;
             const double b1 = 1.0 - a1 * lc1 - c1 * ua1;
+            const double ib0 = dev::recip(b0), ib1 = dev::recip(b1);
             if (act) {
                 bad |= dev::bad_pivot(b0) || dev::bad_pivot(b1);
                 const int i0 = 2 * lane, i1 = i0 + 1, base_k = k * 2 * P;
-                QA[base_k + i0] = a0; QC[base_k + i0] = c0; QB[base_k + i0] = 1.0 / b0;
-                QA[base_k + i1] = a1; QC[base_k + i1] = c1; QB[base_k + i1] = 1.0 / b1;
+                QA[base_k + i0] = a0; QC[base_k + i0] = c0; QB[base_k + i0] = ib0;
+                QA[base_k + i1] = a1; QC[base_k + i1] = c1; QB[base_k + i1] = ib1;
             }
-            const double ib0 = 1.0 / b0, ib1 = 1.0 / b1;
             const double na0 = -a0 * la0 * ib0, nc0 = -c0 * uc0 * ib0;
             const double na1 = -a1 * la1 * ib1, nc1 = -c1 * uc1 * ib1;
             a0 = na0; c0 = nc0; a1 = na1; c1 = nc1;

@@ -32,7 +32,9 @@ def test_fused_autotune_then_solve():
 def test_partitioned_autotune_model_vs_brute():
     import paper_2509_03933_amd as tdma
     from workloads import device
-    p = configs.partitioned(256, 128, 512)          # 32768 systems -> batches 4096..32768
+    # 262,144 systems of n = 512 (~0.13 G unknowns): large enough that stage
+    # times, not per-launch overheads, decide the batch size
+    p = configs.partitioned(512, 512, 512)
     td, coeffs = device.device_inputs(p)
     tx = torch.empty_like(td)
     rec = tdma.autotune(p.layout, coeffs, td, tx, what=2)

@@ -21,19 +21,27 @@ def _sample(nsys, k=96, seed=3):
 
 
 def _check_sampled(p, x_dev, systems, tol, ld_ok=False):
+    """Oracle parity of sampled systems.  With ld_ok, an ill-conditioned
+    system whose FP64 oracle misses the bar against the long-double oracle
+    passes within parity.ILL_FACTOR times that oracle's own error."""
     x = x_dev.double()
     worst = 0.0
     for s in systems:
         a, b, c, d = configs.system_inputs(p, int(s))
-        ref = oracle.thomas(a, b, c, d)
         rows = torch.from_numpy(p.layout.sys_rows(int(s))).cuda()
         got = x[rows].cpu().numpy()
-        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
-        if ld_ok and err > tol:
-            ref = oracle.thomas(a, b, c, d, oracle.LONG_DOUBLE)
-            err = min(err, np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
-        worst = max(worst, err)
-    assert worst <= tol, worst
+        if ld_ok:
+            ok, e64, eld, eorc = parity.conditioned_error(got, a, b, c, d, tol)
+            if eld is not None:
+                print(f"system {int(s)}: err vs FP64 oracle {e64:.2e}, vs long double {eld:.2e}, "
+                      f"FP64 oracle vs long double {eorc:.2e}")
+            assert ok, (int(s), e64, eld, eorc)
+            worst = max(worst, e64 if eld is None else min(e64, eld))
+        else:
+            ref = oracle.thomas(a, b, c, d)
+            worst = max(worst, np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    if not ld_ok:
+        assert worst <= tol, worst
     return worst
 
 
