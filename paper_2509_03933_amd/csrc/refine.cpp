@@ -37,6 +37,34 @@ static bool default_refine_shape(int64_t n, int64_t nsys, bool contig, bool like
     return false;
 }
 
+// Shared operator without a shift: M = 16 (else 8), P a power of two <= 64,
+// S = 16 consecutive systems (128-byte FP64 rows), or 256/P for contiguous rows.
+static bool default_shared_refine_shape(int64_t n, int64_t nsys, bool contig, TileShape *out) {
+    for (int M : {16, 8}) {
+        int P = 1;
+        while ((int64_t)P * M < n) P <<= 1;
+        if (P > 64) continue;
+        TileShape sh;
+        sh.M = M;
+        sh.P = P;
+        sh.contig = contig;
+        int S_log2 = 4;
+        if (contig) {
+            S_log2 = 0;
+            while ((2 << S_log2) * P <= 256) ++S_log2;
+        }
+        while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= nsys) --S_log2;
+        sh.S_log2 = S_log2;
+        while (sh.S_log2 > 0 && (sh.threads() > (M >= 16 ? 512 : 1024) ||
+                                 shared_refine_lds_bytes(sh) > 64 * 1024))
+            --sh.S_log2;
+        if (!shared_refine_supported(sh)) continue;
+        *out = sh;
+        return true;
+    }
+    return false;
+}
+
 }  // namespace tdma
 
 using namespace tdma;
@@ -75,7 +103,12 @@ extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *
     if (e != hipSuccess) return hip_fail(e, "refine init");
     const SysMap map = make_map(layout);
     const Coef coef = make_coef(coeffs);
-    e = launch_refine(map, coef, sh, d, x, iters, tol, state, st);
+    TileShape ssh;
+    if (coeffs->mode == TDMA_COEF_SHARED && coeffs->b_shift == nullptr &&
+        default_shared_refine_shape(layout->n, nsys, layout->row_stride == 1, &ssh))
+        e = launch_shared_refine(map, coef, ssh, d, x, iters, tol, state, st);
+    else
+        e = launch_refine(map, coef, sh, d, x, iters, tol, state, st);
     if (e != hipSuccess) return hip_fail(e, "refine launch");
     if (fallback) {
         TileShape fsh;

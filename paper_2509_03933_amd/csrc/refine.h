@@ -18,4 +18,11 @@ hipError_t launch_refine(const SysMap &map, const Coef &coef, const TileShape &s
                          double *x, int iters, double tol, RefineState *state, hipStream_t st);
 hipError_t launch_refine_init(RefineState *state, int32_t *list, int64_t capacity, hipStream_t st);
 
+// shared-operator variant (shared.hip)
+size_t shared_refine_lds_bytes(const TileShape &sh);
+bool shared_refine_supported(const TileShape &sh);
+hipError_t launch_shared_refine(const SysMap &map, const Coef &coef, const TileShape &sh,
+                                const double *d, double *x, int iters, double tol,
+                                RefineState *state, hipStream_t st);
+
 }  // namespace tdma

@@ -11,6 +11,7 @@
 //   per PCR step and interface row: the pre-step couplings and 1/beta.
 // The per-system work is then about five FP64 operations per row, and the
 // interface solve exchanges one value per row instead of three.
+#include "refine.h"
 #include "tile.hip.h"
 
 namespace tdma {
@@ -67,20 +68,15 @@ __host__ __device__ inline size_t shared_tsys_off(const SharedLds &L, size_t esz
 template <typename T, int M>
 constexpr int shared_max_threads() { return (int)sizeof(T) * M >= 256 ? 512 : 1024; }
 
-template <typename T, int M, bool CONTIG>
-__global__ void __launch_bounds__((shared_max_threads<T, M>()))
-k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *err) {
-    extern __shared__ double lds[];
-    char *base = reinterpret_cast<char *>(lds);
-    const int tid = threadIdx.x;
-    const int S = 1 << S_log2, P = 1 << P_log2;
-    const int s = tid & (S - 1);
-    const int p = tid >> S_log2;
+// Steps shared by the shared-operator kernels: stage the tile's coefficient
+// rows in LDS (coalesced), build the per-partition factor tables (one lane per
+// partition, FP64 arithmetic, stored as T), and record the coefficient
+// history of the interface PCR (first wavefront).  Every thread calls it.
+template <typename T, int M>
+__device__ __forceinline__ void shared_tables(const Coef &coef, int64_t n, const SharedLds &L,
+                                              char *base, int tid, int s, int p, int P,
+                                              bool &bad) {
     const int r0 = p * M;
-    const int64_t n = map.n;
-    const int64_t k0 = (int64_t)blockIdx.x << S_log2;
-    const LaneSys sys = dev::lane_system(map, k0 + s);
-    const SharedLds L = shared_layout(sizeof(T), M, P, S);
     const int pitch = M + 1;
     T *G = reinterpret_cast<T *>(base + L.g);
     T *H = reinterpret_cast<T *>(base + L.h);
@@ -92,37 +88,8 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
            *GL = PT + 5 * P;
     double *QA = reinterpret_cast<double *>(base + L.qa);
     double *QC = QA + L.nsteps * 2 * P, *QB = QC + L.nsteps * 2 * P;
-    double *XD = reinterpret_cast<double *>(base + L.xd);
-    const int xpitch = 2 * P + 1;
-
-    // 1. right-hand sides of this lane's rows (in flight while the tables are built)
-    T dv[M];
-    if constexpr (!CONTIG) {
-        const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
-        const T *pd = d + sys.base + (int64_t)r0 * map.row_stride;
-        const int64_t rs = map.row_stride;
-        if (rows_here == M) {
-#pragma unroll
-            for (int j = 0; j < M; ++j) dv[j] = pd[j * rs];
-        } else {
-#pragma unroll
-            for (int j = 0; j < M; ++j) dv[j] = j < rows_here ? pd[j * rs] : T(0);
-        }
-    } else {
-        const int R = P * M;
-        T *stg = reinterpret_cast<T *>(base + shared_stage_off(L));
-        TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, sizeof(T), M, P, S));
-        if (tid < S) {
-            const LaneSys q = dev::lane_system(map, k0 + tid);
-            tsys[tid].base = q.base;
-            tsys[tid].nrows = q.nrows;
-        }
-        dev::stage_in<T, M>(stg, tsys, d, T(0), S, R, R + 1, 1.0f / (float)R, s, r0, dv);
-    }
-
-    // 2. coefficient tables, one lane per partition (FP64 arithmetic), from a
+    // coefficient tables, one lane per partition (FP64 arithmetic), from a
     //    coalesced copy of the tile's coefficient rows in LDS
-    bool bad = false;
     {
         const T *A = (const T *)coef.a, *B = (const T *)coef.b, *C = (const T *)coef.c;
         double *CO = reinterpret_cast<double *>(base + L.co);
@@ -231,23 +198,23 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
     }
     __syncthreads();
 
-    // 4. Stage A on this lane's right-hand sides
-    const T *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch;
-    const T draw0 = dv[0];
-    dv[1] = g[1] * dv[1];
-#pragma unroll
-    for (int j = 2; j < M; ++j) dv[j] = g[j] * dv[j] - h[j] * dv[j - 1];
-    T dt1 = T(0);
-#pragma unroll
-    for (int j = 1; j <= M - 2; ++j) dt1 += pi_t[j] * dv[j];
-    const double df = K0[p] * (double)draw0 - K1[p] * (double)dt1;
-    const double dl_ = (double)dv[M - 1];
+}
 
-    // 5. Stage B: right-hand-side-only PCR inside wavefronts
+// Stage B of the shared-operator kernels: the interface right-hand sides
+// (first/last row of every partition) go through LDS to P consecutive lanes
+// per system, which run the PCR steps with wavefront shuffles using the
+// recorded coefficient history (QA, QC: pre-step couplings, QB: 1/beta).
+// Every thread calls it; returns X_{2p} and X_{2p+1} of the caller's system.
+__device__ __forceinline__ void shared_rhs_pcr(double *XD, const double *QA, const double *QC,
+                                               const double *QB, int S, int P, int P_log2, int s,
+                                               int p, double df, double dl_, double &xf,
+                                               double &xl) {
+    const int xpitch = 2 * P + 1;
     XD[s * xpitch + 2 * p] = df;
     XD[s * xpitch + 2 * p + 1] = dl_;
     __syncthreads();
     {
+        const int tid = threadIdx.x;
         const int s2 = tid >> P_log2;
         const int p2 = tid & (P - 1);
         const int lane = tid & 63;
@@ -279,8 +246,84 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
         XD[q2 + 1] = e1;
     }
     __syncthreads();
-    const T xf = (T)XD[s * xpitch + 2 * p];
-    const T xl = (T)XD[s * xpitch + 2 * p + 1];
+    xf = XD[s * xpitch + 2 * p];
+    xl = XD[s * xpitch + 2 * p + 1];
+}
+
+template <typename T, int M, bool CONTIG>
+__global__ void __launch_bounds__((shared_max_threads<T, M>()))
+k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *err) {
+    extern __shared__ double lds[];
+    char *base = reinterpret_cast<char *>(lds);
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2, P = 1 << P_log2;
+    const int s = tid & (S - 1);
+    const int p = tid >> S_log2;
+    const int r0 = p * M;
+    const int64_t n = map.n;
+    const int64_t k0 = (int64_t)blockIdx.x << S_log2;
+    const LaneSys sys = dev::lane_system(map, k0 + s);
+    const SharedLds L = shared_layout(sizeof(T), M, P, S);
+    const int pitch = M + 1;
+    T *G = reinterpret_cast<T *>(base + L.g);
+    T *H = reinterpret_cast<T *>(base + L.h);
+    T *PI = reinterpret_cast<T *>(base + L.pi);
+    T *AH = reinterpret_cast<T *>(base + L.ah);
+    T *CH = reinterpret_cast<T *>(base + L.ch);
+    double *PT = reinterpret_cast<double *>(base + L.part);
+    double *K0 = PT, *K1 = PT + P, *AF = PT + 2 * P, *GF = PT + 3 * P, *AL = PT + 4 * P,
+           *GL = PT + 5 * P;
+    double *QA = reinterpret_cast<double *>(base + L.qa);
+    double *QC = QA + L.nsteps * 2 * P, *QB = QC + L.nsteps * 2 * P;
+    double *XD = reinterpret_cast<double *>(base + L.xd);
+    const int xpitch = 2 * P + 1;
+
+    // 1. right-hand sides of this lane's rows (in flight while the tables are built)
+    T dv[M];
+    if constexpr (!CONTIG) {
+        const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
+        const T *pd = d + sys.base + (int64_t)r0 * map.row_stride;
+        const int64_t rs = map.row_stride;
+        if (rows_here == M) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) dv[j] = pd[j * rs];
+        } else {
+#pragma unroll
+            for (int j = 0; j < M; ++j) dv[j] = j < rows_here ? pd[j * rs] : T(0);
+        }
+    } else {
+        const int R = P * M;
+        T *stg = reinterpret_cast<T *>(base + shared_stage_off(L));
+        TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, sizeof(T), M, P, S));
+        if (tid < S) {
+            const LaneSys q = dev::lane_system(map, k0 + tid);
+            tsys[tid].base = q.base;
+            tsys[tid].nrows = q.nrows;
+        }
+        dev::stage_in<T, M>(stg, tsys, d, T(0), S, R, R + 1, 1.0f / (float)R, s, r0, dv);
+    }
+
+    // 2-3. coefficient tables and the interface PCR history
+    bool bad = false;
+    shared_tables<T, M>(coef, n, L, base, tid, s, p, P, bad);
+
+    // 4. Stage A on this lane's right-hand sides
+    const T *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch;
+    const T draw0 = dv[0];
+    dv[1] = g[1] * dv[1];
+#pragma unroll
+    for (int j = 2; j < M; ++j) dv[j] = g[j] * dv[j] - h[j] * dv[j - 1];
+    T dt1 = T(0);
+#pragma unroll
+    for (int j = 1; j <= M - 2; ++j) dt1 += pi_t[j] * dv[j];
+    const double df = K0[p] * (double)draw0 - K1[p] * (double)dt1;
+    const double dl_ = (double)dv[M - 1];
+
+    // 5. Stage B: right-hand-side-only PCR inside wavefronts
+    double xfd, xld;
+    shared_rhs_pcr(XD, QA, QC, QB, S, P, P_log2, s, p, df, dl_, xfd, xld);
+    const T xf = (T)xfd;
+    const T xl = (T)xld;
 
     // 6. Stage C
     const T *ah = AH + p * pitch, *ch = CH + p * pitch;
@@ -308,6 +351,144 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
         dev::stage_out<T, M>(stg, tsys, x, S, R, R + 1, 1.0f / (float)R, s, r0, dv);
     }
     if (bad) atomicOr(err, 1);
+}
+
+// Precision form on a shared operator: FP64 d and x in registers, FP32 factor
+// tables (built in FP64, rounded) for the sweeps, FP64 coefficient rows in LDS
+// for the residual r = d - A x, FP64 interface solve.  1 + iters solves, then a
+// per-system convergence test (max|correction| <= tol max|x|); systems that
+// miss it are listed for the FP64 fallback.
+template <int M, bool CONTIG>
+__global__ void __launch_bounds__((M >= 16 ? 512 : 1024))
+k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, int P_log2,
+                int iters, double tol, RefineState *state) {
+    extern __shared__ double lds[];
+    char *base = reinterpret_cast<char *>(lds);
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2, P = 1 << P_log2;
+    const int s = tid & (S - 1);
+    const int p = tid >> S_log2;
+    const int r0 = p * M;
+    const int R = P * M;
+    const int64_t n = map.n;
+    const int64_t k0 = (int64_t)blockIdx.x << S_log2;
+    const LaneSys sys = dev::lane_system(map, k0 + s);
+    const SharedLds L = shared_layout(sizeof(float), M, P, S);
+    const int pitch = M + 1;
+    const float *G = reinterpret_cast<const float *>(base + L.g);
+    const float *H = reinterpret_cast<const float *>(base + L.h);
+    const float *PI = reinterpret_cast<const float *>(base + L.pi);
+    const float *AH = reinterpret_cast<const float *>(base + L.ah);
+    const float *CH = reinterpret_cast<const float *>(base + L.ch);
+    const double *PT = reinterpret_cast<const double *>(base + L.part);
+    const double *QA = reinterpret_cast<const double *>(base + L.qa);
+    const double *QC = QA + L.nsteps * 2 * P, *QB = QC + L.nsteps * 2 * P;
+    double *XD = reinterpret_cast<double *>(base + L.xd);
+    const double *CO = reinterpret_cast<const double *>(base + L.co);
+    const int xpitch = 2 * P + 1;
+    const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
+
+    double dv[M];
+    if constexpr (!CONTIG) {
+        const double *pd = d + sys.base + (int64_t)r0 * map.row_stride;
+        const int64_t rs = map.row_stride;
+#pragma unroll
+        for (int j = 0; j < M; ++j) dv[j] = j < rows_here ? pd[j * rs] : 0.0;
+    } else {
+        double *stg = reinterpret_cast<double *>(base + shared_stage_off(L));
+        TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, 8, M, P, S));
+        if (tid < S) {
+            const LaneSys q = dev::lane_system(map, k0 + tid);
+            tsys[tid].base = q.base;
+            tsys[tid].nrows = q.nrows;
+        }
+        dev::stage_in<double, M>(stg, tsys, d, 0.0, S, R, R + 1, 1.0f / (float)R, s, r0, dv);
+    }
+    bool bad = false;
+    shared_tables<float, M>(coef, n, L, base, tid, s, p, P, bad);
+
+    const float *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch;
+    const float *ah = AH + p * pitch, *ch = CH + p * pitch;
+    const double K0 = PT[p], K1 = PT[P + p];
+    double xv[M];
+    float e[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) xv[j] = 0.0;
+    for (int it = 0; it <= iters; ++it) {
+        if (it == 0) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) e[j] = (float)dv[j];
+        } else {
+            XD[s * xpitch + 2 * p] = xv[0];
+            XD[s * xpitch + 2 * p + 1] = xv[M - 1];
+            __syncthreads();
+            const double xlo = p > 0 ? XD[s * xpitch + 2 * p - 1] : 0.0;
+            const double xhi = p < P - 1 ? XD[s * xpitch + 2 * p + 2] : 0.0;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const int r = r0 + j;
+                const double xm = j == 0 ? xlo : xv[j > 0 ? j - 1 : 0];
+                const double xp = j == M - 1 ? xhi : xv[j < M - 1 ? j + 1 : M - 1];
+                e[j] = (float)(dv[j] - CO[r] * xm - CO[R + r] * xv[j] - CO[2 * R + r] * xp);
+            }
+        }
+        const float rr0 = e[0];
+        e[1] = g[1] * e[1];
+#pragma unroll
+        for (int j = 2; j < M; ++j) e[j] = g[j] * e[j] - h[j] * e[j - 1];
+        float dt1 = 0.0f;
+#pragma unroll
+        for (int j = 1; j <= M - 2; ++j) dt1 += pi_t[j] * e[j];
+        const double df = K0 * (double)rr0 - K1 * (double)dt1;
+        double xf, xl;
+        shared_rhs_pcr(XD, QA, QC, QB, S, P, P_log2, s, p, df, (double)e[M - 1], xf, xl);
+        e[M - 1] = (float)xl;
+#pragma unroll
+        for (int j = M - 2; j >= 1; --j) e[j] = e[j] - ah[j] * (float)xf - ch[j] * e[j + 1];
+        e[0] = (float)xf;
+#pragma unroll
+        for (int j = 0; j < M; ++j) xv[j] += (double)e[j];
+        __syncthreads();   // XD is rewritten by the next exchange
+    }
+    float emax = 0.0f;
+    double xmax = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        emax = fmaxf(emax, fabsf(e[j]));
+        xmax = fmax(xmax, fabs(xv[j]));
+    }
+    if (bad) emax = __builtin_huge_valf();
+    XD[s * xpitch + 2 * p] = (double)emax;
+    XD[s * xpitch + 2 * p + 1] = xmax;
+    __syncthreads();
+    if (p == 0 && sys.valid) {
+        double em = 0.0, xm = 0.0;
+        for (int q = 0; q < P; ++q) {
+            em = fmax(em, XD[s * xpitch + 2 * q]);
+            xm = fmax(xm, XD[s * xpitch + 2 * q + 1]);
+        }
+        const double rel = xm > 0.0 ? em / xm : (em > 0.0 ? 1.0 : 0.0);
+        const bool conv = rel <= tol && rel == rel;
+        atomicMax(&state->max_rel_bits,
+                  (unsigned long long)__double_as_longlong(rel == rel ? rel : 1e300));
+        if (!conv) {
+            const unsigned long long slot = atomicAdd(&state->not_converged, 1ull);
+            if (state->fallback_list && slot < (unsigned long long)state->list_capacity)
+                state->fallback_list[slot] = (int32_t)sys.id;
+        }
+    }
+    if constexpr (!CONTIG) {
+        double *px = x + sys.base + (int64_t)r0 * map.row_stride;
+        const int64_t rs = map.row_stride;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (j < rows_here) px[j * rs] = xv[j];
+    } else {
+        double *stg = reinterpret_cast<double *>(base + shared_stage_off(L));
+        TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, 8, M, P, S));
+        dev::stage_out<double, M>(stg, tsys, x, S, R, R + 1, 1.0f / (float)R, s, r0, xv);
+    }
 }
 
 template <typename T, int M>
@@ -364,6 +545,42 @@ hipError_t launch_shared(int dtype, const SysMap &map, const Coef &coef, const T
             case 32: return launch_m<float, 32>(map, coef, sh, d, x, err, lds, st);
         }
     }
+    return hipErrorInvalidValue;
+}
+
+size_t shared_refine_lds_bytes(const TileShape &sh) {
+    const int S = 1 << sh.S_log2;
+    const SharedLds L = shared_layout(4, sh.M, sh.P, S);
+    if (!sh.contig) return L.end;
+    return shared_tsys_off(L, 8, sh.M, sh.P, S) + 16 * (size_t)S;
+}
+
+bool shared_refine_supported(const TileShape &sh) {
+    if (sh.P < 1 || sh.P > 64 || (sh.P & (sh.P - 1)) != 0) return false;
+    if (sh.M != 8 && sh.M != 16) return false;
+    if (sh.threads() > (sh.M >= 16 ? 512 : 1024)) return false;
+    return shared_refine_lds_bytes(sh) <= 160 * 1024;
+}
+
+hipError_t launch_shared_refine(const SysMap &map, const Coef &coef, const TileShape &sh,
+                                const double *d, double *x, int iters, double tol,
+                                RefineState *state, hipStream_t st) {
+    const int64_t S = (int64_t)1 << sh.S_log2;
+    const int64_t blocks = (map.nsys + S - 1) / S;
+    if (blocks == 0) return hipSuccess;
+    const size_t lds = shared_refine_lds_bytes(sh);
+    const int P_log2 = ilog2i(sh.P);
+#define TDMA_SR(MM, CT)                                                                          \
+    if (sh.M == MM && sh.contig == CT) {                                                          \
+        hipLaunchKernelGGL((k_shared_refine<MM, CT>), dim3((unsigned)blocks), dim3(sh.threads()), \
+                           lds, st, map, coef, d, x, sh.S_log2, P_log2, iters, tol, state);      \
+        return hipGetLastError();                                                                 \
+    }
+    TDMA_SR(8, false)
+    TDMA_SR(8, true)
+    TDMA_SR(16, false)
+    TDMA_SR(16, true)
+#undef TDMA_SR
     return hipErrorInvalidValue;
 }
 
