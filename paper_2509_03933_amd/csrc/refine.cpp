@@ -120,6 +120,12 @@ extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *
         fm.count = &state->not_converged;
         e = launch_fused(TDMA_F64, fm, coef, fsh, d, x, ctx->d_err, st);
         if (e != hipSuccess) return hip_fail(e, "fallback launch");
+        // the systems that needed the fallback are the ill-conditioned ones:
+        // two rounds of double-double residual + FP64 correction
+        if (polish_partitions(layout->n) <= 512) {
+            e = launch_polish(map, coef, d, x, list, &state->not_converged, capacity, 2, st);
+            if (e != hipSuccess) return hip_fail(e, "fallback polish");
+        }
     }
     if (!report) return TDMA_OK;
     RefineState hs;

@@ -18,6 +18,12 @@ hipError_t launch_refine(const SysMap &map, const Coef &coef, const TileShape &s
                          double *x, int iters, double tol, RefineState *state, hipStream_t st);
 hipError_t launch_refine_init(RefineState *state, int32_t *list, int64_t capacity, hipStream_t st);
 
+// FP64 polishing of listed systems with double-double residuals (refine.hip)
+int polish_partitions(int64_t n);
+hipError_t launch_polish(const SysMap &map, const Coef &coef, const double *d, double *x,
+                         const int32_t *list, const unsigned long long *count, int64_t capacity,
+                         int steps, hipStream_t st);
+
 // shared-operator variant (shared.hip)
 size_t shared_refine_lds_bytes(const TileShape &sh);
 bool shared_refine_supported(const TileShape &sh);

@@ -256,6 +256,102 @@ k_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, int P, i
     }
 }
 
+// Residual r = d - a x_{-} - b x - c x_{+} accumulated in double-double
+// (error-free product via FMA, error-free sums) and rounded once, so the
+// residual of an ill-conditioned system is accurate to the last bit even when
+// its terms cancel.  Contraction is off inside: the error-free transforms
+// rely on every add being rounded on its own.
+__device__ __forceinline__ double residual_dd(double d, double a, double xm, double b, double x0,
+                                              double c, double xp) {
+#pragma clang fp contract(off)
+    double hi = d, lo = 0.0;
+    auto acc = [&](double u, double v) {
+        const double pr = -u * v;
+        const double pe = __builtin_fma(-u, v, -pr);   // exact: -u*v = pr + pe
+        const double s = hi + pr;
+        const double bb = s - hi;
+        const double t = (hi - (s - bb)) + (pr - bb);  // exact: hi + pr = s + t
+        hi = s;
+        lo = lo + (t + pe);
+    };
+    acc(a, xm);
+    acc(b, x0);
+    acc(c, xp);
+    return hi + lo;
+}
+
+// Polishing of listed systems (the FP64 fallback): `steps` rounds of
+// double-double residual and FP64 on-chip correction solve, one system per
+// block of P lanes (M rows each).  Grid-stride over the device-side count.
+template <int M, bool LIKE_D, bool SHIFT>
+__global__ void __launch_bounds__(512)
+k_polish(SysMap map, Coef coef, const double *d, double *x, const int32_t *list,
+         const unsigned long long *count, int64_t capacity, int P, int steps) {
+    extern __shared__ double lds[];
+    const int p = threadIdx.x;
+    const int r0 = p * M;
+    const int64_t n = map.n;
+    const int64_t cnt = (int64_t)*count < capacity ? (int64_t)*count : capacity;
+    const double *A = (const double *)coef.a, *B = (const double *)coef.b,
+                 *C = (const double *)coef.c;
+    double *XB = lds + 3 * (2 * P + 1);          // after the PCR scratch (S = 1)
+    const bool wave_pcr = P <= 64 && (P & (P - 1)) == 0;
+    for (int64_t k = blockIdx.x; k < cnt; k += gridDim.x) {
+        const int64_t id = list[k];
+        const int64_t s1 = id / map.nsys0, s0 = id - s1 * map.nsys0;
+        const int64_t sbase = s0 * map.sys_stride0 + s1 * map.sys_stride1;
+        const int64_t rs = map.row_stride;
+        const double shv = SHIFT ? ((const double *)coef.shift)[id] : 0.0;
+        double av[M], bv[M], cv[M], dv[M], xv[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const int64_t r = r0 + j;
+            if (r < n) {
+                const int64_t idx = sbase + r * rs;
+                dv[j] = d[idx];
+                xv[j] = x[idx];
+                av[j] = r == 0 ? 0.0 : (LIKE_D ? A[idx] : A[r]);
+                bv[j] = (LIKE_D ? B[idx] : B[r]) + shv;
+                cv[j] = r == n - 1 ? 0.0 : (LIKE_D ? C[idx] : C[r]);
+            } else {
+                dv[j] = 0.0; xv[j] = 0.0; av[j] = 0.0; bv[j] = 1.0; cv[j] = 0.0;
+            }
+        }
+        bool bad = false;
+        for (int step = 0; step < steps; ++step) {
+            __syncthreads();
+            XB[2 * p] = xv[0];
+            XB[2 * p + 1] = xv[M - 1];
+            __syncthreads();
+            const double xlo = p > 0 ? XB[2 * p - 1] : 0.0;
+            const double xhi = p < P - 1 ? XB[2 * p + 2] : 0.0;
+            double rv[M], wa[M], wc[M];
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const double xm = j == 0 ? xlo : xv[j > 0 ? j - 1 : 0];
+                const double xp = j == M - 1 ? xhi : xv[j < M - 1 ? j + 1 : M - 1];
+                rv[j] = residual_dd(dv[j], av[j], xm, bv[j], xv[j], cv[j], xp);
+                wa[j] = av[j];
+                wc[j] = cv[j];
+            }
+            const dev::Iface f = dev::reduce_partition<double, M>(wa, bv, wc, rv, bad);
+            double xf, xl;
+            if (wave_pcr)
+                dev::pcr_interface_wave(lds, 1, 0, p, P, __builtin_ctz(P), f, xf, xl, bad);
+            else
+                dev::pcr_interface(lds, 1, 0, p, P, f, xf, xl, bad);
+            dev::substitute_partition<double, M>(wa, wc, rv, xf, xl);
+#pragma unroll
+            for (int j = 0; j < M; ++j) xv[j] += rv[j];
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const int64_t r = r0 + j;
+            if (r < n) x[sbase + r * rs] = xv[j];
+        }
+    }
+}
+
 __global__ void k_refine_init(RefineState *state, int32_t *list, int64_t capacity) {
     state->not_converged = 0ull;
     state->max_rel_bits = 0ull;
@@ -320,6 +416,35 @@ hipError_t launch_refine(const SysMap &map, const Coef &coef, const TileShape &s
     const size_t lds = refine_lds_bytes(sh, coef.mode == TDMA_COEF_LIKE_D);
     if (sh.M == 8) return launch_m<8>(map, coef, sh, d, x, iters, tol, state, lds, st);
     if (sh.M == 16) return launch_m<16>(map, coef, sh, d, x, iters, tol, state, lds, st);
+    return hipErrorInvalidValue;
+}
+
+int polish_partitions(int64_t n) {
+    int P = 1;
+    while ((int64_t)P * 8 < n) P <<= 1;
+    return P;
+}
+
+hipError_t launch_polish(const SysMap &map, const Coef &coef, const double *d, double *x,
+                         const int32_t *list, const unsigned long long *count, int64_t capacity,
+                         int steps, hipStream_t st) {
+    const int P = polish_partitions(map.n);
+    if (P > 512) return hipErrorInvalidValue;
+    const size_t lds = dev::pcr_lds_bytes(1, P) + (size_t)(2 * P + 2) * sizeof(double);
+    const unsigned grid = (unsigned)(capacity < 2048 ? capacity : 2048);
+    if (grid == 0) return hipSuccess;
+    const bool like_d = coef.mode == TDMA_COEF_LIKE_D, shift = coef.shift != nullptr;
+#define TDMA_PO(LD, SH)                                                                     \
+    if (like_d == LD && shift == SH) {                                                      \
+        hipLaunchKernelGGL((k_polish<8, LD, SH>), dim3(grid), dim3(P), lds, st, map, coef, d, x, \
+                           list, count, capacity, P, steps);                                \
+        return hipGetLastError();                                                           \
+    }
+    TDMA_PO(true, false)
+    TDMA_PO(true, true)
+    TDMA_PO(false, false)
+    TDMA_PO(false, true)
+#undef TDMA_PO
     return hipErrorInvalidValue;
 }
 
