@@ -84,3 +84,27 @@ def test_plain_fp32_accuracy_of_first_solve():
     torch.cuda.synchronize()
     ref = parity.oracle_solution(p, a, b, c, d)
     assert parity.per_system_error(p.layout, tx.cpu().numpy(), ref).max() <= parity.TOL_F32
+
+
+def test_refined_meets_bar_against_long_double_everywhere():
+    """With the double-double polishing of its fallback, the precision form is
+    within 1e-12 of the long-double oracle on every mode, the ill-conditioned
+    low modes included, and on the pinned (0,0) system."""
+    p = configs.poisson(16, 16, 1024)
+    x, rep, (a, b, c, d) = _refined(p)
+    ref_ld = parity.oracle_solution(p, a, b, c, d, precision=oracle.LONG_DOUBLE)
+    err = parity.per_system_error(p.layout, x, ref_ld)
+    assert err.max() <= parity.TOL_REFINED, (err.max(), int(err.argmax()))
+    pin = configs.poisson_pinned(p)
+    pa, pb, pc, pd = configs.system_inputs(pin, 0)
+    import paper_2509_03933_amd as tdma
+    td = torch.from_numpy(d).cuda()
+    tx = torch.full_like(td, float("nan"))
+    co = dict(mode=1, a=torch.from_numpy(pin.a).cuda(), b=torch.from_numpy(pin.b).cuda(),
+              c=torch.from_numpy(pin.c).cuda())
+    rep = tdma.solve_refined(pin.layout, co, td, tx)
+    got = tx.cpu().numpy()[pin.layout.sys_rows(0)]
+    ref = oracle.thomas(pa, pb, pc, pd, oracle.LONG_DOUBLE)
+    e = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print("pinned mode: refined vs long double", e, rep)
+    assert e <= parity.TOL_REFINED, e
