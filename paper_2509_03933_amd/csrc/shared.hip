@@ -68,14 +68,62 @@ __host__ __device__ inline size_t shared_tsys_off(const SharedLds &L, size_t esz
 template <typename T, int M>
 constexpr int shared_max_threads() { return (int)sizeof(T) * M >= 256 ? 512 : 1024; }
 
-// Steps shared by the shared-operator kernels: stage the tile's coefficient
-// rows in LDS (coalesced), build the per-partition factor tables (one lane per
-// partition, FP64 arithmetic, stored as T), and record the coefficient
-// history of the interface PCR (first wavefront).  Every thread calls it.
+// Coefficient rows of the tile held in registers from their loads to their
+// copy into LDS.  They are loaded before the right-hand sides: load counters
+// retire in issue order, so the table build then waits only for these loads
+// while the right-hand sides are still in flight.  CR rows per thread cover
+// the tile when S >= M / CR; rows beyond that are loaded by a plain loop.
+template <int M>
+struct CoefRegs {
+    static constexpr int CR = M >= 32 ? 2 : 1;
+    double a[CR], b[CR], c[CR];
+};
+
 template <typename T, int M>
+__device__ __forceinline__ void coef_prefetch(const Coef &coef, int64_t n, int tid,
+                                              CoefRegs<M> &cr) {
+    const T *A = (const T *)coef.a, *B = (const T *)coef.b, *C = (const T *)coef.c;
+#pragma unroll
+    for (int i = 0; i < CoefRegs<M>::CR; ++i) {
+        const int64_t r = tid + (int64_t)i * blockDim.x;
+        const int64_t rc = r < n ? r : n - 1;   // rows past n are identity padding
+        cr.a[i] = (double)A[rc];
+        cr.b[i] = (double)B[rc];
+        cr.c[i] = (double)C[rc];
+    }
+}
+
+// Right-hand sides of a lane's M rows in a strided layout, loaded without
+// branches so that the loads form one straight run behind the coefficient
+// loads (the load counter then stays exact): the pointer stops advancing at
+// the system's last row, rows past it are zeroed after the loads, and a lane
+// past the last system reads the start of the array.
+template <typename T, int M>
+__device__ __forceinline__ void load_rows(const T *d, const LaneSys &sys, int64_t rs, int r0,
+                                          T (&dv)[M]) {
+    const int64_t last = sys.nrows > 0 ? sys.nrows - 1 : 0;
+    const int64_t first = r0 < last ? r0 : last;
+    const int adv = (int)(last - first < M ? last - first : M);   // rows the pointer may advance
+    const T *pd = d + (sys.valid ? sys.base : 0) + first * rs;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        dv[j] = *pd;
+        pd += j < adv ? rs : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+        if (r0 + j >= sys.nrows) dv[j] = T(0);
+}
+
+// Steps shared by the shared-operator kernels: copy the tile's coefficient
+// rows into LDS, build the per-partition factor tables (one lane per
+// partition, FP64 arithmetic, stored as T; the coefficient arrays hold CT),
+// and record the coefficient history of the interface PCR (first wavefront).
+// Every thread calls it.
+template <typename T, typename CT, int M>
 __device__ __forceinline__ void shared_tables(const Coef &coef, int64_t n, const SharedLds &L,
                                               char *base, int tid, int s, int p, int P,
-                                              bool &bad) {
+                                              const CoefRegs<M> &cr, bool &bad) {
     const int r0 = p * M;
     const int pitch = M + 1;
     T *G = reinterpret_cast<T *>(base + L.g);
@@ -89,12 +137,22 @@ __device__ __forceinline__ void shared_tables(const Coef &coef, int64_t n, const
     double *QA = reinterpret_cast<double *>(base + L.qa);
     double *QC = QA + L.nsteps * 2 * P, *QB = QC + L.nsteps * 2 * P;
     // coefficient tables, one lane per partition (FP64 arithmetic), from a
-    //    coalesced copy of the tile's coefficient rows in LDS
+    //    copy of the tile's coefficient rows in LDS (corners and padding removed)
     {
-        const T *A = (const T *)coef.a, *B = (const T *)coef.b, *C = (const T *)coef.c;
         double *CO = reinterpret_cast<double *>(base + L.co);
         const int R = P * M;
-        for (int r = tid; r < R; r += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < CoefRegs<M>::CR; ++i) {
+            const int r = tid + i * (int)blockDim.x;
+            if (r < R) {
+                const bool in = r < n;
+                CO[r] = in && r > 0 ? cr.a[i] : 0.0;
+                CO[R + r] = in ? cr.b[i] : 1.0;
+                CO[2 * R + r] = in && r < n - 1 ? cr.c[i] : 0.0;
+            }
+        }
+        const CT *A = (const CT *)coef.a, *B = (const CT *)coef.b, *C = (const CT *)coef.c;
+        for (int r = tid + CoefRegs<M>::CR * (int)blockDim.x; r < R; r += blockDim.x) {
             const bool in = r < n;
             CO[r] = in && r > 0 ? (double)A[r] : 0.0;
             CO[R + r] = in ? (double)B[r] : 1.0;
@@ -278,19 +336,14 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
     double *XD = reinterpret_cast<double *>(base + L.xd);
     const int xpitch = 2 * P + 1;
 
-    // 1. right-hand sides of this lane's rows (in flight while the tables are built)
+    // 1. coefficient rows, then the right-hand sides of this lane's rows (in
+    //    flight while the tables are built)
+    CoefRegs<M> cr;
+    coef_prefetch<T, M>(coef, n, tid, cr);
+    __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the right-hand sides
     T dv[M];
     if constexpr (!CONTIG) {
-        const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
-        const T *pd = d + sys.base + (int64_t)r0 * map.row_stride;
-        const int64_t rs = map.row_stride;
-        if (rows_here == M) {
-#pragma unroll
-            for (int j = 0; j < M; ++j) dv[j] = pd[j * rs];
-        } else {
-#pragma unroll
-            for (int j = 0; j < M; ++j) dv[j] = j < rows_here ? pd[j * rs] : T(0);
-        }
+        load_rows<T, M>(d, sys, map.row_stride, r0, dv);
     } else {
         const int R = P * M;
         T *stg = reinterpret_cast<T *>(base + shared_stage_off(L));
@@ -305,7 +358,7 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
 
     // 2-3. coefficient tables and the interface PCR history
     bool bad = false;
-    shared_tables<T, M>(coef, n, L, base, tid, s, p, P, bad);
+    shared_tables<T, T, M>(coef, n, L, base, tid, s, p, P, cr, bad);
 
     // 4. Stage A on this lane's right-hand sides
     const T *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch;
@@ -388,12 +441,12 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
     const int xpitch = 2 * P + 1;
     const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
 
+    CoefRegs<M> cr;
+    coef_prefetch<double, M>(coef, n, tid, cr);
+    __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the right-hand sides
     double dv[M];
     if constexpr (!CONTIG) {
-        const double *pd = d + sys.base + (int64_t)r0 * map.row_stride;
-        const int64_t rs = map.row_stride;
-#pragma unroll
-        for (int j = 0; j < M; ++j) dv[j] = j < rows_here ? pd[j * rs] : 0.0;
+        load_rows<double, M>(d, sys, map.row_stride, r0, dv);
     } else {
         double *stg = reinterpret_cast<double *>(base + shared_stage_off(L));
         TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, 8, M, P, S));
@@ -405,7 +458,7 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
         dev::stage_in<double, M>(stg, tsys, d, 0.0, S, R, R + 1, 1.0f / (float)R, s, r0, dv);
     }
     bool bad = false;
-    shared_tables<float, M>(coef, n, L, base, tid, s, p, P, bad);
+    shared_tables<float, double, M>(coef, n, L, base, tid, s, p, P, cr, bad);
 
     const float *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch;
     const float *ah = AH + p * pitch, *ch = CH + p * pitch;
