@@ -11,7 +11,6 @@ using dev::Iface;
 using dev::LaneSys;
 using dev::Ident;
 using dev::TileSysLds;
-using dev::stage_in;
 using dev::stage_out;
 
 // Largest block for M rows per lane: lanes holding >= 128 bytes per array
@@ -71,21 +70,27 @@ __device__ __forceinline__ void fused_tile(const SysMap &map, const Coef &coef, 
             tsys[tid].nrows = q.nrows;
         }
         const float invR = 1.0f / (float)R;
-        stage_in<T, M>(stg, tsys, d, Ident<T>::d, S, R, pitch, invR, s, r0, dv);
-        if constexpr (LIKE_D) {
-            stage_in<T, M>(stg, tsys, A, Ident<T>::a, S, R, pitch, invR, s, r0, av);
-            stage_in<T, M>(stg, tsys, B, Ident<T>::b, S, R, pitch, invR, s, r0, bv);
-            stage_in<T, M>(stg, tsys, C, Ident<T>::c, S, R, pitch, invR, s, r0, cv);
-        } else {
+        if constexpr (!LIKE_D) {
+            // shared coefficient rows (clamped into the system, padding below)
+            const int64_t last = sys.nrows > 0 ? sys.nrows - 1 : 0;
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                const int64_t r = r0 + j;
-                if (r < sys.nrows) {
-                    av[j] = A[r]; bv[j] = B[r]; cv[j] = C[r];
-                } else {
+                const int64_t r = r0 + j < last ? r0 + j : last;
+                av[j] = A[r]; bv[j] = B[r]; cv[j] = C[r];
+            }
+        }
+        // one array at a time through the staging buffer
+        dev::stage_in<T, M>(stg, tsys, d, Ident<T>::d, S, R, pitch, invR, s, r0, dv);
+        if constexpr (LIKE_D) {
+            dev::stage_in<T, M>(stg, tsys, A, Ident<T>::a, S, R, pitch, invR, s, r0, av);
+            dev::stage_in<T, M>(stg, tsys, B, Ident<T>::b, S, R, pitch, invR, s, r0, bv);
+            dev::stage_in<T, M>(stg, tsys, C, Ident<T>::c, S, R, pitch, invR, s, r0, cv);
+        } else {
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (r0 + j >= sys.nrows) {
                     av[j] = Ident<T>::a; bv[j] = Ident<T>::b; cv[j] = Ident<T>::c;
                 }
-            }
         }
     }
     if constexpr (SHIFT) {

@@ -48,53 +48,77 @@ k_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, int P, i
                                             (((size_t)S * xpitch * 8 + 15) & ~(size_t)15));
     const size_t ct_b = LIKE_D ? 0 : (size_t)3 * R * 8;
     dev::TileSysLds *tsys = reinterpret_cast<dev::TileSysLds *>(reinterpret_cast<char *>(CT) + ct_b);
-    if constexpr (!LIKE_D) {
-        // one copy of the shared FP64 operator per workgroup, corners removed,
-        // identity rows past n
-        const double *A0 = (const double *)coef.a, *B0 = (const double *)coef.b,
-                     *C0 = (const double *)coef.c;
-        for (int r = tid; r < R; r += blockDim.x) {
-            const bool in = r < n;
-            CT[r] = in && r > 0 ? A0[r] : 0.0;
-            CT[R + r] = in ? B0[r] : 1.0;
-            CT[2 * R + r] = in && r < n - 1 ? C0[r] : 0.0;
-        }
-        __syncthreads();
+    // Loads in the order their consumers need them: the shift and the shared
+    // operator's rows (the FP32 factors need only these), then the tile's
+    // right-hand sides (and per-row coefficients), which stay in flight while
+    // the shared rows go to LDS.
+    double shv = 0.0;
+    if constexpr (SHIFT) {
+        shv = ((const double *)coef.shift)[sys.valid ? sys.id : 0];
+        if (!sys.valid) shv = 0.0;
     }
+    dev::RowRegs<1> rr;
+    if constexpr (!LIKE_D) dev::rows_prefetch<double, 1>(coef, n, rr);
+    __builtin_amdgcn_sched_barrier(0);
 
     double dv[M], av[LIKE_D ? M : 1], bv[LIKE_D ? M : 1], cv[LIKE_D ? M : 1];
+    double *stg = lds;
+    const float invR = 1.0f / (float)R;
     if constexpr (!CONTIG) {
-        const double *pd = d + sys.base + (int64_t)r0 * map.row_stride;
+        // branch-free: the row index stops at the system's last row, padding
+        // rows are replaced after the loads
         const int64_t rs = map.row_stride;
+        const int64_t last = sys.nrows > 0 ? sys.nrows - 1 : 0;
+        const int64_t first = r0 < last ? r0 : last;
+        const int adv = (int)(last - first < M ? last - first : M);
+        int64_t idx = (sys.valid ? sys.base : 0) + first * rs;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            const bool in = j < rows_here;
-            dv[j] = in ? pd[j * rs] : 0.0;
+            dv[j] = d[idx];
             if constexpr (LIKE_D) {
-                const int64_t off = sys.base + (int64_t)(r0 + j) * rs;
-                av[j] = in ? A[off] : 0.0;
-                bv[j] = in ? B[off] : 1.0;
-                cv[j] = in ? C[off] : 0.0;
+                av[j] = A[idx]; bv[j] = B[idx]; cv[j] = C[idx];
             }
+            idx += j < adv ? rs : 0;
         }
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (j >= rows_here) {
+                dv[j] = 0.0;
+                if constexpr (LIKE_D) { av[j] = 0.0; bv[j] = 1.0; cv[j] = 0.0; }
+            }
     } else {
-        double *stg = lds;
         if (tid < S) {
             const LaneSys q = dev::lane_system(map, k0 + tid);
             tsys[tid].base = q.base;
             tsys[tid].nrows = q.nrows;
         }
-        const float invR = 1.0f / (float)R;
-        dev::stage_in<double, M>(stg, tsys, d, 0.0, S, R, R + 1, invR, s, r0, dv);
+        __syncthreads();
+        dev::stage_load<double, M>(tsys, d, S, R, invR, dv);
         if constexpr (LIKE_D) {
-            dev::stage_in<double, M>(stg, tsys, A, 0.0, S, R, R + 1, invR, s, r0, av);
-            dev::stage_in<double, M>(stg, tsys, B, 1.0, S, R, R + 1, invR, s, r0, bv);
-            dev::stage_in<double, M>(stg, tsys, C, 0.0, S, R, R + 1, invR, s, r0, cv);
+            dev::stage_load<double, M>(tsys, A, S, R, invR, av);
+            dev::stage_load<double, M>(tsys, B, S, R, invR, bv);
+            dev::stage_load<double, M>(tsys, C, S, R, invR, cv);
         }
     }
-    double shv = 0.0;
-    if constexpr (SHIFT) {
-        if (sys.valid) shv = ((const double *)coef.shift)[sys.id];
+    // one copy of the shared FP64 operator per workgroup, corners removed,
+    // identity rows past n
+    if constexpr (!LIKE_D) dev::rows_commit<double, 1>(CT, coef, n, R, rr);
+    if constexpr (CONTIG) {
+        double ld[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) ld[j] = dv[j];
+        dev::stage_put<double, M>(stg, tsys, 0.0, S, R, R + 1, invR, s, r0, ld, dv);
+        if constexpr (LIKE_D) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) ld[j] = av[j];
+            dev::stage_put<double, M>(stg, tsys, 0.0, S, R, R + 1, invR, s, r0, ld, av);
+#pragma unroll
+            for (int j = 0; j < M; ++j) ld[j] = bv[j];
+            dev::stage_put<double, M>(stg, tsys, 1.0, S, R, R + 1, invR, s, r0, ld, bv);
+#pragma unroll
+            for (int j = 0; j < M; ++j) ld[j] = cv[j];
+            dev::stage_put<double, M>(stg, tsys, 0.0, S, R, R + 1, invR, s, r0, ld, cv);
+        }
     }
     // FP64 coefficients of local row j (identity beyond the system)
     auto coefs = [&](int j, double &a, double &b, double &c) {

@@ -68,30 +68,10 @@ __host__ __device__ inline size_t shared_tsys_off(const SharedLds &L, size_t esz
 template <typename T, int M>
 constexpr int shared_max_threads() { return (int)sizeof(T) * M >= 256 ? 512 : 1024; }
 
-// Coefficient rows of the tile held in registers from their loads to their
-// copy into LDS.  They are loaded before the right-hand sides: load counters
-// retire in issue order, so the table build then waits only for these loads
-// while the right-hand sides are still in flight.  CR rows per thread cover
-// the tile when S >= M / CR; rows beyond that are loaded by a plain loop.
+// Coefficient rows held in registers per thread (tile rows P*M over S*P
+// threads: M/S rows each; rows beyond CR per thread are loaded late).
 template <int M>
-struct CoefRegs {
-    static constexpr int CR = M >= 32 ? 2 : 1;
-    double a[CR], b[CR], c[CR];
-};
-
-template <typename T, int M>
-__device__ __forceinline__ void coef_prefetch(const Coef &coef, int64_t n, int tid,
-                                              CoefRegs<M> &cr) {
-    const T *A = (const T *)coef.a, *B = (const T *)coef.b, *C = (const T *)coef.c;
-#pragma unroll
-    for (int i = 0; i < CoefRegs<M>::CR; ++i) {
-        const int64_t r = tid + (int64_t)i * blockDim.x;
-        const int64_t rc = r < n ? r : n - 1;   // rows past n are identity padding
-        cr.a[i] = (double)A[rc];
-        cr.b[i] = (double)B[rc];
-        cr.c[i] = (double)C[rc];
-    }
-}
+constexpr int shared_cr() { return M >= 32 ? 2 : 1; }
 
 // Right-hand sides of a lane's M rows in a strided layout, loaded without
 // branches so that the loads form one straight run behind the coefficient
@@ -123,7 +103,7 @@ __device__ __forceinline__ void load_rows(const T *d, const LaneSys &sys, int64_
 template <typename T, typename CT, int M>
 __device__ __forceinline__ void shared_tables(const Coef &coef, int64_t n, const SharedLds &L,
                                               char *base, int tid, int s, int p, int P,
-                                              const CoefRegs<M> &cr, bool &bad) {
+                                              const dev::RowRegs<shared_cr<M>()> &cr, bool &bad) {
     const int r0 = p * M;
     const int pitch = M + 1;
     T *G = reinterpret_cast<T *>(base + L.g);
@@ -138,28 +118,8 @@ __device__ __forceinline__ void shared_tables(const Coef &coef, int64_t n, const
     double *QC = QA + L.nsteps * 2 * P, *QB = QC + L.nsteps * 2 * P;
     // coefficient tables, one lane per partition (FP64 arithmetic), from a
     //    copy of the tile's coefficient rows in LDS (corners and padding removed)
-    {
-        double *CO = reinterpret_cast<double *>(base + L.co);
-        const int R = P * M;
-#pragma unroll
-        for (int i = 0; i < CoefRegs<M>::CR; ++i) {
-            const int r = tid + i * (int)blockDim.x;
-            if (r < R) {
-                const bool in = r < n;
-                CO[r] = in && r > 0 ? cr.a[i] : 0.0;
-                CO[R + r] = in ? cr.b[i] : 1.0;
-                CO[2 * R + r] = in && r < n - 1 ? cr.c[i] : 0.0;
-            }
-        }
-        const CT *A = (const CT *)coef.a, *B = (const CT *)coef.b, *C = (const CT *)coef.c;
-        for (int r = tid + CoefRegs<M>::CR * (int)blockDim.x; r < R; r += blockDim.x) {
-            const bool in = r < n;
-            CO[r] = in && r > 0 ? (double)A[r] : 0.0;
-            CO[R + r] = in ? (double)B[r] : 1.0;
-            CO[2 * R + r] = in && r < n - 1 ? (double)C[r] : 0.0;
-        }
-        __syncthreads();
-    }
+    dev::rows_commit<CT, shared_cr<M>()>(reinterpret_cast<double *>(base + L.co), coef, n, P * M,
+                                         cr);
     if (s == 0) {
         const double *CO = reinterpret_cast<const double *>(base + L.co);
         const int R = P * M;
@@ -338,27 +298,34 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
 
     // 1. coefficient rows, then the right-hand sides of this lane's rows (in
     //    flight while the tables are built)
-    CoefRegs<M> cr;
-    coef_prefetch<T, M>(coef, n, tid, cr);
+    dev::RowRegs<shared_cr<M>()> cr;
+    dev::rows_prefetch<T, shared_cr<M>()>(coef, n, cr);
     __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the right-hand sides
     T dv[M];
+    T *stg = reinterpret_cast<T *>(base + shared_stage_off(L));
+    TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, sizeof(T), M, P, S));
+    const float invR = 1.0f / (float)(P * M);
     if constexpr (!CONTIG) {
         load_rows<T, M>(d, sys, map.row_stride, r0, dv);
     } else {
-        const int R = P * M;
-        T *stg = reinterpret_cast<T *>(base + shared_stage_off(L));
-        TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, sizeof(T), M, P, S));
         if (tid < S) {
             const LaneSys q = dev::lane_system(map, k0 + tid);
             tsys[tid].base = q.base;
             tsys[tid].nrows = q.nrows;
         }
-        dev::stage_in<T, M>(stg, tsys, d, T(0), S, R, R + 1, 1.0f / (float)R, s, r0, dv);
+        __syncthreads();
+        dev::stage_load<T, M>(tsys, d, S, P * M, invR, dv);
     }
 
     // 2-3. coefficient tables and the interface PCR history
     bool bad = false;
     shared_tables<T, T, M>(coef, n, L, base, tid, s, p, P, cr, bad);
+    if constexpr (CONTIG) {
+        T ld[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) ld[j] = dv[j];
+        dev::stage_put<T, M>(stg, tsys, T(0), S, P * M, P * M + 1, invR, s, r0, ld, dv);
+    }
 
     // 4. Stage A on this lane's right-hand sides
     const T *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch;
@@ -398,10 +365,7 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
                 if (j < rows_here) px[j * rs] = dv[j];
         }
     } else {
-        const int R = P * M;
-        T *stg = reinterpret_cast<T *>(base + shared_stage_off(L));
-        TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, sizeof(T), M, P, S));
-        dev::stage_out<T, M>(stg, tsys, x, S, R, R + 1, 1.0f / (float)R, s, r0, dv);
+        dev::stage_out<T, M>(stg, tsys, x, S, P * M, P * M + 1, invR, s, r0, dv);
     }
     if (bad) atomicOr(err, 1);
 }
@@ -441,24 +405,32 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
     const int xpitch = 2 * P + 1;
     const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
 
-    CoefRegs<M> cr;
-    coef_prefetch<double, M>(coef, n, tid, cr);
+    dev::RowRegs<shared_cr<M>()> cr;
+    dev::rows_prefetch<double, shared_cr<M>()>(coef, n, cr);
     __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the right-hand sides
     double dv[M];
+    double *stg = reinterpret_cast<double *>(base + shared_stage_off(L));
+    TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, 8, M, P, S));
+    const float invR = 1.0f / (float)R;
     if constexpr (!CONTIG) {
         load_rows<double, M>(d, sys, map.row_stride, r0, dv);
     } else {
-        double *stg = reinterpret_cast<double *>(base + shared_stage_off(L));
-        TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, 8, M, P, S));
         if (tid < S) {
             const LaneSys q = dev::lane_system(map, k0 + tid);
             tsys[tid].base = q.base;
             tsys[tid].nrows = q.nrows;
         }
-        dev::stage_in<double, M>(stg, tsys, d, 0.0, S, R, R + 1, 1.0f / (float)R, s, r0, dv);
+        __syncthreads();
+        dev::stage_load<double, M>(tsys, d, S, R, invR, dv);
     }
     bool bad = false;
     shared_tables<float, double, M>(coef, n, L, base, tid, s, p, P, cr, bad);
+    if constexpr (CONTIG) {
+        double ld[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) ld[j] = dv[j];
+        dev::stage_put<double, M>(stg, tsys, 0.0, S, R, R + 1, invR, s, r0, ld, dv);
+    }
 
     const float *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch;
     const float *ah = AH + p * pitch, *ch = CH + p * pitch;
@@ -538,9 +510,7 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
         for (int j = 0; j < M; ++j)
             if (j < rows_here) px[j * rs] = xv[j];
     } else {
-        double *stg = reinterpret_cast<double *>(base + shared_stage_off(L));
-        TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, 8, M, P, S));
-        dev::stage_out<double, M>(stg, tsys, x, S, R, R + 1, 1.0f / (float)R, s, r0, xv);
+        dev::stage_out<double, M>(stg, tsys, x, S, R, R + 1, invR, s, r0, xv);
     }
 }
 

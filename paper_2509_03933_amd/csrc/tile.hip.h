@@ -296,21 +296,149 @@ struct TileSysLds {
     int64_t nrows;
 };
 
+// A tile's rows of a shared operator (three coefficient arrays of length n),
+// copied to LDS in two steps.  rows_prefetch loads rows tid + i*blockDim
+// (i < CR) into registers, before the tile's right-hand sides are loaded:
+// load counters retire in issue order, so whatever waits on these rows then
+// leaves the right-hand sides in flight.  rows_commit writes them (and loads
+// any rows beyond CR per thread) as CO[0..R) = a, CO[R..2R) = b,
+// CO[2R..3R) = c with the corners removed and identity rows past n, then
+// waits at a barrier.  Every thread of the block calls both.
+template <int CR>
+struct RowRegs {
+    double a[CR], b[CR], c[CR];
+};
+
+template <typename T, int CR>
+__device__ __forceinline__ void rows_prefetch(const Coef &coef, int64_t n, RowRegs<CR> &rr) {
+    const T *A = (const T *)coef.a, *B = (const T *)coef.b, *C = (const T *)coef.c;
+#pragma unroll
+    for (int i = 0; i < CR; ++i) {
+        const int64_t r = threadIdx.x + (int64_t)i * blockDim.x;
+        const int64_t rc = r < n ? r : n - 1;
+        rr.a[i] = (double)A[rc];
+        rr.b[i] = (double)B[rc];
+        rr.c[i] = (double)C[rc];
+    }
+}
+
+template <typename T, int CR>
+__device__ __forceinline__ void rows_commit(double *CO, const Coef &coef, int64_t n, int R,
+                                            const RowRegs<CR> &rr) {
+    const int nth = (int)blockDim.x;
+#pragma unroll
+    for (int i = 0; i < CR; ++i) {
+        const int r = (int)threadIdx.x + i * nth;
+        if (r < R) {
+            const bool in = r < n;
+            CO[r] = in && r > 0 ? rr.a[i] : 0.0;
+            CO[R + r] = in ? rr.b[i] : 1.0;
+            CO[2 * R + r] = in && r < n - 1 ? rr.c[i] : 0.0;
+        }
+    }
+    const T *A = (const T *)coef.a, *B = (const T *)coef.b, *C = (const T *)coef.c;
+    for (int r = (int)threadIdx.x + CR * nth; r < R; r += nth) {
+        const bool in = r < n;
+        CO[r] = in && r > 0 ? (double)A[r] : 0.0;
+        CO[R + r] = in ? (double)B[r] : 1.0;
+        CO[2 * R + r] = in && r < n - 1 ? (double)C[r] : 0.0;
+    }
+    __syncthreads();
+}
+
+// The thread index as a value the compiler cannot see through: index math
+// derived from it is then recomputed in each staging call instead of being
+// kept live in registers from one call to the next.
+__device__ __forceinline__ int opaque_tid() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// Tile element e (0 <= e < S*R, rows of a system contiguous) as (system,
+// row): float reciprocal of R with a one-step correction.
+__device__ __forceinline__ void split_elem(int e, int R, float invR, int &se, int &re) {
+    se = (int)(((float)e + 0.5f) * invR);
+    re = e - se * R;
+    if (re < 0) { --se; re += R; } else if (re >= R) { ++se; re -= R; }
+}
+
 // Cooperative coalesced copy of one tile array (S systems x R rows, rows
-// contiguous in memory) into LDS, then each lane picks its M rows.
+// contiguous in memory) into the lanes' registers, in two steps so that the
+// loads of several arrays can all be in flight at once:
+//   stage_load issues this thread's M loads (elements e = tid + i*blockDim)
+//     with no branches: rows past a system's end read its last row and lanes
+//     past the last system read the array's start (both replaced in stage_put);
+//   stage_put writes them to LDS (identity value in the padding) and gives
+//     each lane its M rows.
+// The tile's S*P lanes call both (blockDim.x * M == S * R), after a barrier
+// that makes the tile's system table visible.
 template <typename T, int M>
+__device__ __forceinline__ void stage_load(const TileSysLds *tsys, const T *src, int S, int R,
+                                           float invR, T (&v)[M]) {
+    const int tot = S * R;
+    const int tid = opaque_tid();
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        const int e0 = tid + i * (int)blockDim.x;
+        const int e = e0 < tot ? e0 : tot - 1;
+        int se, re;
+        split_elem(e, R, invR, se, re);
+        const int64_t nr = tsys[se].nrows;
+        const int64_t rr = re < nr ? re : (nr > 0 ? nr - 1 : 0);
+        v[i] = src[(nr > 0 ? tsys[se].base : 0) + rr];
+    }
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void stage_put(T *stg, const TileSysLds *tsys, T ident, int S, int R,
+                                          int pitch, float invR, int s, int r0, const T (&v)[M],
+                                          T (&dst)[M]) {
+    const int tot = S * R;
+    __syncthreads();   // the staging buffer is free
+    const int tid = opaque_tid();
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        const int e = tid + i * (int)blockDim.x;
+        if (e < tot) {
+            int se, re;
+            split_elem(e, R, invR, se, re);
+            stg[se * pitch + re] = re < tsys[se].nrows ? v[i] : ident;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < M; ++j) dst[j] = stg[s * pitch + r0 + j];
+}
+
+// One array in one pass (barrier for the system table included), with K of
+// a thread's loads in flight at a time: each group of K goes to LDS before
+// the next is issued, which bounds the registers that hold their addresses.
+template <typename T, int M, int K = 4>
 __device__ __forceinline__ void stage_in(T *stg, const TileSysLds *tsys, const T *src, T ident,
                                          int S, int R, int pitch, float invR, int s, int r0,
                                          T (&dst)[M]) {
-    const int nthr = blockDim.x;
+    static_assert(M % K == 0, "K must divide M");
+    const int tot = S * R;
     __syncthreads();
-    for (int e = threadIdx.x; e < S * R; e += nthr) {
-        int se = (int)(((float)e + 0.5f) * invR);
-        int re = e - se * R;
-        if (re < 0) { --se; re += R; } else if (re >= R) { ++se; re -= R; }
-        T v = ident;
-        if (re < tsys[se].nrows) v = src[tsys[se].base + re];
-        stg[se * pitch + re] = v;
+    const int tid = opaque_tid();
+#pragma unroll
+    for (int c = 0; c < M; c += K) {
+        T v[K];
+        int se[K], re[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e0 = tid + (c + k) * (int)blockDim.x;
+            split_elem(e0 < tot ? e0 : tot - 1, R, invR, se[k], re[k]);
+            const int64_t nr = tsys[se[k]].nrows;
+            const int64_t rr = re[k] < nr ? re[k] : (nr > 0 ? nr - 1 : 0);
+            v[k] = src[(nr > 0 ? tsys[se[k]].base : 0) + rr];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e0 = tid + (c + k) * (int)blockDim.x;
+            if (e0 < tot) stg[se[k] * pitch + re[k]] = re[k] < tsys[se[k]].nrows ? v[k] : ident;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -326,9 +454,8 @@ __device__ __forceinline__ void stage_out(T *stg, const TileSysLds *tsys, T *dst
     for (int j = 0; j < M; ++j) stg[s * pitch + r0 + j] = src[j];
     __syncthreads();
     for (int e = threadIdx.x; e < S * R; e += nthr) {
-        int se = (int)(((float)e + 0.5f) * invR);
-        int re = e - se * R;
-        if (re < 0) { --se; re += R; } else if (re >= R) { ++se; re -= R; }
+        int se, re;
+        split_elem(e, R, invR, se, re);
         if (re < tsys[se].nrows) dst_g[tsys[se].base + re] = stg[se * pitch + re];
     }
 }
