@@ -14,8 +14,8 @@ Other workloads (measurement of the remaining configurations):
   partitioned  1024^3 per-row z-lines, tdma_solve_partitioned (P = 8, 4 streams)
   poisson      1024^2 FFT modes x n = 1024, shared operator + shift, FP64 fused
                and FP32+refine, plus the pinned (0,0) mode
-  sweeps       768x512x1536 x->y->z ADI sweeps + 10,000 ragged systems in one
-               hipGraph-captured persistent launch
+  sweeps       768x512x1536 x->y->z ADI sweeps + 10,000 ragged systems recorded
+               into one hipGraph (dependent chain + independent ragged branch)
   plain        64 contiguous systems of n = 256
 
 Prints ONE JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
@@ -40,7 +40,8 @@ KERNEL_SOURCES = {
     "k_fused": [CSRC + "fused.hip", CSRC + "fused_tile.hip.h", CSRC + "tile.hip.h"],
     "k_refine": [CSRC + "refine.hip", CSRC + "tile.hip.h"],
     "k_stage_a": [CSRC + "partitioned.hip", CSRC + "tile.hip.h"],
-    "k_persist": [CSRC + "persist.hip", CSRC + "fused_tile.hip.h", CSRC + "tile.hip.h"],
+    "graph": [CSRC + "graph.cpp", CSRC + "fused.hip", CSRC + "shared.hip", CSRC + "fused_tile.hip.h",
+              CSRC + "tile.hip.h"],
 }
 
 
@@ -309,7 +310,7 @@ def bench_sweeps(args):
                 "config": {"workload": f"adi_sweeps_{nx}x{ny}x{nz}_plus_10000_ragged",
                            "entry_point": "tdma_graph_launch"},
                 "max_rel_err_vs_oracle": worst,
-                "roofline": roofline(bytes_step, ms, "k_persist", f"k_persist_sweeps{nx}x{ny}x{nz}_f64")}
+                "roofline": roofline(bytes_step, ms, "graph", f"graph_sweeps{nx}x{ny}x{nz}_f64")}
 
 
 def bench_plain(args):

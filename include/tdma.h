@@ -185,13 +185,21 @@ int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *coeffs, con
                        void *stream);
 
 /*
- * Batching form: a list of solves recorded once into a hipGraph whose body
- * is ONE persistent kernel.  Work items are cut into tiles; tiles of an item
- * with `after` >= 0 wait, on the device, until every tile of item `after`
- * has finished (e.g. the y-sweep of an ADI step reads the x-sweep's output),
- * while independent items (a ragged batch) fill the gaps.  Items use the
- * same layout/coefficient rules as tdma_solve_batched; all items share one
- * dtype.  Pointers are captured at creation and must stay valid.
+ * Batching form: a list of solves recorded once into a hipGraph, replayed as
+ * one submission by tdma_graph_launch.  Each item is planned and launched
+ * exactly as tdma_solve_batched would (same kernels, tile shapes and
+ * results, bit for bit).  An item with `after` >= 0 reads item `after`'s
+ * output (e.g. the y-sweep of an ADI step reads the x-sweep's): such items
+ * and the items they read run in item order on the graph's main branch,
+ * ordered by graph edges; independent items (a ragged batch) run on a
+ * parallel branch beside them.  All items share one dtype.  Pointers and the
+ * ragged offsets' contents are captured at creation (the offsets are copied
+ * to device memory the graph owns); the data pointers must stay valid while
+ * the graph is used.  Destroy graphs before tdma_shutdown.
+ * Errors: EINVAL for an invalid item (as tdma_solve_batched) or an `after`
+ * that does not name an earlier item; EUNSUPPORTED for an item the fused
+ * path cannot take; EHIP/ENOMEM from capture or allocation.  Numerical
+ * errors of a replay are reported by tdma_check.
  */
 typedef struct tdma_work_item {
     tdma_layout layout;

@@ -49,10 +49,7 @@ void DeviceCtx::release() {
     int cur = -1;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(dev);
-    for (auto &kv : ragged_cache) {
-        if (kv.second.d_offsets) (void)hipFree(kv.second.d_offsets);
-        if (kv.second.d_list) (void)hipFree(kv.second.d_list);
-    }
+    for (auto &kv : ragged_cache) free_ragged_plan(&kv.second);
     ragged_cache.clear();
     for (auto &w : workspaces) (void)hipFree(w.ptr);
     workspaces.clear();
@@ -245,20 +242,10 @@ bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileS
 
 // Ragged layout: systems are bucketed by the power-of-two partition count
 // they need; one launch per non-empty bucket (contiguous rows, LDS-staged).
-int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, hipStream_t st,
-                const RaggedPlan **out) {
+// build_ragged_plan allocates the plan's device tables and uploads them
+// synchronously; the caller owns them (free_ragged_plan).
+int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out) {
     const int64_t nsys = L->nsys0;
-    uint64_t h = 1469598103934665603ull;
-    for (int64_t k = 0; k <= nsys; ++k) {
-        h ^= (uint64_t)L->offsets[k];
-        h *= 1099511628211ull;
-    }
-    h ^= (uint64_t)dtype * 0x9E3779B97F4A7C15ull;
-    auto it = ctx->ragged_cache.find(h);
-    if (it != ctx->ragged_cache.end() && it->second.nsys == nsys) {
-        *out = &it->second;
-        return TDMA_OK;
-    }
     const int M = dtype == TDMA_F64 ? 16 : 32;
     std::map<int, std::vector<int32_t>> buckets;
     for (int64_t k = 0; k < nsys; ++k) {
@@ -292,17 +279,43 @@ int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, hipStream_t st,
     if (e != hipSuccess) return fail(TDMA_ENOMEM, "ragged offsets");
     e = hipMalloc(&rp.d_list, std::max<size_t>(1, all.size()) * sizeof(int32_t));
     if (e != hipSuccess) { (void)hipFree(rp.d_offsets); return fail(TDMA_ENOMEM, "ragged list"); }
-    e = hipMemcpyAsync(rp.d_offsets, L->offsets, (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(rp.d_list, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    e = hipMemcpy(rp.d_offsets, L->offsets, (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !all.empty())
+        e = hipMemcpy(rp.d_list, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        (void)hipFree(rp.d_offsets);
-        (void)hipFree(rp.d_list);
+        free_ragged_plan(&rp);
         return hip_fail(e, "upload ragged plan");
     }
+    *out = rp;
+    return TDMA_OK;
+}
+
+void free_ragged_plan(RaggedPlan *rp) {
+    if (rp->d_offsets) (void)hipFree(rp->d_offsets);
+    if (rp->d_list) (void)hipFree(rp->d_list);
+    rp->d_offsets = nullptr;
+    rp->d_list = nullptr;
+}
+
+// Plans of recently seen ragged layouts, keyed by a hash of the offsets.
+int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, const RaggedPlan **out) {
+    const int64_t nsys = L->nsys0;
+    uint64_t h = 1469598103934665603ull;
+    for (int64_t k = 0; k <= nsys; ++k) {
+        h ^= (uint64_t)L->offsets[k];
+        h *= 1099511628211ull;
+    }
+    h ^= (uint64_t)dtype * 0x9E3779B97F4A7C15ull;
+    auto it = ctx->ragged_cache.find(h);
+    if (it != ctx->ragged_cache.end() && it->second.nsys == nsys) {
+        *out = &it->second;
+        return TDMA_OK;
+    }
+    RaggedPlan rp;
+    int rc = build_ragged_plan(L, dtype, &rp);
+    if (rc != TDMA_OK) return rc;
     if (ctx->ragged_cache.size() >= 8) {
-        for (auto &kv : ctx->ragged_cache) { (void)hipFree(kv.second.d_offsets); (void)hipFree(kv.second.d_list); }
+        for (auto &kv : ctx->ragged_cache) free_ragged_plan(&kv.second);
         ctx->ragged_cache.clear();
     }
     auto res = ctx->ragged_cache.emplace(h, rp);
@@ -334,55 +347,78 @@ Coef make_coef(const tdma_coeffs *C) {
     return c;
 }
 
-int run_fused(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dtype, const void *d,
-              void *x, hipStream_t st, const TileShape *force) {
+// One launch per bucket of a ragged plan.
+int launch_ragged(const RaggedPlan &rp, const tdma_layout *L, const tdma_coeffs *C, int dtype,
+                  const void *d, void *x, int *err, hipStream_t st) {
     const Coef coef = make_coef(C);
-    if (L->offsets) {
-        const RaggedPlan *rp = nullptr;
-        int rc = plan_ragged(ctx, L, dtype, st, &rp);
-        if (rc != TDMA_OK) return rc;
-        for (const auto &b : rp->buckets) {
-            SysMap m = make_map(L);
-            m.n = (int64_t)b.shape.P * b.shape.M;
-            m.nsys = b.count;
-            m.offsets = rp->d_offsets;
-            m.sys_list = rp->d_list + b.first;
-            hipError_t e = launch_fused(dtype, m, coef, b.shape, d, x, ctx->d_err, st);
-            if (e != hipSuccess) return hip_fail(e, "fused launch (ragged)");
-        }
-        return TDMA_OK;
+    for (const auto &b : rp.buckets) {
+        SysMap m = make_map(L);
+        m.n = (int64_t)b.shape.P * b.shape.M;
+        m.nsys = b.count;
+        m.offsets = rp.d_offsets;
+        m.sys_list = rp.d_list + b.first;
+        hipError_t e = launch_fused(dtype, m, coef, b.shape, d, x, err, st);
+        if (e != hipSuccess) return hip_fail(e, "fused launch (ragged)");
     }
-    const SysMap m = make_map(L);
-    if (m.nsys == 0) return TDMA_OK;
+    return TDMA_OK;
+}
+
+// Tile shape of a uniform layout: the forced shape, else the autotune cache,
+// else the built-in rules (shared-operator kernel first where it applies).
+int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dtype,
+                 const TileShape *force, TileShape *out) {
+    const int64_t nsys = L->nsys0 * L->nsys1;
     TileShape sh;
     const bool contig = L->row_stride == 1;
     const bool shared_op = C->mode == TDMA_COEF_SHARED && C->b_shift == nullptr;
     if (force) {
         sh = *force;
     } else if (!lookup_tuned(ctx->dev, L, C, dtype, &sh)) {
-        if (!(shared_op && default_shared_shape(dtype, L->n, m.nsys, contig, &sh)) &&
-            !default_shape(dtype, L->n, m.nsys, contig, &sh))
+        if (!(shared_op && default_shared_shape(dtype, L->n, nsys, contig, &sh)) &&
+            !default_shape(dtype, L->n, nsys, contig, &sh))
             return fail(TDMA_EUNSUPPORTED, "n = %lld is too long for the fused path (use "
                         "tdma_solve_partitioned)", (long long)L->n);
     }
     if ((int64_t)sh.P * sh.M < L->n)
         return fail(TDMA_EINVAL, "tile shape M=%d P=%d S=%d does not cover n=%lld", sh.M, sh.P,
                     1 << sh.S_log2, (long long)L->n);
-    hipError_t e;
     if (sh.kernel == 1) {
         if (!shared_op || !shared_supported(dtype, sh))
             return fail(TDMA_EINVAL, "the shared-operator kernel needs shared coefficients without "
                         "a shift and a power-of-two P <= 64 (M=%d P=%d S=%d)", sh.M, sh.P,
                         1 << sh.S_log2);
-        e = launch_shared(dtype, m, coef, sh, d, x, ctx->d_err, st);
-    } else {
-        if (!fused_supported(dtype, sh))
-            return fail(TDMA_EINVAL, "unsupported tile shape M=%d P=%d S=%d", sh.M, sh.P,
-                        1 << sh.S_log2);
-        e = launch_fused(dtype, m, coef, sh, d, x, ctx->d_err, st);
+    } else if (!fused_supported(dtype, sh)) {
+        return fail(TDMA_EINVAL, "unsupported tile shape M=%d P=%d S=%d", sh.M, sh.P,
+                    1 << sh.S_log2);
     }
+    *out = sh;
+    return TDMA_OK;
+}
+
+int launch_uniform(const TileShape &sh, const tdma_layout *L, const tdma_coeffs *C, int dtype,
+                   const void *d, void *x, int *err, hipStream_t st) {
+    const SysMap m = make_map(L);
+    if (m.nsys == 0) return TDMA_OK;
+    const Coef coef = make_coef(C);
+    const hipError_t e = sh.kernel == 1 ? launch_shared(dtype, m, coef, sh, d, x, err, st)
+                                        : launch_fused(dtype, m, coef, sh, d, x, err, st);
     if (e != hipSuccess) return hip_fail(e, "fused launch");
     return TDMA_OK;
+}
+
+int run_fused(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dtype, const void *d,
+              void *x, hipStream_t st, const TileShape *force) {
+    if (L->offsets) {
+        const RaggedPlan *rp = nullptr;
+        int rc = plan_ragged(ctx, L, dtype, &rp);
+        if (rc != TDMA_OK) return rc;
+        return launch_ragged(*rp, L, C, dtype, d, x, ctx->d_err, st);
+    }
+    if (L->nsys0 * L->nsys1 == 0) return TDMA_OK;
+    TileShape sh;
+    int rc = plan_uniform(ctx, L, C, dtype, force, &sh);
+    if (rc != TDMA_OK) return rc;
+    return launch_uniform(sh, L, C, dtype, d, x, ctx->d_err, st);
 }
 
 }  // namespace tdma
@@ -461,8 +497,6 @@ int tdma_check(void *stream) {
     if (flag[0]) {
         e = hipMemset(ctx->d_err, 0, 4 * sizeof(int));
         if (e != hipSuccess) return hip_fail(e, "clear error flag");
-        if (flag[0] & 2)
-            return fail(TDMA_EHIP, "a batching-form dependency wait hit its bound (results invalid)");
         return fail(TDMA_ESINGULAR, "a kernel met a zero or non-finite pivot");
     }
     return TDMA_OK;

@@ -54,8 +54,15 @@ int validate(const tdma_layout *L, const tdma_coeffs *C, int dtype, const void *
 SysMap make_map(const tdma_layout *L);
 Coef make_coef(const tdma_coeffs *C);
 bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *out);
-int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, hipStream_t st,
-                const RaggedPlan **out);
+int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out);
+void free_ragged_plan(RaggedPlan *rp);
+int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, const RaggedPlan **out);
+int launch_ragged(const RaggedPlan &rp, const tdma_layout *L, const tdma_coeffs *C, int dtype,
+                  const void *d, void *x, int *err, hipStream_t st);
+int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dtype,
+                 const TileShape *force, TileShape *out);
+int launch_uniform(const TileShape &sh, const tdma_layout *L, const tdma_coeffs *C, int dtype,
+                   const void *d, void *x, int *err, hipStream_t st);
 int run_fused(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dtype, const void *d,
               void *x, hipStream_t st, const TileShape *force);
 

@@ -1,18 +1,30 @@
-// Batching form host side: plan the work items into tiles and a dependency-
-// ordered queue, then record [counter reset; persistent kernel] into a
-// hipGraph that tdma_graph_launch replays.
+// Batching form: a list of solves recorded once into a hipGraph that
+// tdma_graph_launch replays as one submission.
+//
+// Each item is planned exactly as tdma_solve_batched would plan it (tuned or
+// built-in tile shape, the shared-operator kernel where it applies, one
+// launch per length bucket of a ragged batch), and its launches are recorded
+// into the graph:
+//   - items that read another item's output, and the items they read, go on
+//     the main branch in item order, so a graph edge (kernel boundary) orders
+//     every item after the one it reads;
+//   - independent items go on a second branch forked from the start and
+//     joined at the end, so the GPU runs them beside the dependent chain and
+//     they fill its launch tails.
+// There is no device-side waiting between workgroups: ordering comes only
+// from the graph's edges.  Ragged plans (offsets and bucketed system lists)
+// are uploaded before capture into memory the graph owns.
 #include <algorithm>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "api_internal.h"
-#include "persist.h"
 
 struct tdma_graph {
     int dev = 0;
     int dtype = 0;
-    void *dmem = nullptr;          // descriptors, segments, counters
-    std::vector<void *> owned;     // device copies of ragged offsets and system lists
+    std::vector<tdma::RaggedPlan> ragged;   // device tables owned by the graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -24,30 +36,18 @@ void destroy_graph(tdma_graph *g) {
     if (!g) return;
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    for (void *p : g->owned) (void)hipFree(p);
-    if (g->dmem) (void)hipFree(g->dmem);
+    for (RaggedPlan &rp : g->ragged) free_ragged_plan(&rp);
     delete g;
 }
 
-// Tile of the persistent kernel: M rows per lane, P a power of two covering
-// n, S = 1024 / P systems.
-bool persist_shape(int64_t n, int dtype, bool contig, int *S_log2, int *P) {
-    const int M = persist_rows_per_lane();
-    int p = 1;
-    while ((int64_t)p * M < n) p <<= 1;
-    if (p > kPersistThreads) return false;
-    int s_log2 = 0;
-    while ((p << (s_log2 + 1)) <= kPersistThreads) ++s_log2;
-    TileShape sh;
-    sh.M = M;
-    sh.P = p;
-    sh.S_log2 = s_log2;
-    sh.contig = contig;
-    if (!fused_supported(dtype, sh) || fused_lds_bytes(dtype, sh) > 160 * 1024) return false;
-    *S_log2 = s_log2;
-    *P = p;
-    return true;
-}
+// One item's launches, planned before capture.
+struct ItemPlan {
+    bool ragged = false;
+    int ragged_index = -1;   // into tdma_graph::ragged
+    TileShape shape;
+    bool empty = false;
+    bool side = false;       // independent: recorded on the second branch
+};
 
 }  // namespace
 }  // namespace tdma
@@ -65,8 +65,6 @@ extern "C" int tdma_graph_create(const tdma_work_item *items, int nitems, int dt
         if (rc != TDMA_OK) return rc;
         if (items[i].after >= i || items[i].after < -1)
             return fail(TDMA_EINVAL, "item %d: after = %d must name an earlier item", i, items[i].after);
-        if (items[i].after >= 0 && items[items[i].after].layout.offsets)
-            return fail(TDMA_EUNSUPPORTED, "item %d depends on a ragged item", i);
     }
     DeviceCtx *ctx = nullptr;
     int rc = get_ctx(&ctx);
@@ -74,166 +72,88 @@ extern "C" int tdma_graph_create(const tdma_work_item *items, int nitems, int dt
     tdma_graph *g = new tdma_graph();
     g->dev = ctx->dev;
     g->dtype = dtype;
-    const int M = persist_rows_per_lane();
 
-    // 1. descriptors (ragged items become one descriptor per length class)
-    std::vector<WorkDesc> descs;
-    std::vector<int> item_desc(nitems, -1);
-    std::vector<bool> filler;          // independent of everything, nobody waits for it
+    // 1. plans (host validation of every item before anything is recorded)
     std::vector<bool> needed(nitems, false);
     for (int i = 0; i < nitems; ++i)
         if (items[i].after >= 0) needed[items[i].after] = true;
-    size_t lds = 0;
+    std::vector<ItemPlan> plans(nitems);
     for (int i = 0; i < nitems && rc == TDMA_OK; ++i) {
         const tdma_work_item &it = items[i];
-        const tdma_layout &L = it.layout;
-        WorkDesc wd;
-        std::memset(&wd, 0, sizeof wd);
-        wd.map = make_map(&L);
-        wd.coef = make_coef(&it.coeffs);
-        wd.d = it.d;
-        wd.x = it.x;
-        wd.like_d = it.coeffs.mode == TDMA_COEF_LIKE_D;
-        wd.shift = it.coeffs.b_shift != nullptr;
-        wd.after = it.after >= 0 ? item_desc[it.after] : -1;
-        const bool indep = it.after < 0 && !needed[i];
-        if (!L.offsets) {
-            if (wd.map.nsys == 0) continue;
-            wd.contig = L.row_stride == 1;
-            if (!persist_shape(L.n, dtype, wd.contig, &wd.S_log2, &wd.P)) {
-                rc = fail(TDMA_EUNSUPPORTED, "item %d: n = %lld is too long for the batching form",
-                          i, (long long)L.n);
-                break;
-            }
-            wd.ntiles = (wd.map.nsys + (1 << wd.S_log2) - 1) >> wd.S_log2;
-            item_desc[i] = (int)descs.size();
-            descs.push_back(wd);
-            filler.push_back(indep);
-        } else {
-            const int64_t nsys = L.nsys0;
-            std::vector<std::vector<int32_t>> cls(11);
-            for (int64_t k = 0; k < nsys; ++k) {
-                const int64_t len = L.offsets[k + 1] - L.offsets[k];
-                int c = 0;
-                while (((int64_t)1 << c) * M < len) ++c;
-                if (c > 10) { rc = fail(TDMA_EUNSUPPORTED, "item %d: a ragged system is too long", i); break; }
-                cls[c].push_back((int32_t)k);
-            }
+        ItemPlan &pl = plans[i];
+        pl.side = it.after < 0 && !needed[i];
+        if (it.layout.offsets) {
+            pl.ragged = true;
+            if (it.layout.nsys0 == 0) { pl.empty = true; continue; }
+            RaggedPlan rp;
+            rc = build_ragged_plan(&it.layout, dtype, &rp);
             if (rc != TDMA_OK) break;
-            int64_t *doff = nullptr;
-            if (hipMalloc(&doff, (nsys + 1) * sizeof(int64_t)) != hipSuccess ||
-                hipMemcpy(doff, L.offsets, (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
-                rc = fail(TDMA_ENOMEM, "ragged offsets");
-                break;
-            }
-            g->owned.push_back(doff);
-            for (int c = 0; c <= 10 && rc == TDMA_OK; ++c) {
-                if (cls[c].empty()) continue;
-                int32_t *dl = nullptr;
-                if (hipMalloc(&dl, cls[c].size() * sizeof(int32_t)) != hipSuccess ||
-                    hipMemcpy(dl, cls[c].data(), cls[c].size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
-                    rc = fail(TDMA_ENOMEM, "ragged system list");
-                    break;
-                }
-                g->owned.push_back(dl);
-                WorkDesc rd = wd;
-                rd.contig = 1;
-                rd.P = 1 << c;
-                rd.S_log2 = 0;
-                while ((rd.P << (rd.S_log2 + 1)) <= kPersistThreads) ++rd.S_log2;
-                rd.map.n = (int64_t)rd.P * M;
-                rd.map.nsys = (int64_t)cls[c].size();
-                rd.map.offsets = doff;
-                rd.map.sys_list = dl;
-                rd.ntiles = (rd.map.nsys + (1 << rd.S_log2) - 1) >> rd.S_log2;
-                TileShape sh;
-                sh.M = M; sh.P = rd.P; sh.S_log2 = rd.S_log2; sh.contig = true;
-                if (!fused_supported(dtype, sh) || fused_lds_bytes(dtype, sh) > 160 * 1024) {
-                    rc = fail(TDMA_EUNSUPPORTED, "item %d: ragged tile does not fit", i);
-                    break;
-                }
-                descs.push_back(rd);
-                filler.push_back(true);
+            pl.ragged_index = (int)g->ragged.size();
+            g->ragged.push_back(rp);
+        } else {
+            if (it.layout.nsys0 * it.layout.nsys1 == 0) { pl.empty = true; continue; }
+            rc = plan_uniform(ctx, &it.layout, &it.coeffs, dtype, nullptr, &pl.shape);
+            if (rc != TDMA_OK) {
+                const std::string why = tdma_last_error();
+                rc = fail(rc, "item %d: %s", i, why.c_str());
             }
         }
     }
-    if (rc == TDMA_OK && (descs.empty() || descs.size() > (size_t)kMaxWorkDescs))
-        rc = fail(descs.empty() ? TDMA_EINVAL : TDMA_EUNSUPPORTED, "%zu work descriptors (1..%d)",
-                  descs.size(), kMaxWorkDescs);
     if (rc != TDMA_OK) { destroy_graph(g); return rc; }
-    for (const WorkDesc &wd : descs) {
-        TileShape sh;
-        sh.M = M; sh.P = wd.P; sh.S_log2 = wd.S_log2; sh.contig = wd.contig != 0;
-        lds = std::max(lds, fused_lds_bytes(dtype, sh));
+    bool any_side = false, any_main = false;
+    for (const ItemPlan &pl : plans) {
+        if (pl.empty) continue;
+        (pl.side ? any_side : any_main) = true;
     }
 
-    // 2. occupancy: a grid every block of which can be resident
-    int per_cu = 0;
-    hipError_t e = persist_occupancy(dtype, lds, &per_cu);
-    if (e != hipSuccess || per_cu < 1) {
-        destroy_graph(g);
-        return e != hipSuccess ? hip_fail(e, "occupancy") : fail(TDMA_EUNSUPPORTED, "persistent block does not fit a CU");
+    // 2. record: main branch on `cap`, independent items on `side`
+    hipStream_t cap = nullptr, side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    if (e != hipSuccess) rc = hip_fail(e, "graph streams");
+    bool capturing = false;
+    if (rc == TDMA_OK) {
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) rc = hip_fail(e, "begin capture");
+        else capturing = true;
     }
-    const int grid = per_cu * ctx->num_cus;
-
-    // 3. queue order: dependent descriptors in order, fillers cut into chunks
-    //    placed right after each descriptor that someone waits for
-    std::vector<WorkSeg> segs;
-    int64_t pos = 0;
-    std::vector<int64_t> filler_next(descs.size(), 0);
-    auto push = [&](int di, int64_t begin, int64_t count) {
-        if (count <= 0) return;
-        segs.push_back(WorkSeg{di, begin, count, pos});
-        pos += count;
-    };
-    auto push_fillers = [&](int64_t budget) {
-        for (size_t di = 0; di < descs.size() && budget > 0; ++di) {
-            if (!filler[di]) continue;
-            const int64_t take = std::min(budget, descs[di].ntiles - filler_next[di]);
-            push((int)di, filler_next[di], take);
-            filler_next[di] += take;
-            budget -= take;
-        }
-    };
-    for (size_t di = 0; di < descs.size(); ++di) {
-        if (filler[di]) continue;
-        push((int)di, 0, descs[di].ntiles);
-        bool waited_on = false;
-        for (const WorkDesc &o : descs) waited_on |= o.after == (int)di;
-        if (waited_on) push_fillers(2 * (int64_t)grid);
+    if (rc == TDMA_OK && any_side && any_main) {
+        e = hipEventRecord(fork, cap);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+        if (e != hipSuccess) rc = hip_fail(e, "fork");
     }
-    push_fillers(INT64_MAX);
-    const int64_t total_tiles = pos;
-
-    // 4. device tables
-    const size_t desc_b = (descs.size() * sizeof(WorkDesc) + 255) & ~(size_t)255;
-    const size_t seg_b = (segs.size() * sizeof(WorkSeg) + 255) & ~(size_t)255;
-    e = hipMalloc(&g->dmem, desc_b + seg_b + sizeof(WorkCounters));
-    if (e != hipSuccess) { destroy_graph(g); return fail(TDMA_ENOMEM, "graph tables"); }
-    WorkDesc *d_desc = (WorkDesc *)g->dmem;
-    WorkSeg *d_seg = (WorkSeg *)((char *)g->dmem + desc_b);
-    WorkCounters *d_ctr = (WorkCounters *)((char *)g->dmem + desc_b + seg_b);
-    e = hipMemcpy(d_desc, descs.data(), descs.size() * sizeof(WorkDesc), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_seg, segs.data(), segs.size() * sizeof(WorkSeg), hipMemcpyHostToDevice);
-    if (e != hipSuccess) { destroy_graph(g); return hip_fail(e, "graph tables upload"); }
-
-    // 5. record [reset; persistent kernel] into a graph
-    hipStream_t cap;
-    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (e != hipSuccess) { destroy_graph(g); return hip_fail(e, "capture stream"); }
-    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = launch_persist_reset(d_ctr, (int)descs.size(), cap);
-    if (e == hipSuccess)
-        e = launch_persist(dtype, grid, lds, d_desc, d_seg, (int)segs.size(), total_tiles, d_ctr,
-                           ctx->d_err, cap);
+    for (int i = 0; i < nitems && rc == TDMA_OK; ++i) {
+        const ItemPlan &pl = plans[i];
+        if (pl.empty) continue;
+        const tdma_work_item &it = items[i];
+        hipStream_t st = pl.side && any_main ? side : cap;
+        if (pl.ragged)
+            rc = launch_ragged(g->ragged[pl.ragged_index], &it.layout, &it.coeffs, dtype, it.d, it.x,
+                               ctx->d_err, st);
+        else
+            rc = launch_uniform(pl.shape, &it.layout, &it.coeffs, dtype, it.d, it.x, ctx->d_err, st);
+    }
+    if (rc == TDMA_OK && any_side && any_main) {
+        e = hipEventRecord(join, side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cap, join, 0);
+        if (e != hipSuccess) rc = hip_fail(e, "join");
+    }
     hipGraph_t graph = nullptr;
-    hipError_t e2 = hipStreamEndCapture(cap, &graph);
-    if (e == hipSuccess) e = e2;
-    (void)hipStreamDestroy(cap);
-    if (e != hipSuccess) {
+    if (capturing) {
+        e = hipStreamEndCapture(cap, &graph);
+        if (rc == TDMA_OK && e != hipSuccess) rc = hip_fail(e, "end capture");
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (rc != TDMA_OK) {
         if (graph) (void)hipGraphDestroy(graph);
         destroy_graph(g);
-        return hip_fail(e, "graph capture");
+        return rc;
     }
     g->graph = graph;
     e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);

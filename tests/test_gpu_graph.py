@@ -1,11 +1,12 @@
-"""Batching form: one persistent work-queue kernel in a hipGraph.
+"""Batching form: a list of solves recorded into one hipGraph.
 
 The three ADI sweeps of one grid are chained (y reads x's output, z reads
-y's) beside an independent ragged batch.  Each output is compared with the
-oracle applied in the same chain, and the graph is replayed several times
-with eager work in between: every replay must reproduce the first bit for
-bit (the persistent kernel's arithmetic per system does not depend on which
-block pops which tile)."""
+y's) beside an independent ragged batch that runs on a parallel branch of
+the graph.  Each output is compared with the oracle applied in the same
+chain; every item's output must also equal, bit for bit, what
+solve_batched gives for the same input (the graph records the same
+launches); and the graph is replayed several times with eager work in
+between, every replay reproducing the first bit for bit."""
 import numpy as np
 import pytest
 
@@ -64,6 +65,17 @@ def test_graph_adi_sweeps_and_ragged(grid):
     for rep in (1, 2):
         for a, b in zip(outs[0], outs[rep]):
             assert np.array_equal(a, b)
+    # the same launches as solve_batched, item by item, on the same inputs
+    # (u1 and u2 still hold the last replay's outputs, equal to the first's)
+    chk = torch.empty_like(tR)
+    for it, got in zip(items[:3], outs[0][:3]):
+        tdma.solve_batched(it["layout"], it["coeffs"], it["d"], chk)
+        tdma.check()
+        assert np.array_equal(chk.cpu().numpy(), got)
+    chk_r = torch.empty_like(td)
+    tdma.solve_batched(items[3]["layout"], items[3]["coeffs"], td, chk_r)
+    tdma.check()
+    assert np.array_equal(chk_r.cpu().numpy(), outs[0][3])
 
 
 def test_graph_single_item_fp32():
