@@ -243,7 +243,7 @@ def solve_batched(layout, coeffs, d, x, stream=None):
 
 def solve_batched_tiled(layout, coeffs, d, x, M, S, P, kernel=0, stream=None):
     """Fused solve with an explicit tile shape (tdma_solve_batched_tiled);
-    kernel 0 = generic, 1 = shared-operator."""
+    kernel 0 = generic, 1 = shared-operator, 2 = its streaming form."""
     L, C, keep = _prepare(layout, coeffs, d, x)
     t = _Tile(int(M), int(S), int(P), int(kernel))
     _raise(lib().tdma_solve_batched_tiled(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),

@@ -214,20 +214,22 @@ bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *o
 }
 
 // Shared-operator kernel: P a power of two <= 64 (one system's interface rows
-// fit one wavefront), M in {16, 32, 8}; S as in the generic rule.
+// fit one wavefront), M in {16, 32, 8}.  Strided layouts take the streaming
+// form with S = 32 systems per tile (measured best on the 256^3 ADI sweep in
+// FP64 and FP32); contiguous rows take the one-tile-per-block form, S as in
+// the generic rule.
 bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *out) {
-    const int esz = dtype == TDMA_F64 ? 8 : 4;
     const int Ms[] = {16, 32, 8};
     for (int M : Ms) {
         int64_t P = 1;
         while (P * M < n) P <<= 1;
         if (P > 64) continue;
         TileShape sh;
-        sh.kernel = 1;
+        sh.kernel = contig ? 1 : 2;
         sh.M = M;
         sh.P = (int)P;
         sh.contig = contig;
-        int S_log2 = contig ? ilog2_floor(std::max<int64_t>(1, 256 / P)) : ilog2_floor(128 / esz);
+        int S_log2 = contig ? ilog2_floor(std::max<int64_t>(1, 256 / P)) : 5;
         const int maxt = shared_max_threads(dtype, M);
         while (S_log2 > 0 && ((int64_t)1 << S_log2) * P > maxt) --S_log2;
         while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= nsys) --S_log2;
@@ -382,7 +384,7 @@ int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int
     if ((int64_t)sh.P * sh.M < L->n)
         return fail(TDMA_EINVAL, "tile shape M=%d P=%d S=%d does not cover n=%lld", sh.M, sh.P,
                     1 << sh.S_log2, (long long)L->n);
-    if (sh.kernel == 1) {
+    if (sh.kernel == 1 || sh.kernel == 2) {
         if (!shared_op || !shared_supported(dtype, sh))
             return fail(TDMA_EINVAL, "the shared-operator kernel needs shared coefficients without "
                         "a shift and a power-of-two P <= 64 (M=%d P=%d S=%d)", sh.M, sh.P,
@@ -400,7 +402,7 @@ int launch_uniform(const TileShape &sh, const tdma_layout *L, const tdma_coeffs 
     const SysMap m = make_map(L);
     if (m.nsys == 0) return TDMA_OK;
     const Coef coef = make_coef(C);
-    const hipError_t e = sh.kernel == 1 ? launch_shared(dtype, m, coef, sh, d, x, err, st)
+    const hipError_t e = sh.kernel != 0 ? launch_shared(dtype, m, coef, sh, d, x, err, st)
                                         : launch_fused(dtype, m, coef, sh, d, x, err, st);
     if (e != hipSuccess) return hip_fail(e, "fused launch");
     return TDMA_OK;
@@ -469,10 +471,10 @@ int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeff
     while ((1 << sh.S_log2) < S) ++sh.S_log2;
     sh.contig = layout->row_stride == 1;
     sh.kernel = tile->kernel;
-    if (sh.kernel != 0 && sh.kernel != 1) return fail(TDMA_EINVAL, "unknown kernel %d", sh.kernel);
+    if (sh.kernel < 0 || sh.kernel > 2) return fail(TDMA_EINVAL, "unknown kernel %d", sh.kernel);
     if (sh.kernel == 0 && !fused_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported tile M=%d S=%d P=%d", sh.M, S, sh.P);
-    if (sh.kernel == 1 && !shared_supported(dtype, sh))
+    if (sh.kernel != 0 && !shared_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported shared-operator tile M=%d S=%d P=%d", sh.M, S, sh.P);
     if ((int64_t)sh.M * sh.P < layout->n) return fail(TDMA_EINVAL, "tile covers %lld rows < n = %lld",
                                                       (long long)sh.M * sh.P, (long long)layout->n);

@@ -134,10 +134,12 @@ std::vector<TileShape> fused_candidates(int dtype, const tdma_layout *L, const t
             while ((int64_t)P * M < n) P <<= 1;
             if (P > 64) continue;
             for (int S_log2 = 0; S_log2 <= 6; ++S_log2) {
-                TileShape sh;
-                sh.kernel = 1; sh.M = M; sh.P = P; sh.S_log2 = S_log2; sh.contig = contig;
-                if ((1 << S_log2) * P < 64 && (int64_t)(1 << S_log2) < nsys) continue;
-                if (shared_supported(dtype, sh)) out.push_back(sh);
+                for (int kind : {1, 2}) {
+                    TileShape sh;
+                    sh.kernel = kind; sh.M = M; sh.P = P; sh.S_log2 = S_log2; sh.contig = contig;
+                    if ((1 << S_log2) * P < 64 && (int64_t)(1 << S_log2) < nsys) continue;
+                    if (shared_supported(dtype, sh)) out.push_back(sh);
+                }
             }
         }
     }

@@ -76,23 +76,38 @@ constexpr int shared_cr() { return M >= 32 ? 2 : 1; }
 // Right-hand sides of a lane's M rows in a strided layout, loaded without
 // branches so that the loads form one straight run behind the coefficient
 // loads (the load counter then stays exact): the pointer stops advancing at
-// the system's last row, rows past it are zeroed after the loads, and a lane
-// past the last system reads the start of the array.
-template <typename T, int M>
+// the system's last row and a lane past the last system reads the start of
+// the array.  Rows past the system's end hold garbage until mask_rows zeroes
+// them, which the kernels do only when the rows are consumed, so nothing
+// waits on these loads early.  OffT is the type of the byte offsets from the
+// array's start: uint32_t when the whole array spans less than 4 GiB (one
+// register per address, the base stays scalar), else int64_t.
+template <typename T, int M, typename OffT>
 __device__ __forceinline__ void load_rows(const T *d, const LaneSys &sys, int64_t rs, int r0,
                                           T (&dv)[M]) {
     const int64_t last = sys.nrows > 0 ? sys.nrows - 1 : 0;
     const int64_t first = r0 < last ? r0 : last;
     const int adv = (int)(last - first < M ? last - first : M);   // rows the pointer may advance
-    const T *pd = d + (sys.valid ? sys.base : 0) + first * rs;
+    const char *b = reinterpret_cast<const char *>(d);
+    const OffT step = (OffT)(rs * (int64_t)sizeof(T));
+    OffT off = (OffT)(((sys.valid ? sys.base : 0) + first * rs) * (int64_t)sizeof(T));
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        dv[j] = *pd;
-        pd += j < adv ? rs : 0;
+        dv[j] = *reinterpret_cast<const T *>(b + off);
+        off += j < adv ? step : OffT(0);
     }
+}
+
+// Rows of the lane's partition that lie inside its system (0..M).
+__device__ __forceinline__ int rows_in(const LaneSys &sys, int r0, int M) {
+    return (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void mask_rows(int rows_here, T (&dv)[M]) {
 #pragma unroll
     for (int j = 0; j < M; ++j)
-        if (r0 + j >= sys.nrows) dv[j] = T(0);
+        if (j >= rows_here) dv[j] = T(0);
 }
 
 // Steps shared by the shared-operator kernels: copy the tile's coefficient
@@ -268,7 +283,63 @@ __device__ __forceinline__ void shared_rhs_pcr(double *XD, const double *QA, con
     xl = XD[s * xpitch + 2 * p + 1];
 }
 
-template <typename T, int M, bool CONTIG>
+// Stage A, the right-hand-side interface PCR (Stage B) and Stage C of one
+// tile on the lane's rows dv, with the tables already built; dv becomes x.
+// Every thread of the block calls it.
+template <typename T, int M>
+__device__ __forceinline__ void shared_solve_rows(const SharedLds &L, char *base, int S, int P,
+                                                  int P_log2, int s, int p, T (&dv)[M]) {
+    const int pitch = M + 1;
+    const T *g = reinterpret_cast<const T *>(base + L.g) + p * pitch;
+    const T *h = reinterpret_cast<const T *>(base + L.h) + p * pitch;
+    const T *pi_t = reinterpret_cast<const T *>(base + L.pi) + p * pitch;
+    const T *ah = reinterpret_cast<const T *>(base + L.ah) + p * pitch;
+    const T *ch = reinterpret_cast<const T *>(base + L.ch) + p * pitch;
+    const double *PT = reinterpret_cast<const double *>(base + L.part);
+    const double *QA = reinterpret_cast<const double *>(base + L.qa);
+    const double *QC = QA + L.nsteps * 2 * P, *QB = QC + L.nsteps * 2 * P;
+    double *XD = reinterpret_cast<double *>(base + L.xd);
+    // Stage A
+    const T draw0 = dv[0];
+    dv[1] = g[1] * dv[1];
+#pragma unroll
+    for (int j = 2; j < M; ++j) dv[j] = g[j] * dv[j] - h[j] * dv[j - 1];
+    T dt1 = T(0);
+#pragma unroll
+    for (int j = 1; j <= M - 2; ++j) dt1 += pi_t[j] * dv[j];
+    const double df = PT[p] * (double)draw0 - PT[P + p] * (double)dt1;
+    const double dl_ = (double)dv[M - 1];
+    // Stage B: right-hand-side-only PCR inside wavefronts
+    double xfd, xld;
+    shared_rhs_pcr(XD, QA, QC, QB, S, P, P_log2, s, p, df, dl_, xfd, xld);
+    const T xf = (T)xfd;
+    // Stage C
+    dv[M - 1] = (T)xld;
+#pragma unroll
+    for (int j = M - 2; j >= 1; --j) dv[j] = dv[j] - ah[j] * xf - ch[j] * dv[j + 1];
+    dv[0] = xf;
+}
+
+// The lane's M rows of x in a strided layout (rows past the system's end
+// are not written); OffT as for load_rows.
+template <typename T, int M, typename OffT>
+__device__ __forceinline__ void store_rows(T *x, const LaneSys &sys, int64_t rs, int r0,
+                                           const T (&dv)[M]) {
+    const int rows_here = rows_in(sys, r0, M);
+    char *b = reinterpret_cast<char *>(x);
+    const OffT step = (OffT)(rs * (int64_t)sizeof(T));
+    const OffT off = (OffT)((sys.base + (int64_t)r0 * rs) * (int64_t)sizeof(T));
+    if (rows_here == M) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) *reinterpret_cast<T *>(b + (off + (OffT)j * step)) = dv[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (j < rows_here) *reinterpret_cast<T *>(b + (off + (OffT)j * step)) = dv[j];
+    }
+}
+
+template <typename T, int M, bool CONTIG, typename OffT>
 __global__ void __launch_bounds__((shared_max_threads<T, M>()))
 k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *err) {
     extern __shared__ double lds[];
@@ -282,19 +353,6 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
     const int64_t k0 = (int64_t)blockIdx.x << S_log2;
     const LaneSys sys = dev::lane_system(map, k0 + s);
     const SharedLds L = shared_layout(sizeof(T), M, P, S);
-    const int pitch = M + 1;
-    T *G = reinterpret_cast<T *>(base + L.g);
-    T *H = reinterpret_cast<T *>(base + L.h);
-    T *PI = reinterpret_cast<T *>(base + L.pi);
-    T *AH = reinterpret_cast<T *>(base + L.ah);
-    T *CH = reinterpret_cast<T *>(base + L.ch);
-    double *PT = reinterpret_cast<double *>(base + L.part);
-    double *K0 = PT, *K1 = PT + P, *AF = PT + 2 * P, *GF = PT + 3 * P, *AL = PT + 4 * P,
-           *GL = PT + 5 * P;
-    double *QA = reinterpret_cast<double *>(base + L.qa);
-    double *QC = QA + L.nsteps * 2 * P, *QB = QC + L.nsteps * 2 * P;
-    double *XD = reinterpret_cast<double *>(base + L.xd);
-    const int xpitch = 2 * P + 1;
 
     // 1. coefficient rows, then the right-hand sides of this lane's rows (in
     //    flight while the tables are built)
@@ -306,7 +364,7 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
     TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, sizeof(T), M, P, S));
     const float invR = 1.0f / (float)(P * M);
     if constexpr (!CONTIG) {
-        load_rows<T, M>(d, sys, map.row_stride, r0, dv);
+        load_rows<T, M, OffT>(d, sys, map.row_stride, r0, dv);
     } else {
         if (tid < S) {
             const LaneSys q = dev::lane_system(map, k0 + tid);
@@ -320,6 +378,7 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
     // 2-3. coefficient tables and the interface PCR history
     bool bad = false;
     shared_tables<T, T, M>(coef, n, L, base, tid, s, p, P, cr, bad);
+    if constexpr (!CONTIG) mask_rows<T, M>(rows_in(sys, r0, M), dv);
     if constexpr (CONTIG) {
         T ld[M];
 #pragma unroll
@@ -327,45 +386,97 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
         dev::stage_put<T, M>(stg, tsys, T(0), S, P * M, P * M + 1, invR, s, r0, ld, dv);
     }
 
-    // 4. Stage A on this lane's right-hand sides
-    const T *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch;
-    const T draw0 = dv[0];
-    dv[1] = g[1] * dv[1];
-#pragma unroll
-    for (int j = 2; j < M; ++j) dv[j] = g[j] * dv[j] - h[j] * dv[j - 1];
-    T dt1 = T(0);
-#pragma unroll
-    for (int j = 1; j <= M - 2; ++j) dt1 += pi_t[j] * dv[j];
-    const double df = K0[p] * (double)draw0 - K1[p] * (double)dt1;
-    const double dl_ = (double)dv[M - 1];
-
-    // 5. Stage B: right-hand-side-only PCR inside wavefronts
-    double xfd, xld;
-    shared_rhs_pcr(XD, QA, QC, QB, S, P, P_log2, s, p, df, dl_, xfd, xld);
-    const T xf = (T)xfd;
-    const T xl = (T)xld;
-
-    // 6. Stage C
-    const T *ah = AH + p * pitch, *ch = CH + p * pitch;
-    dv[M - 1] = xl;
-#pragma unroll
-    for (int j = M - 2; j >= 1; --j) dv[j] = dv[j] - ah[j] * xf - ch[j] * dv[j + 1];
-    dv[0] = xf;
+    // 4-6. Stage A, Stage B, Stage C; dv becomes x
+    shared_solve_rows<T, M>(L, base, S, P, P_log2, s, p, dv);
 
     if constexpr (!CONTIG) {
-        const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
-        T *px = x + sys.base + (int64_t)r0 * map.row_stride;
-        const int64_t rs = map.row_stride;
-        if (rows_here == M) {
-#pragma unroll
-            for (int j = 0; j < M; ++j) px[j * rs] = dv[j];
-        } else {
-#pragma unroll
-            for (int j = 0; j < M; ++j)
-                if (j < rows_here) px[j * rs] = dv[j];
-        }
+        store_rows<T, M, OffT>(x, sys, map.row_stride, r0, dv);
     } else {
         dev::stage_out<T, M>(stg, tsys, x, S, P * M, P * M + 1, invR, s, r0, dv);
+    }
+    if (bad) atomicOr(err, 1);
+}
+
+// System of a lane in a uniform layout, stepped through the tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ... without a division per step.
+struct LaneWalk {
+    int64_t k, s0, s1;         // system index and its two grid coordinates
+    int64_t q, r;              // one step (gridDim.x * S systems) = q rows of nsys0 + r
+    __device__ void init(const SysMap &m, int64_t k0, int64_t step) {
+        k = k0;
+        s1 = k0 / m.nsys0;
+        s0 = k0 - s1 * m.nsys0;
+        q = step / m.nsys0;
+        r = step - q * m.nsys0;
+    }
+    __device__ void advance(const SysMap &m, int64_t step) {
+        k += step;
+        s0 += r;
+        s1 += q;
+        if (s0 >= m.nsys0) { s0 -= m.nsys0; ++s1; }
+    }
+    __device__ LaneSys sys(const SysMap &m) const {
+        LaneSys l;
+        l.valid = k < m.nsys;
+        l.id = k;
+        l.base = l.valid ? s0 * m.sys_stride0 + s1 * m.sys_stride1 : 0;
+        l.nrows = l.valid ? m.n : 0;
+        return l;
+    }
+};
+
+// Streaming form of k_shared for uniform strided layouts: each resident
+// block builds the tables once, then walks the tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ... with two register sets in turn: the next
+// tile's right-hand sides are loaded into one set before the tile in the
+// other set is solved and stored, so loads stay in flight through its
+// barriers and arithmetic.
+template <typename T, int M, typename OffT>
+__global__ void __launch_bounds__((shared_max_threads<T, M>()))
+k_shared_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int64_t ntiles,
+                int *err) {
+    extern __shared__ double lds[];
+    char *base = reinterpret_cast<char *>(lds);
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2, P = 1 << P_log2;
+    const int s = tid & (S - 1);
+    const int p = tid >> S_log2;
+    const int r0 = p * M;
+    const int64_t rs = map.row_stride;
+    const SharedLds L = shared_layout(sizeof(T), M, P, S);
+    const int64_t step = (int64_t)gridDim.x << S_log2;
+    int64_t t = blockIdx.x;
+    LaneWalk w;
+    w.init(map, (t << S_log2) + s, step);
+    dev::RowRegs<shared_cr<M>()> cr;
+    dev::rows_prefetch<T, shared_cr<M>()>(coef, map.n, cr);
+    __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the right-hand sides
+    T va[M], vb[M];
+    LaneSys sa = w.sys(map), sb;
+    load_rows<T, M, OffT>(d, sa, rs, r0, va);
+    bool bad = false;
+    shared_tables<T, T, M>(coef, map.n, L, base, tid, s, p, P, cr, bad);
+    for (;;) {
+        // tile t in va; load tile t + G into vb, then solve va
+        w.advance(map, step);
+        sb = w.sys(map);
+        load_rows<T, M, OffT>(d, sb, rs, r0, vb);
+        __builtin_amdgcn_sched_barrier(0);
+        mask_rows<T, M>(rows_in(sa, r0, M), va);
+        shared_solve_rows<T, M>(L, base, S, P, P_log2, s, p, va);
+        store_rows<T, M, OffT>(x, sa, rs, r0, va);
+        t += gridDim.x;
+        if (t >= ntiles) break;
+        // tile t in vb; load tile t + G into va, then solve vb
+        w.advance(map, step);
+        sa = w.sys(map);
+        load_rows<T, M, OffT>(d, sa, rs, r0, va);
+        __builtin_amdgcn_sched_barrier(0);
+        mask_rows<T, M>(rows_in(sb, r0, M), vb);
+        shared_solve_rows<T, M>(L, base, S, P, P_log2, s, p, vb);
+        store_rows<T, M, OffT>(x, sb, rs, r0, vb);
+        t += gridDim.x;
+        if (t >= ntiles) break;
     }
     if (bad) atomicOr(err, 1);
 }
@@ -413,7 +524,7 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
     TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, 8, M, P, S));
     const float invR = 1.0f / (float)R;
     if constexpr (!CONTIG) {
-        load_rows<double, M>(d, sys, map.row_stride, r0, dv);
+        load_rows<double, M, int64_t>(d, sys, map.row_stride, r0, dv);
     } else {
         if (tid < S) {
             const LaneSys q = dev::lane_system(map, k0 + tid);
@@ -425,6 +536,7 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
     }
     bool bad = false;
     shared_tables<float, double, M>(coef, n, L, base, tid, s, p, P, cr, bad);
+    if constexpr (!CONTIG) mask_rows<double, M>(rows_here, dv);
     if constexpr (CONTIG) {
         double ld[M];
 #pragma unroll
@@ -514,6 +626,43 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
     }
 }
 
+// Resident blocks of a kernel on the current device.
+template <typename K>
+int64_t resident_blocks(K kernel, int threads, size_t lds) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess)
+        return 0;
+    return (int64_t)cus * per_cu;
+}
+
+// Largest byte offset of a uniform strided layout, to pick 32-bit offsets.
+inline bool offsets_fit_32(const SysMap &m, size_t esz) {
+    const int64_t nsys1 = (m.nsys + m.nsys0 - 1) / m.nsys0;
+    const int64_t last = (m.n - 1) * m.row_stride + (m.nsys0 - 1) * m.sys_stride0 +
+                         (nsys1 - 1) * m.sys_stride1;
+    return last >= 0 && (last + 1) * (int64_t)esz <= (int64_t)0xFFFFFFFF;
+}
+
+template <typename T, int M, typename OffT>
+hipError_t launch_strided(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
+                          void *x, int *err, size_t lds, hipStream_t st, int64_t blocks,
+                          int P_log2) {
+    if (sh.kernel == 2) {
+        if (map.offsets || map.sys_list || map.count) return hipErrorInvalidValue;
+        const int64_t resident = resident_blocks(k_shared_stream<T, M, OffT>, sh.threads(), lds);
+        if (resident < 1) return hipErrorInvalidConfiguration;
+        const int64_t grid = blocks < resident ? blocks : resident;
+        hipLaunchKernelGGL((k_shared_stream<T, M, OffT>), dim3((unsigned)grid), dim3(sh.threads()),
+                           lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, blocks, err);
+    } else {
+        hipLaunchKernelGGL((k_shared<T, M, false, OffT>), dim3((unsigned)blocks), dim3(sh.threads()),
+                           lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, err);
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int M>
 hipError_t launch_m(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
                     void *x, int *err, size_t lds, hipStream_t st) {
@@ -521,13 +670,14 @@ hipError_t launch_m(const SysMap &map, const Coef &coef, const TileShape &sh, co
     const int64_t blocks = (map.nsys + S - 1) / S;
     if (blocks == 0) return hipSuccess;
     const int P_log2 = ilog2i(sh.P);
-    if (sh.contig)
-        hipLaunchKernelGGL((k_shared<T, M, true>), dim3((unsigned)blocks), dim3(sh.threads()), lds, st,
-                           map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, err);
-    else
-        hipLaunchKernelGGL((k_shared<T, M, false>), dim3((unsigned)blocks), dim3(sh.threads()), lds, st,
-                           map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, err);
-    return hipGetLastError();
+    if (sh.contig) {
+        hipLaunchKernelGGL((k_shared<T, M, true, int64_t>), dim3((unsigned)blocks), dim3(sh.threads()),
+                           lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, err);
+        return hipGetLastError();
+    }
+    if (offsets_fit_32(map, sizeof(T)))
+        return launch_strided<T, M, uint32_t>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
+    return launch_strided<T, M, int64_t>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
 }
 
 }  // namespace
@@ -547,6 +697,7 @@ size_t shared_lds_bytes(int dtype, const TileShape &sh) {
 
 bool shared_supported(int dtype, const TileShape &sh) {
     if (sh.P < 1 || sh.P > 64 || (sh.P & (sh.P - 1)) != 0) return false;
+    if (sh.kernel == 2 && sh.contig) return false;   // the streaming form is strided only
     if (sh.M != 8 && sh.M != 16 && sh.M != 32) return false;
     if (sh.threads() > shared_max_threads(dtype, sh.M)) return false;
     return shared_lds_bytes(dtype, sh) <= 160 * 1024;

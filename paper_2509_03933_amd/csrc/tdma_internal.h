@@ -35,7 +35,8 @@ struct TileShape {
     int S_log2 = 4;
     int P = 4;
     bool contig = false;    // stage loads/stores through LDS (row_stride == 1)
-    int kernel = 0;         // 0: generic fused kernel, 1: shared-operator kernel
+    int kernel = 0;         // 0: generic fused kernel, 1: shared-operator kernel,
+                            // 2: its streaming form (resident blocks walk the tiles)
     int threads() const { return (1 << S_log2) * P; }
 };
 

@@ -143,7 +143,8 @@ def test_singular_flagged():
 
 SHAPES_SHARED = [dict(M=16, S=16, P=16, kernel=1), dict(M=8, S=16, P=32, kernel=1),
                  dict(M=32, S=16, P=8, kernel=1), dict(M=8, S=8, P=64, kernel=1),
-                 dict(M=16, S=1, P=16, kernel=1), dict(M=16, S=16, P=16, kernel=0)]
+                 dict(M=16, S=1, P=16, kernel=1), dict(M=16, S=16, P=16, kernel=0),
+                 dict(M=16, S=16, P=16, kernel=2), dict(M=32, S=32, P=8, kernel=2)]
 
 
 @pytest.mark.parametrize("shape", SHAPES_SHARED,
@@ -153,6 +154,21 @@ def test_shared_operator_shapes(shape):
     ADI problem; n = 200 leaves identity padding rows in the last partition."""
     err, _, _ = _run(configs.adi(40, 12, 200), shape=shape)
     assert err.max() <= parity.TOL_F64, err.max()
+
+
+STREAM_SHAPES = [dict(M=16, S=1, P=16, kernel=2), dict(M=16, S=4, P=16, kernel=2),
+                 dict(M=8, S=2, P=32, kernel=2), dict(M=32, S=8, P=8, kernel=2)]
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, parity.TOL_F64), (np.float32, parity.TOL_F32)])
+@pytest.mark.parametrize("shape", STREAM_SHAPES,
+                         ids=lambda s: "M%d_S%d_P%d" % (s["M"], s["S"], s["P"]))
+def test_shared_streaming_walks_many_tiles(shape, dtype, tol):
+    """Streaming form: far more tiles than resident workgroups, so each
+    workgroup walks several tiles through both register sets; 65,535
+    systems leave a partial last tile and n = 200 padding rows."""
+    err, _, _ = _run(configs.adi(257, 255, 200), dtype, shape=shape)
+    assert err.max() <= tol, err.max()
 
 
 @pytest.mark.parametrize("dtype,tol", [(np.float64, parity.TOL_F64), (np.float32, parity.TOL_F32)])
