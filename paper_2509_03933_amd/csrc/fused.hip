@@ -10,7 +10,7 @@ template <typename T, int M, bool LIKE_D, bool SHIFT, bool CONTIG>
 __global__ void __launch_bounds__((fused_max_threads<T, M>()))
 k_fused(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P, int *err) {
     extern __shared__ double lds[];
-    const int64_t k0 = (int64_t)blockIdx.x << S_log2;
+    const int64_t k0 = dev::xcd_tile(blockIdx.x, gridDim.x) << S_log2;
     if (map.count && k0 >= dev::launch_nsys(map)) return;   // whole tile past a device count
     fused_tile<T, M, LIKE_D, SHIFT, CONTIG>(map, coef, d, x, S_log2, P, k0, err, lds);
 }

@@ -31,7 +31,7 @@ k_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, int P, i
     const int p = tid >> S_log2;
     const int r0 = p * M;
     const int64_t n = map.n;
-    const int64_t k0 = (int64_t)blockIdx.x << S_log2;
+    const int64_t k0 = dev::xcd_tile(blockIdx.x, gridDim.x) << S_log2;
     const LaneSys sys = dev::lane_system(map, k0 + s);
     const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
     const double *A = (const double *)coef.a, *B = (const double *)coef.b,

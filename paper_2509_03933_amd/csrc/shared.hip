@@ -350,7 +350,7 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
     const int p = tid >> S_log2;
     const int r0 = p * M;
     const int64_t n = map.n;
-    const int64_t k0 = (int64_t)blockIdx.x << S_log2;
+    const int64_t k0 = dev::xcd_tile(blockIdx.x, gridDim.x) << S_log2;
     const LaneSys sys = dev::lane_system(map, k0 + s);
     const SharedLds L = shared_layout(sizeof(T), M, P, S);
 
@@ -499,7 +499,7 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
     const int r0 = p * M;
     const int R = P * M;
     const int64_t n = map.n;
-    const int64_t k0 = (int64_t)blockIdx.x << S_log2;
+    const int64_t k0 = dev::xcd_tile(blockIdx.x, gridDim.x) << S_log2;
     const LaneSys sys = dev::lane_system(map, k0 + s);
     const SharedLds L = shared_layout(sizeof(float), M, P, S);
     const int pitch = M + 1;

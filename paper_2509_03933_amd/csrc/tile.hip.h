@@ -66,6 +66,18 @@ struct LaneSys {
     bool valid;
 };
 
+// Tile taken by block b of nb when the hardware hands consecutive block
+// indices to the device's 8 XCDs in turn: the blocks of one XCD take
+// consecutive tiles, so neighbouring tiles (which may share 128-byte lines
+// when a tile row is narrower than a line) run at the same time under one
+// L2.  A bijection of [0, nb).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+    constexpr int64_t kXcds = 8;
+    const int64_t q = nb / kXcds, r = nb % kXcds;
+    const int64_t x = b % kXcds, i = b / kXcds;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Systems covered by a launch: nsys, or the device-side count when given.
 __device__ __forceinline__ int64_t launch_nsys(const SysMap &m) {
     if (!m.count) return m.nsys;
