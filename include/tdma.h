@@ -125,11 +125,14 @@ int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeff
  * Options of the split, pipelined solve.  Zero fields take defaults.
  *  partitions  P per system (>= 1, n/P >= 2); 0 = 8.
  *  batch       systems per pipeline batch (the paper's batch_z, Sec. 4.2.1);
- *              0 = autotuned (cached) or 16384.
- *  nstreams    HIP streams the pipeline uses (1..8); 0 = 4.
- *  schedule    0 = stage roles as in Algorithm 2 (Stage A and C on one stream
- *              role, Stage B on another, ordered by events);
- *              1 = round-robin (batch b runs A->B->C on stream b mod nstreams).
+ *              0 = autotuned (cached) or 32768.
+ *  nstreams    HIP streams the pipeline uses (1..8); 0 = autotuned or 4.
+ *  schedule    0 = autotuned (cached) or round robin;
+ *              1 = round robin (batch b runs A->B->C on stream b mod nstreams);
+ *              2 = stage roles as in Algorithm 2 (Stage A and C on one stream
+ *              role, Stage B on another, ordered by events).
+ * Errors: EINVAL for P < 1, n/P < 2, P > 4096, nstreams > 8, schedule
+ * outside 0..2 or a negative batch.
  */
 typedef struct tdma_part_opts {
     int partitions;

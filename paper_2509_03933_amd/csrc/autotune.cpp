@@ -316,7 +316,7 @@ int tdma_autotune(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtyp
         float brute = -1.f;
         if (what == 2) {
             rc = time_median(st, 3, [&]() {
-                return pipeline_solve(ctx, layout, coeffs, dtype, d, x, P, s, 4, 0, st);
+                return pipeline_solve(ctx, layout, coeffs, dtype, d, x, P, s, 4, 1, st);
             }, &brute);
             if (rc != TDMA_OK) return rc;
             if (brute < best_brute) { best_brute = brute; s_brute = s; }
@@ -335,7 +335,7 @@ int tdma_autotune(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtyp
     Tuned &t = g_tuned[key_of(ctx->dev, layout, coeffs, dtype, "part", P)];
     t.batch = s_model;
     t.nstreams = 4;
-    t.schedule = 0;
+    t.schedule = 1;   // round robin (the pipeline's numbering)
     t.P = P;
     save_cache_locked();
     g_last_json = js.str();

@@ -6,43 +6,59 @@ namespace tdma {
 
 namespace {
 
-template <typename T, int M, bool LIKE_D, bool SHIFT, bool CONTIG>
+// CO: a shared operator whose coefficient rows are held in LDS (fused_tile_co).
+template <typename T, int M, bool LIKE_D, bool SHIFT, bool CONTIG, bool CO>
 __global__ void __launch_bounds__((fused_max_threads<T, M>()))
 k_fused(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P, int *err) {
     extern __shared__ double lds[];
     const int64_t k0 = dev::xcd_tile(blockIdx.x, gridDim.x) << S_log2;
     if (map.count && k0 >= dev::launch_nsys(map)) return;   // whole tile past a device count
-    fused_tile<T, M, LIKE_D, SHIFT, CONTIG>(map, coef, d, x, S_log2, P, k0, err, lds);
+    if constexpr (CO)
+        fused_tile_co<T, M, SHIFT, CONTIG>(map, coef, d, x, S_log2, P, k0, err, lds);
+    else
+        fused_tile<T, M, LIKE_D, SHIFT, CONTIG>(map, coef, d, x, S_log2, P, k0, err, lds);
 }
 
-template <typename T, int M, bool LIKE_D, bool SHIFT, bool CONTIG>
+template <typename T, int M, bool LIKE_D, bool SHIFT, bool CONTIG, bool CO>
 hipError_t launch_t(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
                     void *x, int *err, size_t lds, hipStream_t st) {
     const int64_t S = (int64_t)1 << sh.S_log2;
     const int64_t blocks = (map.nsys + S - 1) / S;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_fused<T, M, LIKE_D, SHIFT, CONTIG>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((k_fused<T, M, LIKE_D, SHIFT, CONTIG, CO>), dim3((unsigned)blocks),
                        dim3(sh.threads()), lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2,
                        sh.P, err);
     return hipGetLastError();
 }
 
+// Largest LDS footprint for which a shared operator is held in LDS: two
+// blocks must still fit a CU.
+constexpr size_t kCoLdsLimit = 64 * 1024;
+
 template <typename T, int M>
 hipError_t launch_m(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
-                    void *x, int *err, size_t lds, hipStream_t st) {
+                    void *x, int *err, hipStream_t st) {
     const bool like_d = coef.mode == TDMA_COEF_LIKE_D;
     const bool shift = coef.shift != nullptr;
-#define TDMA_DISPATCH(LD, SH, CT)                                                            \
-    if (like_d == LD && shift == SH && sh.contig == CT)                                      \
-        return launch_t<T, M, LD, SH, CT>(map, coef, sh, d, x, err, lds, st);
-    TDMA_DISPATCH(true, false, false)
-    TDMA_DISPATCH(true, true, false)
-    TDMA_DISPATCH(false, false, false)
-    TDMA_DISPATCH(false, true, false)
-    TDMA_DISPATCH(true, false, true)
-    TDMA_DISPATCH(true, true, true)
-    TDMA_DISPATCH(false, false, true)
-    TDMA_DISPATCH(false, true, true)
+    const int dtype = sizeof(T) == 8 ? TDMA_F64 : TDMA_F32;
+    const size_t lds_co = fused_lds_bytes(dtype, sh, true);
+    const bool co = !like_d && lds_co <= kCoLdsLimit;
+    const size_t lds = co ? lds_co : fused_lds_bytes(dtype, sh, false);
+#define TDMA_DISPATCH(LD, SH, CT, C)                                                         \
+    if (like_d == LD && shift == SH && sh.contig == CT && co == C)                           \
+        return launch_t<T, M, LD, SH, CT, C>(map, coef, sh, d, x, err, lds, st);
+    TDMA_DISPATCH(true, false, false, false)
+    TDMA_DISPATCH(true, true, false, false)
+    TDMA_DISPATCH(false, false, false, false)
+    TDMA_DISPATCH(false, true, false, false)
+    TDMA_DISPATCH(true, false, true, false)
+    TDMA_DISPATCH(true, true, true, false)
+    TDMA_DISPATCH(false, false, true, false)
+    TDMA_DISPATCH(false, true, true, false)
+    TDMA_DISPATCH(false, false, false, true)
+    TDMA_DISPATCH(false, true, false, true)
+    TDMA_DISPATCH(false, false, true, true)
+    TDMA_DISPATCH(false, true, true, true)
 #undef TDMA_DISPATCH
     return hipErrorInvalidValue;
 }
@@ -62,30 +78,28 @@ bool fused_supported(int dtype, const TileShape &sh) {
     return false;
 }
 
-size_t fused_lds_bytes(int dtype, const TileShape &sh) {
-    const size_t S = (size_t)1 << sh.S_log2;
-    const size_t pcr = dev::pcr_lds_bytes((int)S, sh.P);
-    if (!sh.contig) return pcr;
+size_t fused_lds_bytes(int dtype, const TileShape &sh, bool shared_rows) {
+    const int S = 1 << sh.S_log2;
     const size_t esz = dtype == TDMA_F64 ? 8 : 4;
-    const size_t stg = (S * ((size_t)sh.P * sh.M + 1) * esz + 15) & ~(size_t)15;
-    return (stg > pcr ? stg : pcr) + S * 16;
+    if (shared_rows)
+        return fused_co_offset(esz, S, sh.P, sh.M, sh.contig) + 3 * (size_t)sh.P * sh.M * esz;
+    return fused_region0(esz, S, sh.P, sh.M, sh.contig) + (sh.contig ? (size_t)S * 16 : 0);
 }
 
 hipError_t launch_fused(int dtype, const SysMap &map, const Coef &coef, const TileShape &sh,
                         const void *d, void *x, int *err, hipStream_t st) {
-    const size_t lds = fused_lds_bytes(dtype, sh);
     if (dtype == TDMA_F64) {
         switch (sh.M) {
-            case 4: return launch_m<double, 4>(map, coef, sh, d, x, err, lds, st);
-            case 8: return launch_m<double, 8>(map, coef, sh, d, x, err, lds, st);
-            case 16: return launch_m<double, 16>(map, coef, sh, d, x, err, lds, st);
+            case 4: return launch_m<double, 4>(map, coef, sh, d, x, err, st);
+            case 8: return launch_m<double, 8>(map, coef, sh, d, x, err, st);
+            case 16: return launch_m<double, 16>(map, coef, sh, d, x, err, st);
         }
     } else if (dtype == TDMA_F32) {
         switch (sh.M) {
-            case 4: return launch_m<float, 4>(map, coef, sh, d, x, err, lds, st);
-            case 8: return launch_m<float, 8>(map, coef, sh, d, x, err, lds, st);
-            case 16: return launch_m<float, 16>(map, coef, sh, d, x, err, lds, st);
-            case 32: return launch_m<float, 32>(map, coef, sh, d, x, err, lds, st);
+            case 4: return launch_m<float, 4>(map, coef, sh, d, x, err, st);
+            case 8: return launch_m<float, 8>(map, coef, sh, d, x, err, st);
+            case 16: return launch_m<float, 16>(map, coef, sh, d, x, err, st);
+            case 32: return launch_m<float, 32>(map, coef, sh, d, x, err, st);
         }
     }
     return hipErrorInvalidValue;

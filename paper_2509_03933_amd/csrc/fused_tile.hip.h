@@ -136,4 +136,113 @@ __device__ __forceinline__ void fused_tile(const SysMap &map, const Coef &coef, 
 }
 
 
+// LDS layout of the fused tile: [0, region0) staging (contiguous rows) or the
+// Stage B scratch, whichever is larger; the contiguous-row system table; and,
+// for a shared operator held in LDS, its 3 x P*M coefficient rows.
+__host__ __device__ inline size_t fused_region0(size_t esz, int S, int P, int M, bool contig) {
+    const size_t pcr = dev::pcr_lds_bytes(S, P);
+    if (!contig) return pcr;
+    const size_t stg = ((size_t)S * ((size_t)P * M + 1) * esz + 15) & ~(size_t)15;
+    return stg > pcr ? stg : pcr;
+}
+
+__host__ __device__ inline size_t fused_co_offset(size_t esz, int S, int P, int M, bool contig) {
+    const size_t tsys = contig ? (size_t)S * 16 : 0;
+    return (fused_region0(esz, S, P, M, contig) + tsys + 15) & ~(size_t)15;
+}
+
+// Fused tile of a shared operator (optionally with a per-system diagonal
+// shift): the tile's coefficient rows go to LDS once per block, loaded ahead
+// of the right-hand sides, and each lane keeps only d^, a^ and c^ of its M
+// rows in registers (three values per row instead of four), which doubles
+// the blocks a CU holds.  Same arithmetic as fused_tile.  Every thread of
+// the block must call it.
+template <typename T, int M, bool SHIFT, bool CONTIG>
+__device__ __forceinline__ void fused_tile_co(const SysMap &map, const Coef &coef, const T *d, T *x,
+                                              int S_log2, int P, int64_t k0, int *err, double *lds) {
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2;
+    const int s = tid & (S - 1);
+    const int p = tid >> S_log2;
+    const int r0 = p * M;
+    const int R = P * M;
+    const LaneSys sys = dev::lane_system(map, k0 + s);
+    const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
+    char *base = reinterpret_cast<char *>(lds);
+    T *CO = reinterpret_cast<T *>(base + fused_co_offset(sizeof(T), S, P, M, CONTIG));
+
+    // coefficient rows first, then the right-hand sides (in flight while the
+    // rows go to LDS)
+    constexpr int CR = 2;
+    dev::RowRegs<CR> rr;
+    dev::rows_prefetch<T, CR>(coef, map.n, rr);
+    __builtin_amdgcn_sched_barrier(0);
+    T dv[M];
+    T *stg = reinterpret_cast<T *>(lds);
+    TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + fused_region0(sizeof(T), S, P, M, CONTIG));
+    const float invR = 1.0f / (float)R;
+    if constexpr (!CONTIG) {
+        // branch-free, so the loads form one run behind the coefficient rows:
+        // the row index stops at the system's last row (a lane past the last
+        // system reads the array's start); padding rows are zeroed below
+        const int64_t rs = map.row_stride;
+        const int64_t last = sys.nrows > 0 ? sys.nrows - 1 : 0;
+        const int64_t first = r0 < last ? r0 : last;
+        const int adv = (int)(last - first < M ? last - first : M);
+        int64_t idx = (sys.valid ? sys.base : 0) + first * rs;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            dv[j] = d[idx];
+            idx += j < adv ? rs : 0;
+        }
+    } else {
+        if (tid < S) {
+            const LaneSys q = dev::lane_system(map, k0 + tid);
+            tsys[tid].base = q.base;
+            tsys[tid].nrows = q.nrows;
+        }
+        __syncthreads();
+        dev::stage_load<T, M>(tsys, d, S, R, invR, dv);
+    }
+    T sh = T(0);
+    if constexpr (SHIFT) {
+        sh = ((const T *)coef.shift)[sys.valid ? sys.id : 0];
+        if (!sys.valid) sh = T(0);
+    }
+    dev::rows_commit<T, CR, T>(CO, coef, map.n, R, rr);
+    if constexpr (!CONTIG) {
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (j >= rows_here) dv[j] = T(0);
+    }
+    if constexpr (CONTIG) {
+        T ld[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) ld[j] = dv[j];
+        dev::stage_put<T, M>(stg, tsys, Ident<T>::d, S, R, R + 1, invR, s, r0, ld, dv);
+    }
+
+    bool bad = false;
+    T ah[M], ch[M];
+    const Iface f = dev::reduce_partition_rows<T, M, SHIFT>(CO + r0, CO + R + r0, CO + 2 * R + r0, sh,
+                                                            rows_here, ah, ch, dv, bad);
+    double xf, xl;
+    if (P <= 64 && (P & (P - 1)) == 0)
+        dev::pcr_interface_wave(lds, S, s, p, P, __builtin_ctz(P), f, xf, xl, bad);
+    else
+        dev::pcr_interface(lds, S, s, p, P, f, xf, xl, bad);
+    dev::substitute_partition<T, M>(ah, ch, dv, xf, xl);
+
+    if constexpr (!CONTIG) {
+        const int64_t off0 = sys.base + (int64_t)r0 * map.row_stride;
+        const int64_t rs = map.row_stride;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (j < rows_here) x[off0 + j * rs] = dv[j];
+    } else {
+        dev::stage_out<T, M>(stg, tsys, x, S, R, R + 1, invR, s, r0, dv);
+    }
+    if (bad && sys.valid) atomicOr(err, 1);
+}
+
 }  // namespace tdma

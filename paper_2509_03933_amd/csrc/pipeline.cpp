@@ -154,20 +154,27 @@ extern "C" int tdma_solve_partitioned(const tdma_layout *layout, const tdma_coef
     if (nsys == 0) return TDMA_OK;
     int P = opts && opts->partitions ? opts->partitions : 8;
     int64_t batch = opts && opts->batch ? opts->batch : 0;
-    int nstreams = opts && opts->nstreams ? opts->nstreams : 4;
-    int schedule = opts ? opts->schedule : 0;
+    int nstreams = opts && opts->nstreams ? opts->nstreams : 0;
+    const int sched_opt = opts ? opts->schedule : 0;
     if (P < 1) return fail(TDMA_EINVAL, "partitions = %d (< 1)", P);
     if (layout->n / P < 2) return fail(TDMA_EINVAL, "n = %lld gives partitions of < 2 rows (P = %d)",
                                        (long long)layout->n, P);
     if (P > 4096) return fail(TDMA_EINVAL, "partitions = %d (> 4096)", P);
-    if (nstreams < 1 || nstreams > 8) return fail(TDMA_EINVAL, "nstreams = %d (1..8)", nstreams);
-    if (schedule != 0 && schedule != 1) return fail(TDMA_EINVAL, "schedule = %d (0 or 1)", schedule);
+    if (nstreams < 0 || nstreams > 8) return fail(TDMA_EINVAL, "nstreams = %d (1..8)", nstreams);
+    if (sched_opt < 0 || sched_opt > 2) return fail(TDMA_EINVAL, "schedule = %d (0, 1 or 2)", sched_opt);
     if (batch < 0) return fail(TDMA_EINVAL, "batch = %lld (< 0)", (long long)batch);
     DeviceCtx *ctx = nullptr;
     rc = get_ctx(&ctx);
     if (rc != TDMA_OK) return rc;
-    if (batch == 0 && !lookup_tuned_batch(ctx->dev, layout, coeffs, dtype, P, &batch, &nstreams, &schedule))
-        batch = 16384;
+    // unset fields: the autotuned values for this shape if cached, else the
+    // measured defaults (batches of 32,768 systems, 4 streams, round robin)
+    int64_t t_batch = 32768;
+    int t_streams = 4, t_sched = 1;
+    (void)lookup_tuned_batch(ctx->dev, layout, coeffs, dtype, P, &t_batch, &t_streams, &t_sched);
+    if (batch == 0) batch = t_batch;
+    if (nstreams == 0) nstreams = t_streams;
+    // the pipeline's own numbering: 0 = stage roles, 1 = round robin
+    const int schedule = sched_opt == 0 ? t_sched : (sched_opt == 1 ? 1 : 0);
     return pipeline_solve(ctx, layout, coeffs, dtype, d, x, P, batch, nstreams, schedule,
                           (hipStream_t)stream);
 }

@@ -47,7 +47,8 @@ hipError_t launch_fused(int dtype, const SysMap &map, const Coef &coef, const Ti
                         const void *d, void *x, int *err_flag, hipStream_t stream);
 bool fused_supported(int dtype, const TileShape &shape);
 int fused_max_threads(int dtype, int M);
-size_t fused_lds_bytes(int dtype, const TileShape &shape);
+// LDS bytes of a fused launch; shared_rows: with the operator's rows in LDS.
+size_t fused_lds_bytes(int dtype, const TileShape &shape, bool shared_rows = false);
 
 // shared-operator launchers (shared.hip)
 hipError_t launch_shared(int dtype, const SysMap &map, const Coef &coef, const TileShape &shape,

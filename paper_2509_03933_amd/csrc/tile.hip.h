@@ -177,6 +177,65 @@ __device__ __forceinline__ void substitute_partition(const T (&av)[M], const T (
     dv[0] = xf;
 }
 
+// Stage A with the coefficient rows read from LDS (a shared operator): CA,
+// CB, CC point at the partition's first row of the tile's a, b and c rows;
+// `sh` is added to the diagonal of the first rows_here rows (a per-system
+// shift; the rows past the system are identity rows).  On return ah, ch and
+// dv hold a^, c^ and d^ of rows 1..M-1, as reduce_partition leaves them, so
+// that substitute_partition(ah, ch, dv, ...) finishes the partition; only
+// three values per row stay in registers.
+template <typename T, int M, bool SHIFT>
+__device__ __forceinline__ Iface reduce_partition_rows(const T *CA, const T *CB, const T *CC,
+                                                       T sh, int rows_here, T (&ah)[M], T (&ch)[M],
+                                                       T (&dv)[M], bool &bad) {
+    static_assert(M >= 2, "a partition needs at least two rows");
+    auto bj = [&](int j) {
+        T b = CB[j];
+        if constexpr (SHIFT) b += j < rows_here ? sh : T(0);
+        return b;
+    };
+    T piv = bj(0);
+    bad |= bad_pivot(piv);
+    T ib = recip(piv);
+    const T a0 = CA[0] * ib, c0 = CC[0] * ib, d0 = dv[0] * ib;
+    piv = bj(1);
+    bad |= bad_pivot(piv);
+    ib = recip(piv);
+    ah[1] = CA[1] * ib;
+    ch[1] = CC[1] * ib;
+    dv[1] *= ib;
+#pragma unroll
+    for (int j = 2; j < M; ++j) {
+        const T aj = CA[j];
+        piv = bj(j) - aj * ch[j - 1];
+        bad |= bad_pivot(piv);
+        ib = recip(piv);
+        const T ra = aj * ib;
+        dv[j] = (dv[j] - aj * dv[j - 1]) * ib;
+        ch[j] = CC[j] * ib;
+        ah[j] = -ra * ah[j - 1];
+    }
+    T pi = T(1), dt1 = T(0), at1 = T(0);
+#pragma unroll
+    for (int j = 1; j <= M - 2; ++j) {
+        dt1 += pi * dv[j];
+        at1 += pi * ah[j];
+        pi = -ch[j] * pi;
+    }
+    const T ct1 = -pi;
+    Iface f;
+    const double den = 1.0 - (double)c0 * (double)at1;
+    bad |= bad_pivot(den);
+    const double rho = recip(den);
+    f.fa = rho * (double)a0;
+    f.fc = -rho * (double)c0 * (double)ct1;
+    f.fd = rho * ((double)d0 - (double)c0 * (double)dt1);
+    f.la = (double)ah[M - 1];
+    f.lc = (double)ch[M - 1];
+    f.ld = (double)dv[M - 1];
+    return f;
+}
+
 // Stage B: PCR over the 2P interface rows of the S systems of a tile, in LDS.
 // Row i of system s lives at i*S + s of each of the three arrays (unit
 // diagonal kept implicit).  Lane (p, s) owns rows 2p and 2p+1; every thread
@@ -334,8 +393,8 @@ __device__ __forceinline__ void rows_prefetch(const Coef &coef, int64_t n, RowRe
     }
 }
 
-template <typename T, int CR>
-__device__ __forceinline__ void rows_commit(double *CO, const Coef &coef, int64_t n, int R,
+template <typename T, int CR, typename LT = double>
+__device__ __forceinline__ void rows_commit(LT *CO, const Coef &coef, int64_t n, int R,
                                             const RowRegs<CR> &rr) {
     const int nth = (int)blockDim.x;
 #pragma unroll
@@ -343,17 +402,17 @@ __device__ __forceinline__ void rows_commit(double *CO, const Coef &coef, int64_
         const int r = (int)threadIdx.x + i * nth;
         if (r < R) {
             const bool in = r < n;
-            CO[r] = in && r > 0 ? rr.a[i] : 0.0;
-            CO[R + r] = in ? rr.b[i] : 1.0;
-            CO[2 * R + r] = in && r < n - 1 ? rr.c[i] : 0.0;
+            CO[r] = (LT)(in && r > 0 ? rr.a[i] : 0.0);
+            CO[R + r] = (LT)(in ? rr.b[i] : 1.0);
+            CO[2 * R + r] = (LT)(in && r < n - 1 ? rr.c[i] : 0.0);
         }
     }
     const T *A = (const T *)coef.a, *B = (const T *)coef.b, *C = (const T *)coef.c;
     for (int r = (int)threadIdx.x + CR * nth; r < R; r += nth) {
         const bool in = r < n;
-        CO[r] = in && r > 0 ? (double)A[r] : 0.0;
-        CO[R + r] = in ? (double)B[r] : 1.0;
-        CO[2 * R + r] = in && r < n - 1 ? (double)C[r] : 0.0;
+        CO[r] = (LT)(in && r > 0 ? (double)A[r] : 0.0);
+        CO[R + r] = (LT)(in ? (double)B[r] : 1.0);
+        CO[2 * R + r] = (LT)(in && r < n - 1 ? (double)C[r] : 0.0);
     }
     __syncthreads();
 }

@@ -51,7 +51,7 @@ def test_bit_identical_across_batching_and_streams():
     assert parity.per_system_error(p.layout, base, ref).max() <= parity.TOL_F64
     for batch in (1, 7, 255, 256, 170, 509, 4096):
         for nstreams in (1, 2, 4, 8):
-            for schedule in (0, 1):
+            for schedule in (0, 1, 2):
                 x = _solve(p, coeffs, td, partitions=8, batch=batch, nstreams=nstreams,
                            schedule=schedule)
                 assert np.array_equal(x, base), (batch, nstreams, schedule)
