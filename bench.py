@@ -33,6 +33,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "G unknowns/s & % HBM peak: FP32+refine vs FP64 at ≤1e-12 rel err, 1 GPU"
+# Precision form at the metric's error bar: two refinement steps, a system
+# converged when its last correction is <= 1e-12 of its solution (else the
+# FP64 fallback takes it); the error against the oracle is reported beside.
+REFINE_ITERS = 2
+REFINE_TOL = 1e-12
 HBM_PEAK_GBS = 8000.0
 CSRC = "paper_2509_03933_amd/csrc/"
 KERNEL_SOURCES = {
@@ -193,14 +198,16 @@ def bench_adi(args):
         "roofline": roofline(bytes_step, ms, kernel, f"{kernel}_adi{nx}x{ny}x{nz}_{args.dtype}"),
     }
     if args.dtype == "f64" and not args.no_refine:
-        msr = timed(lambda i: tdma.solve_refined(lay, coeffs, ds[i % n], xs[i % n], report=False,
-                                                 stream=st), args.steps, args.warmup, st)
-        rep = tdma.solve_refined(lay, coeffs, ds[0], xs[0], report=True, stream=st)
+        msr = timed(lambda i: tdma.solve_refined(lay, coeffs, ds[i % n], xs[i % n], REFINE_ITERS,
+                                                 REFINE_TOL, report=False, stream=st),
+                    args.steps, args.warmup, st)
+        rep = tdma.solve_refined(lay, coeffs, ds[0], xs[0], REFINE_ITERS, REFINE_TOL, report=True,
+                                 stream=st)
         xr = xs[0].cpu().numpy()
         out["fp32_refine"] = {
             "value": round(unknowns / (msr * 1e-3) / 1e9, 3), "ms_per_step": round(msr, 6),
             "max_rel_err_vs_oracle": sampled_error(p, xr, samp), "report": rep,
-            "entry_point": "tdma_solve_refined (3 steps, tol 1e-15, FP64 fallback)",
+            "entry_point": f"tdma_solve_refined ({REFINE_ITERS} steps, tol {REFINE_TOL:g}, FP64 fallback)",
             "roofline": roofline(bytes_step, msr, "k_shared_refine",
                                  f"k_shared_refine_adi{nx}x{ny}x{nz}_f64"),
             "faster_than_fp64": msr < ms,
@@ -252,8 +259,8 @@ def bench_poisson(args):
         tdma.solve_batched(pin.layout, pco, d, x, stream=st)
 
     def refined(i):
-        tdma.solve_refined(lay, coeffs, d, x, report=False, stream=st)
-        tdma.solve_refined(pin.layout, pco, d, x, report=False, stream=st)
+        tdma.solve_refined(lay, coeffs, d, x, REFINE_ITERS, REFINE_TOL, report=False, stream=st)
+        tdma.solve_refined(pin.layout, pco, d, x, REFINE_ITERS, REFINE_TOL, report=False, stream=st)
 
     unknowns = lay.unknowns()
     low = [(kx % nx) + nx * (ky % ny) for kx in range(-3, 4) for ky in range(-3, 4) if (kx, ky) != (0, 0)]
@@ -261,8 +268,8 @@ def bench_poisson(args):
     ms = timed(fp64, steps, 1, st)
     e64 = sampled_error(p, x.cpu().numpy(), samp, ld_fallback=True)
     msr = timed(refined, steps, 1, st)
-    rep = tdma.solve_refined(lay, coeffs, d, x, report=True, stream=st)
-    tdma.solve_refined(pin.layout, pco, d, x, stream=st)
+    rep = tdma.solve_refined(lay, coeffs, d, x, REFINE_ITERS, REFINE_TOL, report=True, stream=st)
+    tdma.solve_refined(pin.layout, pco, d, x, REFINE_ITERS, REFINE_TOL, stream=st)
     er = sampled_error(p, x.cpu().numpy(), samp, ld_fallback=True)
     return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
                "dtype": "f64", "steps": steps,

@@ -16,12 +16,13 @@ def _run(p, dtype=np.float64, inplace=False, shape=None):
     a, b, c, d = parity.host_problem(p)
     if dtype == np.float32:
         # the FP32 path solves the FP32-rounded problem; the oracle sees the same values
+        import dataclasses
         a, b, c, d = [None if v is None else v.astype(np.float32).astype(np.float64)
                       for v in (a, b, c, d)]
+        if p.shift is not None:
+            p = dataclasses.replace(p, shift=p.shift.astype(np.float32).astype(np.float64))
     ref = parity.oracle_solution(p, a, b, c, d)
     coeffs = parity.device_coeffs(p, a, b, c, tt)
-    if p.shift is not None and dtype == np.float32:
-        pass
     (td,) = parity.to_device([d], tt)
     tx = td if inplace else torch.full_like(td, float("nan"))
     if shape is None:
@@ -80,6 +81,43 @@ def test_poisson_shift_fp64():
         ok, e64, eld, eorc = parity.conditioned_error(x[p.layout.sys_rows(int(s))], sa, sb, sc, sd,
                                                       parity.TOL_F64)
         assert ok, (int(s), e64, eld, eorc)
+
+
+def _contiguous(p):
+    """The same systems stored with contiguous rows (system s at s*n)."""
+    import dataclasses
+    nsys = p.layout.nsys
+    lay = configs.Layout(n=p.layout.n, nsys0=nsys, nsys1=1, row_stride=1, sys_stride0=p.layout.n,
+                         sys_stride1=0)
+    return dataclasses.replace(p, layout=lay)
+
+
+def _adi_with_shift(nx, ny, nz):
+    """The ADI operator plus a seeded per-system diagonal shift in [0, 0.5):
+    a shared operator with a shift, as diagonally dominant as the ADI one."""
+    import dataclasses
+    from workloads import rng
+    p = configs.adi(nx, ny, nz)
+    shift = 0.5 * rng.uniform01(p.seed, rng.STREAM_NOISE, np.arange(p.layout.nsys))
+    return dataclasses.replace(p, shift=shift)
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, parity.TOL_F64), (np.float32, parity.TOL_F32)])
+@pytest.mark.parametrize("shape", [None, dict(M=8, S=4, P=32, kernel=0), dict(M=16, S=2, P=16, kernel=0)],
+                         ids=["default", "M8_S4_P32", "M16_S2_P16"])
+def test_shared_shift_contiguous_rows(shape, dtype, tol):
+    """Shared operator plus per-system shift with contiguous rows (LDS-staged
+    right-hand sides beside the LDS-held operator rows); n = 250 leaves
+    padding rows."""
+    err, _, _ = _run(_contiguous(_adi_with_shift(16, 12, 250)), dtype, shape=shape)
+    assert err.max() <= tol, err.max()
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, parity.TOL_F64), (np.float32, parity.TOL_F32)])
+def test_shared_shift_strided(dtype, tol):
+    """The same with strided z-lines (the FFT-Poisson layout)."""
+    err, _, _ = _run(_adi_with_shift(24, 12, 250), dtype)
+    assert err.max() <= tol, err.max()
 
 
 def test_in_place():
