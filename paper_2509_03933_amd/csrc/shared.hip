@@ -22,16 +22,24 @@ using dev::LaneSys;
 using dev::TileSysLds;
 
 // LDS carve-up, byte offsets (each region 16-byte aligned):
-//   g, h, pi, ah, ch : P x (M+1) values of T (odd pitch against bank conflicts)
-//   part             : 6 x P doubles (K0, K1, AF, GF, AL, GL)
-//   qa               : 3 x nsteps x 2P doubles (pre-step a, c and 1/beta)
-//   xd               : S x (2P+1) doubles (interface right-hand sides)
-//   co               : 3 x P*M doubles (the tile's a, b, c rows, corners removed)
-//   end              : staging of the contiguous-row variant starts here
+//   gh, ac : P x (M+1) pairs of T, {g_j, h_j} and {a^_j, c^_j}: one LDS read
+//            per row for each pair; the partition pitch of M+1 pairs puts the
+//            two partitions a wavefront reads on different banks
+//   pi     : P x (M+1) values of T
+//   part   : 6 x P doubles (K0, K1, AF, GF, AL, GL)
+//   qa     : 3 x nsteps x 2P doubles (pre-step a, c and 1/beta)
+//   xd     : S x (2P+2) doubles (interface right-hand sides, read and written
+//            as pairs; the even pitch keeps both lane mappings conflict-free)
+//   co     : 3 x P*M doubles (the tile's a, b, c rows, corners removed)
+//   end    : staging of the contiguous-row variant starts here
 struct SharedLds {
-    size_t g, h, pi, ah, ch, part, qa, xd, co, end;
+    size_t gh, ac, pi, part, qa, xd, co, end;
     int nsteps;
 };
+
+template <typename T> struct PairOf;
+template <> struct PairOf<double> { using type = double2; };
+template <> struct PairOf<float> { using type = float2; };
 
 __host__ __device__ inline int ilog2i(int v) {
     int r = 0;
@@ -41,23 +49,36 @@ __host__ __device__ inline int ilog2i(int v) {
 
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
+__host__ __device__ inline int xd_pitch(int P) { return 2 * P + 2; }
+
 __host__ __device__ inline SharedLds shared_layout(size_t esz, int M, int P, int S) {
     SharedLds L;
-    const size_t tab = align16((size_t)P * (M + 1) * esz);
-    L.g = 0;
-    L.h = L.g + tab;
-    L.pi = L.h + tab;
-    L.ah = L.pi + tab;
-    L.ch = L.ah + tab;
-    L.part = L.ch + tab;
+    const size_t pairs = align16((size_t)P * (M + 1) * 2 * esz);
+    L.gh = 0;
+    L.ac = L.gh + pairs;
+    L.pi = L.ac + pairs;
+    L.part = align16(L.pi + (size_t)P * (M + 1) * esz);
     L.nsteps = ilog2i(2 * P);
     if ((1 << L.nsteps) < 2 * P) ++L.nsteps;
     L.qa = align16(L.part + 6 * (size_t)P * 8);
     L.xd = align16(L.qa + 3 * (size_t)L.nsteps * 2 * P * 8);
-    L.co = align16(L.xd + (size_t)S * (2 * P + 1) * 8);
+    L.co = align16(L.xd + (size_t)S * xd_pitch(P) * 8);
     L.end = align16(L.co + 3 * (size_t)P * M * 8);
     return L;
 }
+
+// Read side of one partition's factor tables.
+template <typename T>
+struct PartTab {
+    const typename PairOf<T>::type *gh, *ac;
+    const T *pi;
+    __device__ PartTab(const SharedLds &L, const char *base, int p, int M) {
+        using P2 = typename PairOf<T>::type;
+        gh = reinterpret_cast<const P2 *>(base + L.gh) + p * (M + 1);
+        ac = reinterpret_cast<const P2 *>(base + L.ac) + p * (M + 1);
+        pi = reinterpret_cast<const T *>(base + L.pi) + p * (M + 1);
+    }
+};
 
 // contiguous-row variant: staging of S x (P*M+1) values of T, then S tile entries
 __host__ __device__ inline size_t shared_stage_off(const SharedLds &L) { return L.end; }
@@ -119,13 +140,12 @@ template <typename T, typename CT, int M>
 __device__ __forceinline__ void shared_tables(const Coef &coef, int64_t n, const SharedLds &L,
                                               char *base, int tid, int s, int p, int P,
                                               const dev::RowRegs<shared_cr<M>()> &cr, bool &bad) {
+    using P2 = typename PairOf<T>::type;
     const int r0 = p * M;
     const int pitch = M + 1;
-    T *G = reinterpret_cast<T *>(base + L.g);
-    T *H = reinterpret_cast<T *>(base + L.h);
+    P2 *GH = reinterpret_cast<P2 *>(base + L.gh);
+    P2 *AC = reinterpret_cast<P2 *>(base + L.ac);
     T *PI = reinterpret_cast<T *>(base + L.pi);
-    T *AH = reinterpret_cast<T *>(base + L.ah);
-    T *CH = reinterpret_cast<T *>(base + L.ch);
     double *PT = reinterpret_cast<double *>(base + L.part);
     double *K0 = PT, *K1 = PT + P, *AF = PT + 2 * P, *GF = PT + 3 * P, *AL = PT + 4 * P,
            *GL = PT + 5 * P;
@@ -149,14 +169,14 @@ __device__ __forceinline__ void shared_tables(const Coef &coef, int64_t n, const
         bad |= dev::bad_pivot(b0);
         const double ib0 = dev::recip(b0);
         const double ah0 = a0 * ib0, ch0 = c0 * ib0;
-        T *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch, *ah = AH + p * pitch,
-          *ch = CH + p * pitch;
-        g[0] = (T)ib0; h[0] = T(0); pi_t[0] = T(0); ah[0] = (T)ah0; ch[0] = (T)ch0;
+        P2 *gh = GH + p * pitch, *ac = AC + p * pitch;
+        T *pi_t = PI + p * pitch;
+        gh[0] = P2{(T)ib0, T(0)}; pi_t[0] = T(0); ac[0] = P2{(T)ah0, (T)ch0};
         row(1, aj, bj, cj);
         bad |= dev::bad_pivot(bj);
         double gj = dev::recip(bj);
         double ahp = aj * gj, chp = cj * gj;
-        g[1] = (T)gj; h[1] = T(0); ah[1] = (T)ahp; ch[1] = (T)chp;
+        gh[1] = P2{(T)gj, T(0)}; ac[1] = P2{(T)ahp, (T)chp};
         double pi = 1.0, at1 = 0.0;
         if (M > 2) { pi_t[1] = (T)pi; at1 += pi * ahp; pi = -chp * pi; }
 #pragma unroll 1
@@ -168,7 +188,7 @@ __device__ __forceinline__ void shared_tables(const Coef &coef, int64_t n, const
             const double hj = aj * gj;
             ahp = -hj * ahp;
             chp = cj * gj;
-            g[j] = (T)gj; h[j] = (T)hj; ah[j] = (T)ahp; ch[j] = (T)chp;
+            gh[j] = P2{(T)gj, (T)hj}; ac[j] = P2{(T)ahp, (T)chp};
             if (j <= M - 2) { pi_t[j] = (T)pi; at1 += pi * ahp; pi = -chp * pi; }
         }
         pi_t[M - 1] = T(0);
@@ -233,90 +253,172 @@ __device__ __forceinline__ void shared_tables(const Coef &coef, int64_t n, const
 
 }
 
+// The value `v` of the lane DL below / above the caller's lane.  DPP: the
+// lane DL positions lower / higher in the caller's row of 16 lanes (zero when
+// that lane is outside the row), a VALU operand modifier instead of an LDS
+// permute; valid when every system's interface lanes lie in one row.
+// Otherwise a wavefront shuffle (the caller's own value when out of range).
+template <int DL, bool DPP>
+__device__ __forceinline__ double lane_below(double v, int lane) {
+    if constexpr (DPP && DL < 16) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x110 + DL, 0xF, 0xF, true);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x110 + DL, 0xF, 0xF, true);
+        return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+    } else {
+        return __shfl(v, lane >= DL ? lane - DL : lane);
+    }
+}
+
+template <int DL, bool DPP>
+__device__ __forceinline__ double lane_above(double v, int lane) {
+    if constexpr (DPP && DL < 16) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x100 + DL, 0xF, 0xF, true);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x100 + DL, 0xF, 0xF, true);
+        return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+    } else {
+        return __shfl(v, lane + DL < 64 ? lane + DL : lane);
+    }
+}
+
+// The four neighbour values of one PCR step at distance DL: rows 2p and
+// 2p+1 of the lanes DL below (x0, x1) and above (y0, y1).
+template <int DL, bool DPP>
+__device__ __forceinline__ void fetch4(double e0, double e1, int lane, double &x0, double &x1,
+                                       double &y0, double &y1) {
+    x0 = lane_below<DL, DPP>(e0, lane);
+    x1 = lane_below<DL, DPP>(e1, lane);
+    y0 = lane_above<DL, DPP>(e0, lane);
+    y1 = lane_above<DL, DPP>(e1, lane);
+}
+
+// PCR over the right-hand sides e0 = row 2p, e1 = row 2p+1 of one system
+// held by P consecutive lanes, with the recorded coefficient history (QA,
+// QC: pre-step couplings, QB: 1/beta; rows 2p and 2p+1 are adjacent, read as
+// pairs).  A loop, not unrolled, so each step's history is read in its step;
+// the exchange distance picks its DPP form through a uniform switch.
+template <bool DPP>
+__device__ __forceinline__ void rhs_pcr(double &e0, double &e1, const double *QA, const double *QC,
+                                        const double *QB, int P, int p2, int lane) {
+#pragma unroll 1
+    for (int k = 0; (1 << k) < 2 * P; ++k) {
+        const int q = k * 2 * P + 2 * p2;
+        const double2 qa = *reinterpret_cast<const double2 *>(QA + q);
+        const double2 qc = *reinterpret_cast<const double2 *>(QC + q);
+        const double2 qb = *reinterpret_cast<const double2 *>(QB + q);
+        double l0, u0, l1, u1;
+        if (k == 0) {
+            const bool has_lo = p2 > 0, has_hi = p2 < P - 1;
+            const double m = lane_below<1, DPP>(e1, lane);
+            const double pp = lane_above<1, DPP>(e0, lane);
+            l0 = has_lo ? m : 0.0; u0 = e1;
+            l1 = e0; u1 = has_hi ? pp : 0.0;
+        } else {
+            const int dl = 1 << (k - 1);
+            const bool has_lo = p2 >= dl, has_hi = p2 + dl < P;
+            double x0, x1, y0, y1;
+            switch (k) {
+                case 1: fetch4<1, DPP>(e0, e1, lane, x0, x1, y0, y1); break;
+                case 2: fetch4<2, DPP>(e0, e1, lane, x0, x1, y0, y1); break;
+                case 3: fetch4<4, DPP>(e0, e1, lane, x0, x1, y0, y1); break;
+                case 4: fetch4<8, DPP>(e0, e1, lane, x0, x1, y0, y1); break;
+                case 5: fetch4<16, DPP>(e0, e1, lane, x0, x1, y0, y1); break;
+                default: fetch4<32, DPP>(e0, e1, lane, x0, x1, y0, y1); break;
+            }
+            l0 = has_lo ? x0 : 0.0; l1 = has_lo ? x1 : 0.0;
+            u0 = has_hi ? y0 : 0.0; u1 = has_hi ? y1 : 0.0;
+        }
+        e0 = (e0 - qa.x * l0 - qc.x * u0) * qb.x;
+        e1 = (e1 - qa.y * l1 - qc.y * u1) * qb.y;
+    }
+}
+
 // Stage B of the shared-operator kernels: the interface right-hand sides
 // (first/last row of every partition) go through LDS to P consecutive lanes
-// per system, which run the PCR steps with wavefront shuffles using the
-// recorded coefficient history (QA, QC: pre-step couplings, QB: 1/beta).
-// Every thread calls it; returns X_{2p} and X_{2p+1} of the caller's system.
+// per system, which run the PCR steps (DPP row shifts when a system's P
+// lanes lie in one row of 16, else wavefront shuffles) using the recorded
+// coefficient history.  Every thread calls it; returns X_{2p} and X_{2p+1}
+// of the caller's system.
+// PCR_ANY: choose per launch between the two neighbour exchanges; PCR_DPP /
+// PCR_SHFL: the caller guarantees P <= 16 / uses shuffles only.
+enum { PCR_ANY = 0, PCR_DPP = 1, PCR_SHFL = 2 };
+
+template <int MODE = PCR_ANY>
 __device__ __forceinline__ void shared_rhs_pcr(double *XD, const double *QA, const double *QC,
                                                const double *QB, int S, int P, int P_log2, int s,
                                                int p, double df, double dl_, double &xf,
                                                double &xl) {
-    const int xpitch = 2 * P + 1;
-    XD[s * xpitch + 2 * p] = df;
-    XD[s * xpitch + 2 * p + 1] = dl_;
+    const int xpitch = xd_pitch(P);
+    *reinterpret_cast<double2 *>(XD + s * xpitch + 2 * p) = double2{df, dl_};
     __syncthreads();
     {
         const int tid = threadIdx.x;
         const int s2 = tid >> P_log2;
         const int p2 = tid & (P - 1);
         const int lane = tid & 63;
-        const int q2 = s2 * xpitch + 2 * p2;
-        double e0 = XD[q2], e1 = XD[q2 + 1];
-        int k = 0;
-        for (int hh = 1; hh < 2 * P; hh <<= 1, ++k) {
-            const int i0 = 2 * p2, i1 = i0 + 1, bk = k * 2 * P;
-            double l0, u0, l1, u1;
-            if (hh == 1) {
-                const bool has_lo = p2 > 0, has_hi = p2 < P - 1;
-                const double m = __shfl(e1, has_lo ? lane - 1 : lane);
-                const double pp = __shfl(e0, has_hi ? lane + 1 : lane);
-                l0 = has_lo ? m : 0.0; u0 = e1;
-                l1 = e0; u1 = has_hi ? pp : 0.0;
-            } else {
-                const int dl = hh >> 1;
-                const bool has_lo = p2 >= dl, has_hi = p2 + dl < P;
-                const int lo = has_lo ? lane - dl : lane, hi = has_hi ? lane + dl : lane;
-                const double x0 = __shfl(e0, lo), x1 = __shfl(e1, lo);
-                const double y0 = __shfl(e0, hi), y1 = __shfl(e1, hi);
-                l0 = has_lo ? x0 : 0.0; l1 = has_lo ? x1 : 0.0;
-                u0 = has_hi ? y0 : 0.0; u1 = has_hi ? y1 : 0.0;
-            }
-            e0 = (e0 - QA[bk + i0] * l0 - QC[bk + i0] * u0) * QB[bk + i0];
-            e1 = (e1 - QA[bk + i1] * l1 - QC[bk + i1] * u1) * QB[bk + i1];
+        double2 *q2 = reinterpret_cast<double2 *>(XD + s2 * xpitch + 2 * p2);
+        const double2 e = *q2;
+        double e0 = e.x, e1 = e.y;
+        if constexpr (MODE == PCR_DPP) {
+            rhs_pcr<true>(e0, e1, QA, QC, QB, P, p2, lane);
+        } else if constexpr (MODE == PCR_SHFL) {
+            rhs_pcr<false>(e0, e1, QA, QC, QB, P, p2, lane);
+        } else {
+            if (P <= 16)
+                rhs_pcr<true>(e0, e1, QA, QC, QB, P, p2, lane);
+            else
+                rhs_pcr<false>(e0, e1, QA, QC, QB, P, p2, lane);
         }
-        XD[q2] = e0;
-        XD[q2 + 1] = e1;
+        *q2 = double2{e0, e1};
     }
     __syncthreads();
-    xf = XD[s * xpitch + 2 * p];
-    xl = XD[s * xpitch + 2 * p + 1];
+    const double2 r = *reinterpret_cast<const double2 *>(XD + s * xpitch + 2 * p);
+    xf = r.x;
+    xl = r.y;
 }
 
 // Stage A, the right-hand-side interface PCR (Stage B) and Stage C of one
 // tile on the lane's rows dv, with the tables already built; dv becomes x.
 // Every thread of the block calls it.
-template <typename T, int M>
+template <typename T, int M, int MODE = PCR_ANY>
 __device__ __forceinline__ void shared_solve_rows(const SharedLds &L, char *base, int S, int P,
                                                   int P_log2, int s, int p, T (&dv)[M]) {
-    const int pitch = M + 1;
-    const T *g = reinterpret_cast<const T *>(base + L.g) + p * pitch;
-    const T *h = reinterpret_cast<const T *>(base + L.h) + p * pitch;
-    const T *pi_t = reinterpret_cast<const T *>(base + L.pi) + p * pitch;
-    const T *ah = reinterpret_cast<const T *>(base + L.ah) + p * pitch;
-    const T *ch = reinterpret_cast<const T *>(base + L.ch) + p * pitch;
+    const PartTab<T> tab(L, base, p, M);
     const double *PT = reinterpret_cast<const double *>(base + L.part);
     const double *QA = reinterpret_cast<const double *>(base + L.qa);
     const double *QC = QA + L.nsteps * 2 * P, *QB = QC + L.nsteps * 2 * P;
     double *XD = reinterpret_cast<double *>(base + L.xd);
     // Stage A
     const T draw0 = dv[0];
-    dv[1] = g[1] * dv[1];
+    dv[1] = tab.gh[1].x * dv[1];
 #pragma unroll
-    for (int j = 2; j < M; ++j) dv[j] = g[j] * dv[j] - h[j] * dv[j - 1];
+    for (int j = 2; j < M; ++j) {
+        const auto gh = tab.gh[j];
+        dv[j] = gh.x * dv[j] - gh.y * dv[j - 1];
+        // table reads are hoisted at most a few rows ahead (register pressure)
+        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
     T dt1 = T(0);
 #pragma unroll
-    for (int j = 1; j <= M - 2; ++j) dt1 += pi_t[j] * dv[j];
+    for (int j = 1; j <= M - 2; ++j) {
+        dt1 += tab.pi[j] * dv[j];
+        if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
     const double df = PT[p] * (double)draw0 - PT[P + p] * (double)dt1;
     const double dl_ = (double)dv[M - 1];
     // Stage B: right-hand-side-only PCR inside wavefronts
     double xfd, xld;
-    shared_rhs_pcr(XD, QA, QC, QB, S, P, P_log2, s, p, df, dl_, xfd, xld);
+    shared_rhs_pcr<MODE>(XD, QA, QC, QB, S, P, P_log2, s, p, df, dl_, xfd, xld);
     const T xf = (T)xfd;
     // Stage C
     dv[M - 1] = (T)xld;
 #pragma unroll
-    for (int j = M - 2; j >= 1; --j) dv[j] = dv[j] - ah[j] * xf - ch[j] * dv[j + 1];
+    for (int j = M - 2; j >= 1; --j) {
+        const auto ac = tab.ac[j];
+        dv[j] = dv[j] - ac.x * xf - ac.y * dv[j + 1];
+        if ((j & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+    }
     dv[0] = xf;
 }
 
@@ -397,29 +499,32 @@ k_shared(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int *e
     if (bad) atomicOr(err, 1);
 }
 
-// System of a lane in a uniform layout, stepped through the tiles
-// blockIdx.x, blockIdx.x + gridDim.x, ... without a division per step.
+// System of a lane in a uniform layout (fewer than 2^31 systems), stepped
+// through the tiles blockIdx.x, blockIdx.x + gridDim.x, ... without a
+// division per step; 32-bit state.
 struct LaneWalk {
-    int64_t k, s0, s1;         // system index and its two grid coordinates
-    int64_t q, r;              // one step (gridDim.x * S systems) = q rows of nsys0 + r
-    __device__ void init(const SysMap &m, int64_t k0, int64_t step) {
+    int32_t k, s0, s1;         // system index and its two grid coordinates
+    int32_t q, r;              // one step (gridDim.x * S systems) = q rows of nsys0 + r
+    __device__ void init(const SysMap &m, int32_t k0, int32_t step) {
+        const int32_t n0 = (int32_t)m.nsys0;
         k = k0;
-        s1 = k0 / m.nsys0;
-        s0 = k0 - s1 * m.nsys0;
-        q = step / m.nsys0;
-        r = step - q * m.nsys0;
+        s1 = k0 / n0;
+        s0 = k0 - s1 * n0;
+        q = step / n0;
+        r = step - q * n0;
     }
-    __device__ void advance(const SysMap &m, int64_t step) {
+    __device__ void advance(const SysMap &m, int32_t step) {
         k += step;
         s0 += r;
         s1 += q;
-        if (s0 >= m.nsys0) { s0 -= m.nsys0; ++s1; }
+        if (s0 >= (int32_t)m.nsys0) { s0 -= (int32_t)m.nsys0; ++s1; }
     }
+    // the lane's system as load_rows / store_rows take it
     __device__ LaneSys sys(const SysMap &m) const {
         LaneSys l;
         l.valid = k < m.nsys;
         l.id = k;
-        l.base = l.valid ? s0 * m.sys_stride0 + s1 * m.sys_stride1 : 0;
+        l.base = l.valid ? (int64_t)s0 * m.sys_stride0 + (int64_t)s1 * m.sys_stride1 : 0;
         l.nrows = l.valid ? m.n : 0;
         return l;
     }
@@ -430,8 +535,8 @@ struct LaneWalk {
 // blockIdx.x + gridDim.x, ... with two register sets in turn: the next
 // tile's right-hand sides are loaded into one set before the tile in the
 // other set is solved and stored, so loads stay in flight through its
-// barriers and arithmetic.
-template <typename T, int M, typename OffT>
+// barriers and arithmetic.  MODE: the interface exchange (DPP when P <= 16).
+template <typename T, int M, typename OffT, int MODE>
 __global__ void __launch_bounds__((shared_max_threads<T, M>()))
 k_shared_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int64_t ntiles,
                 int *err) {
@@ -444,39 +549,57 @@ k_shared_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2,
     const int r0 = p * M;
     const int64_t rs = map.row_stride;
     const SharedLds L = shared_layout(sizeof(T), M, P, S);
-    const int64_t step = (int64_t)gridDim.x << S_log2;
-    int64_t t = blockIdx.x;
+    const int32_t step = (int32_t)gridDim.x << S_log2;
+    const int32_t nt = (int32_t)ntiles;
+    int32_t t = blockIdx.x;
     LaneWalk w;
     w.init(map, (t << S_log2) + s, step);
     dev::RowRegs<shared_cr<M>()> cr;
     dev::rows_prefetch<T, shared_cr<M>()>(coef, map.n, cr);
     __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the right-hand sides
     T va[M], vb[M];
-    LaneSys sa = w.sys(map), sb;
-    load_rows<T, M, OffT>(d, sa, rs, r0, va);
+    int64_t ba = w.sys(map).base, bb = 0;    // element offsets of the two sets' systems
+    int na = (int)w.sys(map).nrows, nb = 0;  // their rows (0 past the last system)
+    auto lane_of = [&](int64_t b, int nr) {
+        LaneSys l;
+        l.valid = nr > 0;
+        l.id = 0;
+        l.base = b;
+        l.nrows = nr;
+        return l;
+    };
+    load_rows<T, M, OffT>(d, lane_of(ba, na), rs, r0, va);
     bool bad = false;
     shared_tables<T, T, M>(coef, map.n, L, base, tid, s, p, P, cr, bad);
     for (;;) {
         // tile t in va; load tile t + G into vb, then solve va
         w.advance(map, step);
-        sb = w.sys(map);
-        load_rows<T, M, OffT>(d, sb, rs, r0, vb);
+        {
+            const LaneSys l = w.sys(map);
+            bb = l.base;
+            nb = (int)l.nrows;
+        }
+        load_rows<T, M, OffT>(d, lane_of(bb, nb), rs, r0, vb);
         __builtin_amdgcn_sched_barrier(0);
-        mask_rows<T, M>(rows_in(sa, r0, M), va);
-        shared_solve_rows<T, M>(L, base, S, P, P_log2, s, p, va);
-        store_rows<T, M, OffT>(x, sa, rs, r0, va);
+        mask_rows<T, M>(rows_in(lane_of(ba, na), r0, M), va);
+        shared_solve_rows<T, M, MODE>(L, base, S, P, P_log2, s, p, va);
+        store_rows<T, M, OffT>(x, lane_of(ba, na), rs, r0, va);
         t += gridDim.x;
-        if (t >= ntiles) break;
+        if (t >= nt) break;
         // tile t in vb; load tile t + G into va, then solve vb
         w.advance(map, step);
-        sa = w.sys(map);
-        load_rows<T, M, OffT>(d, sa, rs, r0, va);
+        {
+            const LaneSys l = w.sys(map);
+            ba = l.base;
+            na = (int)l.nrows;
+        }
+        load_rows<T, M, OffT>(d, lane_of(ba, na), rs, r0, va);
         __builtin_amdgcn_sched_barrier(0);
-        mask_rows<T, M>(rows_in(sb, r0, M), vb);
-        shared_solve_rows<T, M>(L, base, S, P, P_log2, s, p, vb);
-        store_rows<T, M, OffT>(x, sb, rs, r0, vb);
+        mask_rows<T, M>(rows_in(lane_of(bb, nb), r0, M), vb);
+        shared_solve_rows<T, M, MODE>(L, base, S, P, P_log2, s, p, vb);
+        store_rows<T, M, OffT>(x, lane_of(bb, nb), rs, r0, vb);
         t += gridDim.x;
-        if (t >= ntiles) break;
+        if (t >= nt) break;
     }
     if (bad) atomicOr(err, 1);
 }
@@ -503,17 +626,12 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
     const LaneSys sys = dev::lane_system(map, k0 + s);
     const SharedLds L = shared_layout(sizeof(float), M, P, S);
     const int pitch = M + 1;
-    const float *G = reinterpret_cast<const float *>(base + L.g);
-    const float *H = reinterpret_cast<const float *>(base + L.h);
-    const float *PI = reinterpret_cast<const float *>(base + L.pi);
-    const float *AH = reinterpret_cast<const float *>(base + L.ah);
-    const float *CH = reinterpret_cast<const float *>(base + L.ch);
     const double *PT = reinterpret_cast<const double *>(base + L.part);
     const double *QA = reinterpret_cast<const double *>(base + L.qa);
     const double *QC = QA + L.nsteps * 2 * P, *QB = QC + L.nsteps * 2 * P;
     double *XD = reinterpret_cast<double *>(base + L.xd);
     const double *CO = reinterpret_cast<const double *>(base + L.co);
-    const int xpitch = 2 * P + 1;
+    const int xpitch = xd_pitch(P);
     const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
 
     dev::RowRegs<shared_cr<M>()> cr;
@@ -544,8 +662,7 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
         dev::stage_put<double, M>(stg, tsys, 0.0, S, R, R + 1, invR, s, r0, ld, dv);
     }
 
-    const float *g = G + p * pitch, *h = H + p * pitch, *pi_t = PI + p * pitch;
-    const float *ah = AH + p * pitch, *ch = CH + p * pitch;
+    const PartTab<float> tab(L, base, p, M);
     const double K0 = PT[p], K1 = PT[P + p];
     double xv[M];
     float e[M];
@@ -571,18 +688,24 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
             }
         }
         const float rr0 = e[0];
-        e[1] = g[1] * e[1];
+        e[1] = tab.gh[1].x * e[1];
 #pragma unroll
-        for (int j = 2; j < M; ++j) e[j] = g[j] * e[j] - h[j] * e[j - 1];
+        for (int j = 2; j < M; ++j) {
+            const float2 gh = tab.gh[j];
+            e[j] = gh.x * e[j] - gh.y * e[j - 1];
+        }
         float dt1 = 0.0f;
 #pragma unroll
-        for (int j = 1; j <= M - 2; ++j) dt1 += pi_t[j] * e[j];
+        for (int j = 1; j <= M - 2; ++j) dt1 += tab.pi[j] * e[j];
         const double df = K0 * (double)rr0 - K1 * (double)dt1;
         double xf, xl;
         shared_rhs_pcr(XD, QA, QC, QB, S, P, P_log2, s, p, df, (double)e[M - 1], xf, xl);
         e[M - 1] = (float)xl;
 #pragma unroll
-        for (int j = M - 2; j >= 1; --j) e[j] = e[j] - ah[j] * (float)xf - ch[j] * e[j + 1];
+        for (int j = M - 2; j >= 1; --j) {
+            const float2 ac = tab.ac[j];
+            e[j] = e[j] - ac.x * (float)xf - ac.y * e[j + 1];
+        }
         e[0] = (float)xf;
 #pragma unroll
         for (int j = 0; j < M; ++j) xv[j] += (double)e[j];
@@ -645,17 +768,28 @@ inline bool offsets_fit_32(const SysMap &m, size_t esz) {
     return last >= 0 && (last + 1) * (int64_t)esz <= (int64_t)0xFFFFFFFF;
 }
 
+template <typename T, int M, typename OffT, int MODE>
+hipError_t launch_stream(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
+                         void *x, int *err, size_t lds, hipStream_t st, int64_t blocks,
+                         int P_log2) {
+    const int64_t resident = resident_blocks(k_shared_stream<T, M, OffT, MODE>, sh.threads(), lds);
+    if (resident < 1) return hipErrorInvalidConfiguration;
+    const int64_t grid = blocks < resident ? blocks : resident;
+    hipLaunchKernelGGL((k_shared_stream<T, M, OffT, MODE>), dim3((unsigned)grid), dim3(sh.threads()),
+                       lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, blocks, err);
+    return hipGetLastError();
+}
+
 template <typename T, int M, typename OffT>
 hipError_t launch_strided(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
                           void *x, int *err, size_t lds, hipStream_t st, int64_t blocks,
                           int P_log2) {
     if (sh.kernel == 2) {
-        if (map.offsets || map.sys_list || map.count) return hipErrorInvalidValue;
-        const int64_t resident = resident_blocks(k_shared_stream<T, M, OffT>, sh.threads(), lds);
-        if (resident < 1) return hipErrorInvalidConfiguration;
-        const int64_t grid = blocks < resident ? blocks : resident;
-        hipLaunchKernelGGL((k_shared_stream<T, M, OffT>), dim3((unsigned)grid), dim3(sh.threads()),
-                           lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, blocks, err);
+        if (map.offsets || map.sys_list || map.count || map.nsys >= ((int64_t)1 << 31) - blocks)
+            return hipErrorInvalidValue;
+        if (sh.P <= 16)
+            return launch_stream<T, M, OffT, PCR_DPP>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
+        return launch_stream<T, M, OffT, PCR_SHFL>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
     } else {
         hipLaunchKernelGGL((k_shared<T, M, false, OffT>), dim3((unsigned)blocks), dim3(sh.threads()),
                            lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, err);
