@@ -185,12 +185,17 @@ static int ilog2_floor(int64_t v) {
 // Strided systems: S consecutive systems per tile so that each row load is a
 // full 128-byte line (S = 16 in FP64, 32 in FP32); P partitions of M rows so
 // that P*M covers n.  Contiguous rows: the tile is staged through LDS.
+// Small problems (fewer than 2^20 unknowns) are latency-bound: short
+// partitions (M = 4 first) and one system per tile, so the solve spreads
+// over as many CUs as it can and each lane's serial chain is short.
 bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *out) {
     const int esz = dtype == TDMA_F64 ? 8 : 4;
+    const bool small = n * nsys < ((int64_t)1 << 20);
     const int Ms_f64[] = {16, 8, 4};
     const int Ms_f32[] = {16, 32, 8, 4};
-    const int *Ms = dtype == TDMA_F64 ? Ms_f64 : Ms_f32;
-    const int nM = dtype == TDMA_F64 ? 3 : 4;
+    const int Ms_small[] = {4, 8, 16};
+    const int *Ms = small ? Ms_small : (dtype == TDMA_F64 ? Ms_f64 : Ms_f32);
+    const int nM = small ? 3 : (dtype == TDMA_F64 ? 3 : 4);
     for (int mi = 0; mi < nM; ++mi) {
         const int M = Ms[mi];
         const int64_t P = (n + M - 1) / M;
@@ -204,6 +209,7 @@ bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *o
         while (S_log2 > 0 && ((int64_t)1 << S_log2) * P > maxt) --S_log2;
         // a tile larger than the number of systems only wastes lanes
         while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= nsys) --S_log2;
+        if (small) S_log2 = 0;
         sh.S_log2 = S_log2;
         if (((int64_t)1 << S_log2) * P > maxt) continue;
         if (contig && fused_lds_bytes(dtype, sh) > 96 * 1024) continue;
