@@ -784,9 +784,14 @@ template <typename T, int M, typename OffT>
 hipError_t launch_strided(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
                           void *x, int *err, size_t lds, hipStream_t st, int64_t blocks,
                           int P_log2) {
-    if (sh.kernel == 2) {
-        if (map.offsets || map.sys_list || map.count || map.nsys >= ((int64_t)1 << 31) - blocks)
-            return hipErrorInvalidValue;
+    // the streaming form walks 32-bit system indices of a plain uniform map
+    // (an index reaches at most one grid stride past the last tile, below
+    // 2 * blocks * S); anything else takes the one-tile-per-block form, which
+    // gives the same results
+    const int64_t S = (int64_t)1 << sh.S_log2;
+    const bool stream_ok = !map.offsets && !map.sys_list && !map.count &&
+                           2 * (blocks + 1) * S < ((int64_t)1 << 31);
+    if (sh.kernel == 2 && stream_ok) {
         if (sh.P <= 16)
             return launch_stream<T, M, OffT, PCR_DPP>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
         return launch_stream<T, M, OffT, PCR_SHFL>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
