@@ -105,10 +105,12 @@ int tdma_solve_batched(const tdma_layout *layout, const tdma_coeffs *coeffs, int
  * S*P lanes form one workgroup, at most 1024 (512 when M rows of one array
  * fill 128 bytes).  kernel 1 (shared operator: TDMA_COEF_SHARED without
  * b_shift; coefficient factors built once per workgroup in LDS): M = 8, 16,
- * 32 and P a power of two <= 64.  kernel 2: kernel 1 in streaming form
- * (strided layouts only): as many workgroups as fit the device at once each
- * build the factors once and walk the tiles, loading the next tile's
- * right-hand sides while solving the current one.  Uniform layouts only.
+ * 32 and P a power of two <= 64.  kernel 2: kernel 1 in streaming form: as
+ * many workgroups as fit the device at once each build the factors once and
+ * walk the tiles, loading the next tile's right-hand sides while solving the
+ * current one.  With contiguous rows it streams when the systems are
+ * consecutive (system k at element k*n) and otherwise runs as kernel 1, with
+ * the same results.  Uniform layouts only.
  * Errors: EINVAL for a shape outside these rules or with M*P < n.
  */
 typedef struct tdma_tile {

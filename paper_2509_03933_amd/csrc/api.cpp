@@ -219,11 +219,12 @@ bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *o
     return false;
 }
 
-// Shared-operator kernel: P a power of two <= 64 (one system's interface rows
-// fit one wavefront), M in {16, 32, 8}.  Strided layouts take the streaming
-// form with S = 32 systems per tile (measured best on the 256^3 ADI sweep in
-// FP64 and FP32); contiguous rows take the one-tile-per-block form, S as in
-// the generic rule.
+// Shared-operator kernel, streaming form: P a power of two <= 64 (one
+// system's interface rows fit one wavefront), M in {16, 32, 8}.  Strided
+// layouts take S = 32 systems per tile (measured best on the 256^3 ADI sweep
+// in FP64 and FP32), contiguous rows S = 8 and at least 256 lanes (best on
+// x-lines of n = 384 and 768); both as far as the lanes and LDS allow.  A streaming block holds its CU's LDS for the whole
+// launch, so the whole 160 KB is available to it.
 bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *out) {
     const int Ms[] = {16, 32, 8};
     for (int M : Ms) {
@@ -231,16 +232,16 @@ bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileS
         while (P * M < n) P <<= 1;
         if (P > 64) continue;
         TileShape sh;
-        sh.kernel = contig ? 1 : 2;
+        sh.kernel = 2;
         sh.M = M;
         sh.P = (int)P;
         sh.contig = contig;
-        int S_log2 = contig ? ilog2_floor(std::max<int64_t>(1, 256 / P)) : 5;
-        const int maxt = shared_max_threads(dtype, M);
+        int S_log2 = contig ? ilog2_floor(std::max<int64_t>(8, 256 / P)) : 5;
+        const int maxt = shared_max_threads(dtype, M, sh.kernel, contig);
         while (S_log2 > 0 && ((int64_t)1 << S_log2) * P > maxt) --S_log2;
         while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= nsys) --S_log2;
         sh.S_log2 = S_log2;
-        while (sh.S_log2 > 0 && shared_lds_bytes(dtype, sh) > 64 * 1024) --sh.S_log2;
+        while (sh.S_log2 > 0 && shared_lds_bytes(dtype, sh) > 160 * 1024) --sh.S_log2;
         if (!shared_supported(dtype, sh)) continue;
         *out = sh;
         return true;

@@ -51,7 +51,12 @@ __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t
 
 __host__ __device__ inline int xd_pitch(int P) { return 2 * P + 2; }
 
-__host__ __device__ inline SharedLds shared_layout(size_t esz, int M, int P, int S) {
+// co_transient: the coefficient rows are read only while the tables are
+// built (k_shared, k_shared_stream), so they share the space of the
+// interface exchange, which is first written after that build's barrier;
+// the precision form reads them for every residual and keeps them apart.
+__host__ __device__ inline SharedLds shared_layout(size_t esz, int M, int P, int S,
+                                                   bool co_transient = true) {
     SharedLds L;
     const size_t pairs = align16((size_t)P * (M + 1) * 2 * esz);
     L.gh = 0;
@@ -62,8 +67,14 @@ __host__ __device__ inline SharedLds shared_layout(size_t esz, int M, int P, int
     if ((1 << L.nsteps) < 2 * P) ++L.nsteps;
     L.qa = align16(L.part + 6 * (size_t)P * 8);
     L.xd = align16(L.qa + 3 * (size_t)L.nsteps * 2 * P * 8);
-    L.co = align16(L.xd + (size_t)S * xd_pitch(P) * 8);
-    L.end = align16(L.co + 3 * (size_t)P * M * 8);
+    const size_t xd_bytes = (size_t)S * xd_pitch(P) * 8, co_bytes = 3 * (size_t)P * M * 8;
+    if (co_transient) {
+        L.co = L.xd;
+        L.end = align16(L.xd + (xd_bytes > co_bytes ? xd_bytes : co_bytes));
+    } else {
+        L.co = align16(L.xd + xd_bytes);
+        L.end = align16(L.co + co_bytes);
+    }
     return L;
 }
 
@@ -604,6 +615,130 @@ k_shared_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2,
     if (bad) atomicOr(err, 1);
 }
 
+// Streaming form for contiguous rows of consecutive systems (system k's rows
+// at k*n .. k*n+n-1, fewer than 2^31 elements in all): a tile of S systems
+// is one run of S*n elements, read and written with unit-stride accesses and
+// transposed through LDS, where element e of the run sits at slot e + e/n.
+// Each system thus owns n + 1 slots; its last one stays zero and stands for
+// every identity padding row.  Elements past the run's end are replaced by
+// its last element, on loads (never used) and on stores (the same value to
+// the same address), so both are branch-free.  The next tile's elements are
+// in flight in registers while the current one is solved and written.
+// Index math below starts from dev::opaque_tid() in every phase, so that it
+// is recomputed there rather than hoisted out of the tile loop and kept live
+// in registers; global accesses use 32-bit byte offsets from the tile's
+// (scalar) base pointer.
+template <typename T>
+__device__ __forceinline__ const T &at_off(const T *p, int32_t e) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) +
+                                        (uint32_t)e * (uint32_t)sizeof(T));
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void run_load(const T *dt, int32_t tot, int nt, T (&v)[M]) {
+    const int tid = dev::opaque_tid();
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        const int32_t e = tid + i * nt;
+        v[i] = at_off(dt, e < tot ? e : tot - 1);
+    }
+}
+
+// Lanes per block of k_shared_cstream: it holds a raw tile and a row tile in
+// registers, and its LDS staging buffer leaves room for one block per CU in
+// the usual shapes, so the register budget per lane is raised instead.
+template <typename T, int M>
+constexpr int cstream_max_threads() {
+    return (int)sizeof(T) * M >= 256 ? 256 : ((int)sizeof(T) * M >= 128 ? 512 : 1024);
+}
+
+template <typename T, int M, int MODE>
+__global__ void __launch_bounds__((cstream_max_threads<T, M>()))
+k_shared_cstream(Coef coef, const T *d, T *x, int32_t n, int32_t total, int S_log2, int P_log2,
+                 int32_t ntiles, int *err) {
+    extern __shared__ double lds[];
+    char *base = reinterpret_cast<char *>(lds);
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2, P = 1 << P_log2;
+    const int nt = S * P;
+    const int s = tid & (S - 1);
+    const int p = tid >> S_log2;
+    const SharedLds L = shared_layout(sizeof(T), M, P, S);
+    T *stg = reinterpret_cast<T *>(base + shared_stage_off(L));
+    const int32_t run = S * n, pitch = n + 1;
+    const float invn = 1.0f / (float)n;
+    auto slot = [&](int32_t e) {
+        int se, re;
+        dev::split_elem(e, n, invn, se, re);
+        return e + se;
+    };
+    for (int i = tid; i < S; i += nt) stg[i * pitch + n] = T(0);
+    dev::RowRegs<shared_cr<M>()> cr;
+    dev::rows_prefetch<T, shared_cr<M>()>(coef, n, cr);
+    __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the right-hand sides
+    int32_t t = blockIdx.x;
+    int32_t tb = t * run, tot = total - tb < run ? total - tb : run;
+    T ld[M], dv[M];
+    run_load<T, M>(d + tb, tot, nt, ld);
+    bool bad = false;
+    shared_tables<T, T, M>(coef, n, L, base, tid, s, p, P, cr, bad);   // ends with a barrier
+    for (;;) {
+        // tile t: its elements to LDS, the lane's rows back (padding rows
+        // read the zero slot)
+        {
+            const int q = dev::opaque_tid();
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const int32_t e = q + i * nt;
+                if (e < tot) stg[slot(e)] = ld[i];
+                if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        __syncthreads();
+        {
+            const int q = dev::opaque_tid();
+            const int qs = q & (S - 1), qr = (q >> S_log2) * M;
+            const T *row = stg + qs * pitch;
+#pragma unroll
+            for (int j = 0; j < M; ++j) dv[j] = row[qr + j < n ? qr + j : n];
+        }
+        // the next tile's elements go in flight
+        const int32_t tn = t + (int32_t)gridDim.x;
+        const int32_t tbn = tn * run, totn = total - tbn < run ? total - tbn : run;
+        if (tn < ntiles) run_load<T, M>(d + tbn, totn, nt, ld);
+        __builtin_amdgcn_sched_barrier(0);
+        shared_solve_rows<T, M, MODE>(L, base, S, P, P_log2, s, p, dv);
+        // x of tile t through LDS (every lane read its rows before the
+        // barriers inside the solve); the zero slots are not written
+        {
+            const int q = dev::opaque_tid();
+            const int qs = q & (S - 1), qr = (q >> S_log2) * M;
+            T *row = stg + qs * pitch;
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (qr + j < n) row[qr + j] = dv[j];
+        }
+        __syncthreads();
+        {
+            const int q = dev::opaque_tid();
+            T *xt = x + tb;
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const int32_t e = q + i * nt, ec = e < tot ? e : tot - 1;
+                *reinterpret_cast<T *>(reinterpret_cast<char *>(xt) + (uint32_t)ec * (uint32_t)sizeof(T)) =
+                    stg[slot(ec)];
+                if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (tn >= ntiles) break;
+        t = tn;
+        tb = tbn;
+        tot = totn;
+        __syncthreads();   // the staging slots are read before they are rewritten
+    }
+    if (bad) atomicOr(err, 1);
+}
+
 // Precision form on a shared operator: FP64 d and x in registers, FP32 factor
 // tables (built in FP64, rounded) for the sweeps, FP64 coefficient rows in LDS
 // for the residual r = d - A x, FP64 interface solve.  1 + iters solves, then a
@@ -624,7 +759,7 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
     const int64_t n = map.n;
     const int64_t k0 = dev::xcd_tile(blockIdx.x, gridDim.x) << S_log2;
     const LaneSys sys = dev::lane_system(map, k0 + s);
-    const SharedLds L = shared_layout(sizeof(float), M, P, S);
+    const SharedLds L = shared_layout(sizeof(float), M, P, S, false);
     const int pitch = M + 1;
     const double *PT = reinterpret_cast<const double *>(base + L.part);
     const double *QA = reinterpret_cast<const double *>(base + L.qa);
@@ -802,6 +937,27 @@ hipError_t launch_strided(const SysMap &map, const Coef &coef, const TileShape &
     return hipGetLastError();
 }
 
+// Contiguous rows of consecutive systems (system k at element k*n) with
+// 32-bit element indices up to one grid stride past the last tile.
+inline bool consecutive_32(const SysMap &m, int64_t S, int64_t blocks) {
+    if (m.offsets || m.sys_list || m.count || m.row_stride != 1 || m.sys_stride0 != m.n) return false;
+    if (m.nsys > m.nsys0 && m.sys_stride1 != m.n * m.nsys0) return false;
+    return 2 * (blocks + 1) * S * m.n < ((int64_t)1 << 31);
+}
+
+template <typename T, int M, int MODE>
+hipError_t launch_cstream(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
+                          void *x, int *err, size_t lds, hipStream_t st, int64_t blocks,
+                          int P_log2) {
+    const int64_t resident = resident_blocks(k_shared_cstream<T, M, MODE>, sh.threads(), lds);
+    if (resident < 1) return hipErrorInvalidConfiguration;
+    const int64_t grid = blocks < resident ? blocks : resident;
+    hipLaunchKernelGGL((k_shared_cstream<T, M, MODE>), dim3((unsigned)grid), dim3(sh.threads()),
+                       lds, st, coef, (const T *)d, (T *)x, (int32_t)map.n,
+                       (int32_t)(map.nsys * map.n), sh.S_log2, P_log2, (int32_t)blocks, err);
+    return hipGetLastError();
+}
+
 template <typename T, int M>
 hipError_t launch_m(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
                     void *x, int *err, size_t lds, hipStream_t st) {
@@ -810,6 +966,13 @@ hipError_t launch_m(const SysMap &map, const Coef &coef, const TileShape &sh, co
     if (blocks == 0) return hipSuccess;
     const int P_log2 = ilog2i(sh.P);
     if (sh.contig) {
+        // the streaming form takes consecutive systems; any other contiguous
+        // layout takes the one-tile-per-block form, which gives the same results
+        if (sh.kernel == 2 && consecutive_32(map, S, blocks)) {
+            if (sh.P <= 16)
+                return launch_cstream<T, M, PCR_DPP>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
+            return launch_cstream<T, M, PCR_SHFL>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
+        }
         hipLaunchKernelGGL((k_shared<T, M, true, int64_t>), dim3((unsigned)blocks), dim3(sh.threads()),
                            lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, err);
         return hipGetLastError();
@@ -821,8 +984,9 @@ hipError_t launch_m(const SysMap &map, const Coef &coef, const TileShape &sh, co
 
 }  // namespace
 
-int shared_max_threads(int dtype, int M) {
+int shared_max_threads(int dtype, int M, int kernel, bool contig) {
     const int esz = dtype == TDMA_F64 ? 8 : 4;
+    if (kernel == 2 && contig) return esz * M >= 256 ? 256 : (esz * M >= 128 ? 512 : 1024);
     return esz * M >= 256 ? 512 : 1024;
 }
 
@@ -836,9 +1000,8 @@ size_t shared_lds_bytes(int dtype, const TileShape &sh) {
 
 bool shared_supported(int dtype, const TileShape &sh) {
     if (sh.P < 1 || sh.P > 64 || (sh.P & (sh.P - 1)) != 0) return false;
-    if (sh.kernel == 2 && sh.contig) return false;   // the streaming form is strided only
     if (sh.M != 8 && sh.M != 16 && sh.M != 32) return false;
-    if (sh.threads() > shared_max_threads(dtype, sh.M)) return false;
+    if (sh.threads() > shared_max_threads(dtype, sh.M, sh.kernel, sh.contig)) return false;
     return shared_lds_bytes(dtype, sh) <= 160 * 1024;
 }
 
@@ -863,7 +1026,7 @@ hipError_t launch_shared(int dtype, const SysMap &map, const Coef &coef, const T
 
 size_t shared_refine_lds_bytes(const TileShape &sh) {
     const int S = 1 << sh.S_log2;
-    const SharedLds L = shared_layout(4, sh.M, sh.P, S);
+    const SharedLds L = shared_layout(4, sh.M, sh.P, S, false);
     if (!sh.contig) return L.end;
     return shared_tsys_off(L, 8, sh.M, sh.P, S) + 16 * (size_t)S;
 }

@@ -54,7 +54,9 @@ size_t fused_lds_bytes(int dtype, const TileShape &shape, bool shared_rows = fal
 hipError_t launch_shared(int dtype, const SysMap &map, const Coef &coef, const TileShape &shape,
                          const void *d, void *x, int *err_flag, hipStream_t stream);
 bool shared_supported(int dtype, const TileShape &shape);
-int shared_max_threads(int dtype, int M);
+// lanes per block of the shared-operator kernels (kernel 2 with contiguous
+// rows: the form that streams them, which holds two tiles in registers)
+int shared_max_threads(int dtype, int M, int kernel, bool contig);
 size_t shared_lds_bytes(int dtype, const TileShape &shape);
 
 }  // namespace tdma

@@ -221,3 +221,46 @@ def test_adi_sweeps_all_directions(dtype, tol):
 def test_shared_fp32_padding():
     err, _, _ = _run(configs.adi(33, 7, 100), np.float32)
     assert err.max() <= parity.TOL_F32, err.max()
+
+
+CSTREAM_SHAPES = [dict(M=16, S=16, P=16, kernel=2), dict(M=8, S=8, P=32, kernel=2),
+                  dict(M=32, S=16, P=8, kernel=2), dict(M=16, S=1, P=16, kernel=2),
+                  dict(M=8, S=4, P=64, kernel=2)]
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, parity.TOL_F64), (np.float32, parity.TOL_F32)])
+@pytest.mark.parametrize("shape", CSTREAM_SHAPES,
+                         ids=lambda s: "M%d_S%d_P%d" % (s["M"], s["S"], s["P"]))
+def test_shared_streaming_contiguous_rows(shape, dtype, tol):
+    """Streaming form with contiguous rows of consecutive systems (x-lines):
+    8,000 systems of n = 250 walk several tiles per workgroup through the LDS
+    transpose; n = 250 leaves identity padding rows, and 8,000 systems a
+    partial last tile for S = 16."""
+    px, _, _ = configs.sweeps(250, 80, 100)
+    err, _, _ = _run(px, dtype, shape=shape)
+    assert err.max() <= tol, err.max()
+
+
+@pytest.mark.parametrize("grid", [(256, 40, 50), (1000, 3, 7), (17, 5, 3)])
+def test_shared_streaming_contiguous_sizes(grid):
+    """The default contiguous-row shape at n = 256 (no padding rows), at
+    n = 1000 (P = 64 partitions of 16 rows) with 21 systems (one partial
+    tile), and at n = 17 (mostly padding)."""
+    px, _, _ = configs.sweeps(*grid)
+    err, _, _ = _run(px)
+    assert err.max() <= parity.TOL_F64, err.max()
+
+
+def test_shared_streaming_contiguous_gapped_layout():
+    """Contiguous rows whose systems are not consecutive (6 unused elements
+    after each system): the streaming shape runs the one-tile-per-block form
+    and gives the oracle's answer."""
+    import dataclasses
+    p = configs.adi(20, 30, 256)            # right-hand sides defined on 256 x 600 elements
+    a, b, c = p.a[:250].copy(), p.b[:250].copy(), p.c[:250].copy()
+    c[-1] = 0.0
+    lay = configs.Layout(n=250, nsys0=p.layout.nsys, nsys1=1, row_stride=1, sys_stride0=256,
+                         sys_stride1=0)
+    q = dataclasses.replace(p, layout=lay, a=a, b=b, c=c)
+    err, _, _ = _run(q, shape=dict(M=16, S=16, P=16, kernel=2))
+    assert err.max() <= parity.TOL_F64, err.max()
