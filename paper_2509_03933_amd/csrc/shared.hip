@@ -739,67 +739,34 @@ k_shared_cstream(Coef coef, const T *d, T *x, int32_t n, int32_t total, int S_lo
     if (bad) atomicOr(err, 1);
 }
 
-// Precision form on a shared operator: FP64 d and x in registers, FP32 factor
-// tables (built in FP64, rounded) for the sweeps, FP64 coefficient rows in LDS
-// for the residual r = d - A x, FP64 interface solve.  1 + iters solves, then a
-// per-system convergence test (max|correction| <= tol max|x|); systems that
-// miss it are listed for the FP64 fallback.
-template <int M, bool CONTIG>
-__global__ void __launch_bounds__((M >= 16 ? 512 : 1024))
-k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, int P_log2,
-                int iters, double tol, RefineState *state) {
-    extern __shared__ double lds[];
-    char *base = reinterpret_cast<char *>(lds);
+// Precision form on one tile of a shared operator, the lane's FP64
+// right-hand sides dv in registers (tables built as FP32, rows past the
+// system's end zero): 1 + iters FP32 solves, the residual r = d - A x and
+// the interface solve in FP64 (coefficient rows in LDS), corrections summed
+// into xv.  Then the per-system convergence test (max|last correction| <=
+// tol max|x|): the systems that miss are appended to the fallback list, and
+// thread 0 gets the tile's largest ratio (0 elsewhere), which the caller
+// folds into the state -- atomics on one address serialise, so kernels issue
+// few of them.  Every thread of the block calls it; it ends with a barrier,
+// after which the interface exchange buffer is free again, except for the
+// ratios thread 0 reads.
+template <int M, int MODE>
+__device__ __forceinline__ double refine_rows(const SharedLds &L, char *base, int S, int P,
+                                            int P_log2, int s, int p, int iters, double tol,
+                                            bool bad, bool valid, int64_t sys_id,
+                                            RefineState *state, const double (&dv)[M],
+                                            double (&xv)[M]) {
     const int tid = threadIdx.x;
-    const int S = 1 << S_log2, P = 1 << P_log2;
-    const int s = tid & (S - 1);
-    const int p = tid >> S_log2;
     const int r0 = p * M;
     const int R = P * M;
-    const int64_t n = map.n;
-    const int64_t k0 = dev::xcd_tile(blockIdx.x, gridDim.x) << S_log2;
-    const LaneSys sys = dev::lane_system(map, k0 + s);
-    const SharedLds L = shared_layout(sizeof(float), M, P, S, false);
-    const int pitch = M + 1;
     const double *PT = reinterpret_cast<const double *>(base + L.part);
     const double *QA = reinterpret_cast<const double *>(base + L.qa);
     const double *QC = QA + L.nsteps * 2 * P, *QB = QC + L.nsteps * 2 * P;
     double *XD = reinterpret_cast<double *>(base + L.xd);
     const double *CO = reinterpret_cast<const double *>(base + L.co);
     const int xpitch = xd_pitch(P);
-    const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
-
-    dev::RowRegs<shared_cr<M>()> cr;
-    dev::rows_prefetch<double, shared_cr<M>()>(coef, n, cr);
-    __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the right-hand sides
-    double dv[M];
-    double *stg = reinterpret_cast<double *>(base + shared_stage_off(L));
-    TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, 8, M, P, S));
-    const float invR = 1.0f / (float)R;
-    if constexpr (!CONTIG) {
-        load_rows<double, M, int64_t>(d, sys, map.row_stride, r0, dv);
-    } else {
-        if (tid < S) {
-            const LaneSys q = dev::lane_system(map, k0 + tid);
-            tsys[tid].base = q.base;
-            tsys[tid].nrows = q.nrows;
-        }
-        __syncthreads();
-        dev::stage_load<double, M>(tsys, d, S, R, invR, dv);
-    }
-    bool bad = false;
-    shared_tables<float, double, M>(coef, n, L, base, tid, s, p, P, cr, bad);
-    if constexpr (!CONTIG) mask_rows<double, M>(rows_here, dv);
-    if constexpr (CONTIG) {
-        double ld[M];
-#pragma unroll
-        for (int j = 0; j < M; ++j) ld[j] = dv[j];
-        dev::stage_put<double, M>(stg, tsys, 0.0, S, R, R + 1, invR, s, r0, ld, dv);
-    }
-
     const PartTab<float> tab(L, base, p, M);
     const double K0 = PT[p], K1 = PT[P + p];
-    double xv[M];
     float e[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) xv[j] = 0.0;
@@ -834,7 +801,7 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
         for (int j = 1; j <= M - 2; ++j) dt1 += tab.pi[j] * e[j];
         const double df = K0 * (double)rr0 - K1 * (double)dt1;
         double xf, xl;
-        shared_rhs_pcr(XD, QA, QC, QB, S, P, P_log2, s, p, df, (double)e[M - 1], xf, xl);
+        shared_rhs_pcr<MODE>(XD, QA, QC, QB, S, P, P_log2, s, p, df, (double)e[M - 1], xf, xl);
         e[M - 1] = (float)xl;
 #pragma unroll
         for (int j = M - 2; j >= 1; --j) {
@@ -856,23 +823,107 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
     if (bad) emax = __builtin_huge_valf();
     XD[s * xpitch + 2 * p] = (double)emax;
     XD[s * xpitch + 2 * p + 1] = xmax;
+    // the system's id (-1 past the last system) in its spare exchange slot
+    if (p == 0) XD[s * xpitch + 2 * P] = __longlong_as_double(valid ? (long long)sys_id : -1ll);
     __syncthreads();
-    if (p == 0 && sys.valid) {
-        double em = 0.0, xm = 0.0;
-        for (int q = 0; q < P; ++q) {
-            em = fmax(em, XD[s * xpitch + 2 * q]);
-            xm = fmax(xm, XD[s * xpitch + 2 * q + 1]);
+    // lane t reads partition (t mod P) of system (t / P): the P partitions of
+    // a system are P adjacent lanes of one wavefront (P divides 64), reduced
+    // by butterfly shuffles; the lane of partition 0 judges the system
+    {
+        const int s2 = tid >> P_log2, p2 = tid & (P - 1);
+        double em = XD[s2 * xpitch + 2 * p2], xm = XD[s2 * xpitch + 2 * p2 + 1];
+        for (int off = P >> 1; off >= 1; off >>= 1) {
+            em = fmax(em, __shfl_xor(em, off));
+            xm = fmax(xm, __shfl_xor(xm, off));
         }
-        const double rel = xm > 0.0 ? em / xm : (em > 0.0 ? 1.0 : 0.0);
-        const bool conv = rel <= tol && rel == rel;
-        atomicMax(&state->max_rel_bits,
-                  (unsigned long long)__double_as_longlong(rel == rel ? rel : 1e300));
-        if (!conv) {
-            const unsigned long long slot = atomicAdd(&state->not_converged, 1ull);
-            if (state->fallback_list && slot < (unsigned long long)state->list_capacity)
-                state->fallback_list[slot] = (int32_t)sys.id;
+        const long long id = s2 < S ? __double_as_longlong(XD[s2 * xpitch + 2 * P]) : -1ll;
+        const bool judge = p2 == 0 && id >= 0;
+        double rel = 0.0;
+        bool miss = false;
+        if (judge) {
+            rel = xm > 0.0 ? em / xm : (em > 0.0 ? 1.0 : 0.0);
+            miss = !(rel <= tol);          // also for NaN
+            if (rel != rel) rel = 1e300;
+        }
+        // (blocks narrower than a wavefront: only their own lanes)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+            if (off < (int)blockDim.x) rel = fmax(rel, __shfl_xor(rel, off));
+        const unsigned long long ball = __ballot(miss);
+        // the wavefront's largest ratio in the second spare slot of row
+        // (wavefront index) -- there are at least as many rows (S) as
+        // wavefronts (S*P/64) -- for thread 0 after the barrier
+        if ((tid & 63) == 0) XD[(tid >> 6) * xpitch + 2 * P + 1] = rel;
+        if (ball) {
+            unsigned long long first = 0;
+            if ((tid & 63) == 0) first = atomicAdd(&state->not_converged, (unsigned long long)__popcll(ball));
+            first = __shfl(first, 0);
+            if (miss) {
+                const unsigned long long slot = first + __popcll(ball & __lanemask_lt());
+                if (state->fallback_list && slot < (unsigned long long)state->list_capacity)
+                    state->fallback_list[slot] = (int32_t)id;
+            }
         }
     }
+    __syncthreads();
+    double rel_max = 0.0;
+    if (tid == 0)
+        for (int w = 0; w < ((int)blockDim.x + 63) >> 6; ++w) rel_max = fmax(rel_max, XD[w * xpitch + 2 * P + 1]);
+    return rel_max;
+}
+
+// Precision form on a shared operator, one tile per block (contiguous rows
+// staged through LDS, or any strided layout).
+template <int M, bool CONTIG>
+__global__ void __launch_bounds__((M >= 16 ? 512 : 1024))
+k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, int P_log2,
+                int iters, double tol, RefineState *state) {
+    extern __shared__ double lds[];
+    char *base = reinterpret_cast<char *>(lds);
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2, P = 1 << P_log2;
+    const int s = tid & (S - 1);
+    const int p = tid >> S_log2;
+    const int r0 = p * M;
+    const int R = P * M;
+    const int64_t n = map.n;
+    const int64_t k0 = dev::xcd_tile(blockIdx.x, gridDim.x) << S_log2;
+    const LaneSys sys = dev::lane_system(map, k0 + s);
+    const SharedLds L = shared_layout(sizeof(float), M, P, S, false);
+    const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
+
+    dev::RowRegs<shared_cr<M>()> cr;
+    dev::rows_prefetch<double, shared_cr<M>()>(coef, n, cr);
+    __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the right-hand sides
+    double dv[M];
+    double *stg = reinterpret_cast<double *>(base + shared_stage_off(L));
+    TileSysLds *tsys = reinterpret_cast<TileSysLds *>(base + shared_tsys_off(L, 8, M, P, S));
+    const float invR = 1.0f / (float)R;
+    if constexpr (!CONTIG) {
+        load_rows<double, M, int64_t>(d, sys, map.row_stride, r0, dv);
+    } else {
+        if (tid < S) {
+            const LaneSys q = dev::lane_system(map, k0 + tid);
+            tsys[tid].base = q.base;
+            tsys[tid].nrows = q.nrows;
+        }
+        __syncthreads();
+        dev::stage_load<double, M>(tsys, d, S, R, invR, dv);
+    }
+    bool bad = false;
+    shared_tables<float, double, M>(coef, n, L, base, tid, s, p, P, cr, bad);
+    if constexpr (!CONTIG) mask_rows<double, M>(rows_here, dv);
+    if constexpr (CONTIG) {
+        double ld[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) ld[j] = dv[j];
+        dev::stage_put<double, M>(stg, tsys, 0.0, S, R, R + 1, invR, s, r0, ld, dv);
+    }
+    double xv[M];
+    const double rel = refine_rows<M, PCR_ANY>(L, base, S, P, P_log2, s, p, iters, tol, bad,
+                                               sys.valid, sys.id, state, dv, xv);
+    if (tid == 0 && rel > 0.0)
+        atomicMax(&state->max_rel_bits, (unsigned long long)__double_as_longlong(rel));
     if constexpr (!CONTIG) {
         double *px = x + sys.base + (int64_t)r0 * map.row_stride;
         const int64_t rs = map.row_stride;

@@ -136,3 +136,19 @@ def test_refined_meets_bar_against_long_double_everywhere():
     e = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     print("pinned mode: refined vs long double", e, rep)
     assert e <= parity.TOL_REFINED, e
+
+
+def test_streaming_form_many_tiles():
+    """65,535 strided systems (several tiles per resident workgroup, a partial
+    last tile, n = 200 with padding rows): two steps at tol 1e-12 meet the
+    bar without fallback; with no refinement step every system misses
+    1e-15, each is listed once for the FP64 fallback, and the result then
+    meets the FP64 bar."""
+    p = configs.adi(257, 255, 200)
+    x, rep, (a, b, c, d) = _refined(p, max_iters=2, tol=1e-12)
+    ref = parity.oracle_solution(p, a, b, c, d)
+    assert parity.per_system_error(p.layout, x, ref).max() <= parity.TOL_REFINED
+    assert rep["fallback_systems"] == 0, rep
+    x, rep, _ = _refined(p, max_iters=0)
+    assert rep["not_converged"] == p.layout.nsys == rep["fallback_systems"], rep
+    assert parity.per_system_error(p.layout, x, ref).max() <= parity.TOL_F64
