@@ -215,6 +215,15 @@ def bench_adi(args):
                                  f"k_shared_refine_adi{nx}x{ny}x{nz}_f64"),
             "faster_than_fp64": msr < ms,
         }
+    # the same memory traffic with no arithmetic (same tile walk and grid):
+    # the ceiling of this access pattern on the device
+    mc = timed(lambda i: tdma.copy_streamed(lay, ds[i % n], xs[i % n], stream=st),
+               args.steps, args.warmup, st)
+    out["pattern_copy"] = {
+        "entry_point": "tdma_copy_streamed", "ms_per_step": round(mc, 6),
+        "GB_s": round(2 * esz * unknowns / (mc * 1e-3) / 1e9, 1),
+        "solve_frac_of_copy": round(mc / ms, 4),
+    }
     return p, out
 
 

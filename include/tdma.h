@@ -124,6 +124,22 @@ int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeff
                              const void *d, void *x, const tdma_tile *tile, void *stream);
 
 /*
+ * tdma_copy_streamed (measurement): dst = src on every system row, moved
+ * with the tile walk, lane-to-row mapping and register double-buffering of
+ * the streaming shared-operator solve that tdma_solve_batched picks for this
+ * layout, on the same number of workgroups, with no arithmetic.  It gives the
+ * memory ceiling of that access pattern on the device, the figure against
+ * which the solve's bandwidth is read.  Uniform strided layouts only
+ * (row_stride != 1); src and dst are device arrays in the layout (elements
+ * outside the systems are not touched) and must differ.  Stream-ordered.
+ * Errors: EINVAL (NULL or equal pointers, bad layout or dtype),
+ * EUNSUPPORTED (contiguous rows, ragged layouts, n > 2048, or a layout past
+ * the walk's 32-bit system indices).
+ */
+int tdma_copy_streamed(const tdma_layout *layout, int dtype, const void *src, void *dst,
+                       void *stream);
+
+/*
  * Options of the split, pipelined solve.  Zero fields take defaults.
  *  partitions  P per system (>= 1, n/P >= 2); 0 = 8.
  *  batch       systems per pipeline batch (the paper's batch_z, Sec. 4.2.1);

@@ -97,6 +97,7 @@ def lib():
             L.tdma_graph_destroy.argtypes = [vp]
             L.tdma_graph_destroy.restype = None
             L.tdma_autotune.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, vp, vp, i, vp]
+            L.tdma_copy_streamed.argtypes = [ctypes.POINTER(_Layout), i, vp, vp, vp]
             L.tdma_check.argtypes = [vp]
             L.tdma_autotune_last_json.restype = ctypes.c_char_p
             L.tdma_pipeline_model_ms.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
@@ -114,6 +115,7 @@ def lib():
 
 
 EXPORTED_SYMBOLS = ("tdma_solve_batched", "tdma_solve_batched_tiled", "tdma_solve_partitioned", "tdma_solve_refined",
+                    "tdma_copy_streamed",
                     "tdma_graph_create", "tdma_graph_launch", "tdma_graph_destroy",
                     "tdma_autotune", "tdma_autotune_last_json", "tdma_pipeline_model_ms",
                     "tdma_check", "tdma_status_string", "tdma_last_error", "tdma_shutdown")
@@ -249,6 +251,18 @@ def solve_batched_tiled(layout, coeffs, d, x, M, S, P, kernel=0, stream=None):
     _raise(lib().tdma_solve_batched_tiled(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),
                                           ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                           ctypes.byref(t), _stream_handle(stream)))
+
+
+def copy_streamed(layout, src, dst, stream=None):
+    """dst = src on every system row with the streaming solve's access pattern
+    and no arithmetic (tdma_copy_streamed): the memory ceiling of that pattern."""
+    keep = []
+    need = _extent(layout)
+    _check_tensor("src", src, need)
+    _check_tensor("dst", dst, need, src.dtype)
+    L = _make_layout(layout, keep)
+    _raise(lib().tdma_copy_streamed(ctypes.byref(L), _dtype_code(src), ctypes.c_void_p(src.data_ptr()),
+                                    ctypes.c_void_p(dst.data_ptr()), _stream_handle(stream)))
 
 
 def solve_partitioned(layout, coeffs, d, x, partitions=0, batch=0, nstreams=0, schedule=0,

@@ -493,6 +493,34 @@ int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeff
     return run_fused(ctx, layout, coeffs, dtype, d, x, (hipStream_t)stream, &sh);
 }
 
+int tdma_copy_streamed(const tdma_layout *layout, int dtype, const void *src, void *dst,
+                       void *stream) {
+    clear_error();
+    if (src == dst && src) return fail(TDMA_EINVAL, "src and dst must differ");
+    tdma_coeffs none{};   // validation only, never read
+    none.a = none.b = none.c = src;
+    none.mode = TDMA_COEF_SHARED;
+    int rc = validate(layout, &none, dtype, src, dst);
+    if (rc != TDMA_OK) return rc;
+    if (layout->offsets) return fail(TDMA_EUNSUPPORTED, "the streamed copy takes uniform layouts");
+    if (layout->row_stride == 1)
+        return fail(TDMA_EUNSUPPORTED, "the streamed copy follows the strided solve (row_stride != 1)");
+    const int64_t nsys = layout->nsys0 * layout->nsys1;
+    if (nsys == 0) return TDMA_OK;
+    TileShape sh;
+    if (!default_shared_shape(dtype, layout->n, nsys, false, &sh))
+        return fail(TDMA_EUNSUPPORTED, "n = %lld has no streaming shape", (long long)layout->n);
+    const SysMap map = make_map(layout);
+    if (!copy_streamed_supported(map, sh))
+        return fail(TDMA_EUNSUPPORTED, "layout beyond the streaming walk's 32-bit indices");
+    DeviceCtx *ctx = nullptr;
+    rc = get_ctx(&ctx);
+    if (rc != TDMA_OK) return rc;
+    const hipError_t e = launch_copy_streamed(dtype, map, sh, src, dst, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "streamed copy launch");
+    return TDMA_OK;
+}
+
 int tdma_check(void *stream) {
     clear_error();
     DeviceCtx *ctx = nullptr;

@@ -615,6 +615,43 @@ k_shared_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2,
     if (bad) atomicOr(err, 1);
 }
 
+// The memory traffic of k_shared_stream alone: the same tile walk, lane rows
+// and register double-buffering, with no tables and no arithmetic (x = d on
+// every system row).  The ceiling of that access pattern, for measurement.
+template <typename T, int M, typename OffT>
+__global__ void __launch_bounds__((shared_max_threads<T, M>()))
+k_copy_stream(SysMap map, const T *d, T *x, int S_log2, int64_t ntiles) {
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2;
+    const int s = tid & (S - 1);
+    const int r0 = (tid >> S_log2) * M;
+    const int64_t rs = map.row_stride;
+    const int32_t step = (int32_t)gridDim.x << S_log2;
+    const int32_t nt = (int32_t)ntiles;
+    int32_t t = blockIdx.x;
+    LaneWalk w;
+    w.init(map, (t << S_log2) + s, step);
+    T va[M], vb[M];
+    LaneSys la = w.sys(map), lb;
+    load_rows<T, M, OffT>(d, la, rs, r0, va);
+    for (;;) {
+        w.advance(map, step);
+        lb = w.sys(map);
+        load_rows<T, M, OffT>(d, lb, rs, r0, vb);
+        __builtin_amdgcn_sched_barrier(0);
+        store_rows<T, M, OffT>(x, la, rs, r0, va);
+        t += gridDim.x;
+        if (t >= nt) break;
+        w.advance(map, step);
+        la = w.sys(map);
+        load_rows<T, M, OffT>(d, la, rs, r0, va);
+        __builtin_amdgcn_sched_barrier(0);
+        store_rows<T, M, OffT>(x, lb, rs, r0, vb);
+        t += gridDim.x;
+        if (t >= nt) break;
+    }
+}
+
 // Streaming form for contiguous rows of consecutive systems (system k's rows
 // at k*n .. k*n+n-1, fewer than 2^31 elements in all): a tile of S systems
 // is one run of S*n elements, read and written with unit-stride accesses and
@@ -1033,6 +1070,28 @@ hipError_t launch_m(const SysMap &map, const Coef &coef, const TileShape &sh, co
     return launch_strided<T, M, int64_t>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
 }
 
+// The copy on the grid the streaming solve of the same shape would get
+// (its resident blocks, with its LDS), so both run at the same concurrency.
+template <typename T, int M, typename OffT>
+hipError_t launch_copy_m(const SysMap &map, const TileShape &sh, const void *d, void *x,
+                         size_t lds, hipStream_t st, int64_t blocks) {
+    const int64_t resident =
+        sh.P <= 16 ? resident_blocks(k_shared_stream<T, M, OffT, PCR_DPP>, sh.threads(), lds)
+                   : resident_blocks(k_shared_stream<T, M, OffT, PCR_SHFL>, sh.threads(), lds);
+    if (resident < 1) return hipErrorInvalidConfiguration;
+    const int64_t grid = blocks < resident ? blocks : resident;
+    hipLaunchKernelGGL((k_copy_stream<T, M, OffT>), dim3((unsigned)grid), dim3(sh.threads()), 0, st,
+                       map, (const T *)d, (T *)x, sh.S_log2, blocks);
+    return hipGetLastError();
+}
+
+template <typename T, int M>
+hipError_t launch_copy_t(const SysMap &map, const TileShape &sh, const void *d, void *x,
+                         size_t lds, hipStream_t st, int64_t blocks) {
+    if (offsets_fit_32(map, sizeof(T))) return launch_copy_m<T, M, uint32_t>(map, sh, d, x, lds, st, blocks);
+    return launch_copy_m<T, M, int64_t>(map, sh, d, x, lds, st, blocks);
+}
+
 }  // namespace
 
 int shared_max_threads(int dtype, int M, int kernel, bool contig) {
@@ -1108,6 +1167,36 @@ hipError_t launch_shared_refine(const SysMap &map, const Coef &coef, const TileS
     TDMA_SR(16, false)
     TDMA_SR(16, true)
 #undef TDMA_SR
+    return hipErrorInvalidValue;
+}
+
+bool copy_streamed_supported(const SysMap &map, const TileShape &sh) {
+    const int64_t S = (int64_t)1 << sh.S_log2;
+    const int64_t blocks = (map.nsys + S - 1) / S;
+    return !sh.contig && !map.offsets && !map.sys_list && !map.count &&
+           2 * (blocks + 1) * S < ((int64_t)1 << 31);
+}
+
+hipError_t launch_copy_streamed(int dtype, const SysMap &map, const TileShape &sh, const void *d,
+                                void *x, hipStream_t st) {
+    const int64_t S = (int64_t)1 << sh.S_log2;
+    const int64_t blocks = (map.nsys + S - 1) / S;
+    if (blocks == 0) return hipSuccess;
+    if (!copy_streamed_supported(map, sh)) return hipErrorInvalidValue;
+    const size_t lds = shared_lds_bytes(dtype, sh);
+    if (dtype == TDMA_F64) {
+        switch (sh.M) {
+            case 8: return launch_copy_t<double, 8>(map, sh, d, x, lds, st, blocks);
+            case 16: return launch_copy_t<double, 16>(map, sh, d, x, lds, st, blocks);
+            case 32: return launch_copy_t<double, 32>(map, sh, d, x, lds, st, blocks);
+        }
+    } else if (dtype == TDMA_F32) {
+        switch (sh.M) {
+            case 8: return launch_copy_t<float, 8>(map, sh, d, x, lds, st, blocks);
+            case 16: return launch_copy_t<float, 16>(map, sh, d, x, lds, st, blocks);
+            case 32: return launch_copy_t<float, 32>(map, sh, d, x, lds, st, blocks);
+        }
+    }
     return hipErrorInvalidValue;
 }
 

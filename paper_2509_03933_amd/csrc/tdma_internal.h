@@ -58,5 +58,9 @@ bool shared_supported(int dtype, const TileShape &shape);
 // rows: the form that streams them, which holds two tiles in registers)
 int shared_max_threads(int dtype, int M, int kernel, bool contig);
 size_t shared_lds_bytes(int dtype, const TileShape &shape);
+// the streaming solve's memory traffic alone (shared.hip), for measurement
+bool copy_streamed_supported(const SysMap &map, const TileShape &shape);
+hipError_t launch_copy_streamed(int dtype, const SysMap &map, const TileShape &shape,
+                                const void *d, void *x, hipStream_t stream);
 
 }  // namespace tdma

@@ -111,3 +111,20 @@ def test_binding_bounds_checks(tdma):
     d = torch.zeros(31, dtype=torch.float64)   # one element short, and on the CPU
     with pytest.raises(ValueError):
         tdma.solve_batched(lay, dict(mode=0, a=d, b=d, c=d), d, d)
+
+
+def test_streamed_copy_validation(tdma):
+    """The measurement copy refuses, on the host, what it does not mirror."""
+    lib = tdma.lib()
+
+    def copy(layout, dtype=0, src=1, dst=2):
+        L = tdma._Layout(*layout, None)
+        return lib.tdma_copy_streamed(ctypes.byref(L), dtype, ctypes.c_void_p(src),
+                                      ctypes.c_void_p(dst), None)
+    strided = (256, 16, 1, 16, 1, 0)          # n, nsys0, nsys1, row_stride, sys_stride0, sys_stride1
+    assert lib.tdma_copy_streamed(None, 0, None, None, None) == tdma.EINVAL
+    assert copy(strided, src=0) == tdma.EINVAL                   # null source
+    assert copy(strided, src=5, dst=5) == tdma.EINVAL            # dst == src
+    assert copy(strided, dtype=3) == tdma.EINVAL                 # unknown dtype
+    assert copy((256, 16, 1, 1, 256, 0)) == tdma.EUNSUPPORTED    # contiguous rows
+    assert copy((4096, 16, 1, 16, 1, 0)) == tdma.EUNSUPPORTED    # n beyond the streaming shape

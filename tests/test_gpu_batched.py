@@ -264,3 +264,22 @@ def test_shared_streaming_contiguous_gapped_layout():
     q = dataclasses.replace(p, layout=lay, a=a, b=b, c=c)
     err, _, _ = _run(q, shape=dict(M=16, S=16, P=16, kernel=2))
     assert err.max() <= parity.TOL_F64, err.max()
+
+
+@pytest.mark.parametrize("tt", ["float64", "float32"])
+def test_streamed_copy_is_exact(tt):
+    """The measurement copy moves every system row bit for bit and leaves the
+    elements outside the systems alone: z-lines of the first 18 of 20
+    x-columns (n = 200, 540 systems; a partial last tile)."""
+    import paper_2509_03933_amd as tdma
+    dt = getattr(torch, tt)
+    nx, ny, nz = 20, 30, 200
+    lay = configs.Layout(n=nz, nsys0=18, nsys1=ny, row_stride=nx * ny, sys_stride0=1,
+                         sys_stride1=nx)
+    src = torch.randn(nx * ny * nz, dtype=torch.float64, device="cuda").to(dt)
+    dst = torch.full_like(src, float("nan"))
+    tdma.copy_streamed(lay, src, dst)
+    torch.cuda.synchronize()
+    s, g = src.view(nz, ny, nx), dst.view(nz, ny, nx)
+    assert torch.equal(g[:, :, :18], s[:, :, :18])
+    assert torch.isnan(g[:, :, 18:]).all()
