@@ -253,31 +253,42 @@ bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileS
 // they need; one launch per non-empty bucket (contiguous rows, LDS-staged).
 // build_ragged_plan allocates the plan's device tables and uploads them
 // synchronously; the caller owns them (free_ragged_plan).
+// Bucket of a ragged system of len rows: M rows per lane (16 in FP64 up to
+// 3,072 rows and 8 beyond, where more lanes per system measured faster; 32
+// and 16 in FP32 at 6,144 rows), P the power of two that covers len / M.
+static void ragged_bucket(int dtype, int64_t len, int *M_out, int *P_out) {
+    const int M = dtype == TDMA_F64 ? (len <= 3072 ? 16 : 8) : (len <= 6144 ? 32 : 16);
+    const int64_t P = (len + M - 1) / M;
+    int64_t Pb = 1;
+    while (Pb < P) Pb <<= 1;
+    *M_out = M;
+    *P_out = (int)std::min<int64_t>(Pb, 1 << 30);
+}
+
 int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out) {
     const int64_t nsys = L->nsys0;
-    const int M = dtype == TDMA_F64 ? 16 : 32;
-    std::map<int, std::vector<int32_t>> buckets;
+    std::map<std::pair<int, int>, std::vector<int32_t>> buckets;   // (M, P) -> systems
     for (int64_t k = 0; k < nsys; ++k) {
         const int64_t len = L->offsets[k + 1] - L->offsets[k];
-        int64_t P = (len + M - 1) / M;
-        int64_t Pp = 1;
-        while (Pp < P) Pp <<= 1;
-        buckets[(int)Pp].push_back((int32_t)k);
+        int M, P;
+        ragged_bucket(dtype, len, &M, &P);
+        buckets[{M, P}].push_back((int32_t)k);
     }
     for (auto &kv : buckets)
-        if (kv.first > fused_max_threads(dtype, M))
+        if (kv.first.second > fused_max_threads(dtype, kv.first.first))
             return fail(TDMA_EUNSUPPORTED, "a ragged system needs %d partitions of %d rows (max %d)",
-                        kv.first, M, fused_max_threads(dtype, M));
+                        kv.first.second, kv.first.first, fused_max_threads(dtype, kv.first.first));
     RaggedPlan rp;
     rp.nsys = nsys;
     std::vector<int32_t> all;
     for (auto &kv : buckets) {
+        const int M = kv.first.first, P = kv.first.second;
         RaggedBucket b;
         b.shape.M = M;
-        b.shape.P = kv.first;
+        b.shape.P = P;
         b.shape.contig = true;
-        int S_log2 = ilog2_floor(std::max(1, 256 / kv.first));
-        while (S_log2 > 0 && (kv.first << S_log2) > fused_max_threads(dtype, M)) --S_log2;
+        int S_log2 = ilog2_floor(std::max(1, 256 / P));
+        while (S_log2 > 0 && (P << S_log2) > fused_max_threads(dtype, M)) --S_log2;
         b.shape.S_log2 = S_log2;
         b.first = (int64_t)all.size();
         b.count = (int64_t)kv.second.size();
@@ -358,17 +369,33 @@ Coef make_coef(const tdma_coeffs *C) {
 
 // One launch per bucket of a ragged plan.
 int launch_ragged(const RaggedPlan &rp, const tdma_layout *L, const tdma_coeffs *C, int dtype,
-                  const void *d, void *x, int *err, hipStream_t st) {
+                  const void *d, void *x, int *err, hipStream_t st, const hipStream_t *aux,
+                  int naux, const hipEvent_t *ev) {
     const Coef coef = make_coef(C);
-    for (const auto &b : rp.buckets) {
+    const int nb = (int)rp.buckets.size();
+    const int nuse = std::max(0, std::min(naux, nb - 1));
+    hipError_t e = hipSuccess;
+    if (nuse > 0) {
+        e = hipEventRecord(ev[0], st);
+        for (int i = 0; i < nuse && e == hipSuccess; ++i) e = hipStreamWaitEvent(aux[i], ev[0], 0);
+        if (e != hipSuccess) return hip_fail(e, "ragged fork");
+    }
+    for (int k = 0; k < nb; ++k) {
+        const RaggedBucket &b = rp.buckets[k];
+        const int lane = k % (nuse + 1);
         SysMap m = make_map(L);
         m.n = (int64_t)b.shape.P * b.shape.M;
         m.nsys = b.count;
         m.offsets = rp.d_offsets;
         m.sys_list = rp.d_list + b.first;
-        hipError_t e = launch_fused(dtype, m, coef, b.shape, d, x, err, st);
+        e = launch_fused(dtype, m, coef, b.shape, d, x, err, lane == 0 ? st : aux[lane - 1]);
         if (e != hipSuccess) return hip_fail(e, "fused launch (ragged)");
     }
+    for (int i = 0; i < nuse && e == hipSuccess; ++i) {
+        e = hipEventRecord(ev[1 + i], aux[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, ev[1 + i], 0);
+    }
+    if (e != hipSuccess) return hip_fail(e, "ragged join");
     return TDMA_OK;
 }
 
@@ -421,7 +448,20 @@ int run_fused(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dt
         const RaggedPlan *rp = nullptr;
         int rc = plan_ragged(ctx, L, dtype, &rp);
         if (rc != TDMA_OK) return rc;
-        return launch_ragged(*rp, L, C, dtype, d, x, ctx->d_err, st);
+        // buckets on the caller's stream and kRaggedAux library streams at
+        // once -- except while the caller's stream is being captured into a
+        // graph, where they stay on that stream
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        const hipError_t ce = hipStreamIsCapturing(st, &cs);
+        if (ce != hipSuccess) return hip_fail(ce, "hipStreamIsCapturing");
+        if (cs != hipStreamCaptureStatusNone)
+            return launch_ragged(*rp, L, C, dtype, d, x, ctx->d_err, st, nullptr, 0, nullptr);
+        hipStream_t *aux = nullptr;
+        hipEvent_t *ev = nullptr;
+        rc = ctx->get_streams(kRaggedAux, &aux);
+        if (rc == TDMA_OK) rc = ctx->get_events(kRaggedAux + 1, &ev);
+        if (rc != TDMA_OK) return rc;
+        return launch_ragged(*rp, L, C, dtype, d, x, ctx->d_err, st, aux, kRaggedAux, ev);
     }
     if (L->nsys0 * L->nsys1 == 0) return TDMA_OK;
     TileShape sh;

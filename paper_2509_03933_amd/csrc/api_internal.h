@@ -57,8 +57,13 @@ bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *o
 int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out);
 void free_ragged_plan(RaggedPlan *rp);
 int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, const RaggedPlan **out);
+// The buckets of a ragged plan on st and up to naux streams aux at once
+// (forked from st by event ev[0], joined back by ev[1..naux]); naux = 0
+// keeps them all on st (the form recorded into graphs).
+constexpr int kRaggedAux = 3;
 int launch_ragged(const RaggedPlan &rp, const tdma_layout *L, const tdma_coeffs *C, int dtype,
-                  const void *d, void *x, int *err, hipStream_t st);
+                  const void *d, void *x, int *err, hipStream_t st, const hipStream_t *aux,
+                  int naux, const hipEvent_t *ev);
 int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dtype,
                  const TileShape *force, TileShape *out);
 int launch_uniform(const TileShape &sh, const tdma_layout *L, const tdma_coeffs *C, int dtype,

@@ -132,7 +132,7 @@ extern "C" int tdma_graph_create(const tdma_work_item *items, int nitems, int dt
         hipStream_t st = pl.side && any_main ? side : cap;
         if (pl.ragged)
             rc = launch_ragged(g->ragged[pl.ragged_index], &it.layout, &it.coeffs, dtype, it.d, it.x,
-                               ctx->d_err, st);
+                               ctx->d_err, st, nullptr, 0, nullptr);
         else
             rc = launch_uniform(pl.shape, &it.layout, &it.coeffs, dtype, it.d, it.x, ctx->d_err, st);
     }
