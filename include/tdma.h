@@ -179,22 +179,31 @@ int tdma_solve_partitioned(const tdma_layout *layout, const tdma_coeffs *coeffs,
  * Options and report of the precision form (mixed-precision refinement).
  *  max_iters  refinement steps after the first FP32 solve, 0..3; the default
  *             (opts NULL) is 3.
- *  tol        a system has converged when max|correction| <= tol*max|x|;
+ *  tol        a system has converged when its tested ratio is <= tol;
  *             default 1e-15.
  *  fallback   1 (default): systems that still miss tol are re-solved by the
  *             FP64 path; 0: they are counted and TDMA_ENOCONV is returned.
+ *  criterion  the tested ratio.  0 (default): the last correction,
+ *             max|dx_k| / max|x|.  1: the error left after the last step as
+ *             the contraction observed between the last two refinement
+ *             corrections predicts it, max|dx_k| q / (1 - q) / max|x| with
+ *             q = max|dx_k| / max|dx_{k-1}| (q >= 1 never converges); it
+ *             needs max_iters >= 2 and is criterion 0 below that.  It keeps
+ *             systems that converge slowly but steadily (ill-conditioned
+ *             ones) out of the FP64 fallback.
  */
 typedef struct tdma_refine_opts {
     int max_iters;
     double tol;
     int fallback;
+    int criterion;
 } tdma_refine_opts;
 
 typedef struct tdma_refine_report {
     int iterations;               /* refinement steps run (max over systems)       */
-    int64_t not_converged;        /* systems whose last correction exceeded tol    */
+    int64_t not_converged;        /* systems whose tested ratio exceeded tol       */
     int64_t fallback_systems;     /* systems re-solved by the FP64 path            */
-    double max_rel_correction;    /* max over systems of the last max|dx|/max|x|   */
+    double max_rel_correction;    /* max over systems of the tested ratio          */
 } tdma_refine_report;
 
 /*

@@ -49,7 +49,8 @@ class _PartOpts(ctypes.Structure):
 
 
 class _RefineOpts(ctypes.Structure):
-    _fields_ = [("max_iters", ctypes.c_int), ("tol", ctypes.c_double), ("fallback", ctypes.c_int)]
+    _fields_ = [("max_iters", ctypes.c_int), ("tol", ctypes.c_double), ("fallback", ctypes.c_int),
+                ("criterion", ctypes.c_int)]
 
 
 class RefineReport(ctypes.Structure):
@@ -276,14 +277,16 @@ def solve_partitioned(layout, coeffs, d, x, partitions=0, batch=0, nstreams=0, s
 
 
 def solve_refined(layout, coeffs, d, x, max_iters=3, tol=1e-15, fallback=1, report=True,
-                  stream=None):
+                  stream=None, criterion=0):
     """FP32 sweeps with FP64 refinement (tdma_solve_refined).  Returns the
-    report as a dict when report=True (the call then synchronises)."""
+    report as a dict when report=True (the call then synchronises).
+    criterion 0 tests the last correction against tol, 1 the remaining error
+    estimated from the observed contraction."""
     import torch
     if d.dtype != torch.float64:
         raise TypeError("tdma_solve_refined takes FP64 d and x")
     L, C, keep = _prepare(layout, coeffs, d, x)
-    o = _RefineOpts(int(max_iters), float(tol), int(fallback))
+    o = _RefineOpts(int(max_iters), float(tol), int(fallback), int(criterion))
     rep = RefineReport()
     _raise(lib().tdma_solve_refined(ctypes.byref(L), ctypes.byref(C), ctypes.c_void_p(d.data_ptr()),
                                     ctypes.c_void_p(x.data_ptr()), ctypes.byref(o),

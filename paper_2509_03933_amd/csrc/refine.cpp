@@ -79,8 +79,11 @@ extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *
     const int iters = opts ? opts->max_iters : 3;
     const double tol = opts && opts->tol > 0.0 ? opts->tol : 1e-15;
     const int fallback = opts ? opts->fallback : 1;
+    const int criterion = opts ? opts->criterion : 0;
     if (iters < 0 || iters > 3) return fail(TDMA_EINVAL, "max_iters = %d (0..3)", iters);
     if (fallback != 0 && fallback != 1) return fail(TDMA_EINVAL, "fallback = %d (0 or 1)", fallback);
+    if (criterion != 0 && criterion != 1)
+        return fail(TDMA_EINVAL, "criterion = %d (0 or 1)", criterion);
     const int64_t nsys = layout->nsys0 * layout->nsys1;
     if (report) std::memset(report, 0, sizeof *report);
     if (nsys == 0) return TDMA_OK;
@@ -99,7 +102,7 @@ extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *
     if (rc != TDMA_OK) return rc;
     RefineState *state = (RefineState *)ws;
     int32_t *list = (int32_t *)((char *)ws + 256);
-    hipError_t e = launch_refine_init(state, list, capacity, st);
+    hipError_t e = launch_refine_init(state, list, capacity, criterion, st);
     if (e != hipSuccess) return hip_fail(e, "refine init");
     const SysMap map = make_map(layout);
     const Coef coef = make_coef(coeffs);

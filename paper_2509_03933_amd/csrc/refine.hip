@@ -187,6 +187,7 @@ k_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, int P, i
 
     double xv[M];
     float e[M];
+    float ecur = 0.0f, eprev = 0.0f;   // largest entry of the last two corrections
 #pragma unroll
     for (int j = 0; j < M; ++j) xv[j] = 0.0;
     for (int it = 0; it <= iters; ++it) {
@@ -237,36 +238,58 @@ k_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, int P, i
 #pragma unroll
         for (int j = M - 2; j >= 1; --j) e[j] = e[j] - fa[j] * (float)xf - fc[j] * e[j + 1];
         e[0] = (float)xf;
+        eprev = ecur;
+        ecur = 0.0f;
 #pragma unroll
-        for (int j = 0; j < M; ++j) xv[j] += (double)e[j];
+        for (int j = 0; j < M; ++j) {
+            xv[j] += (double)e[j];
+            ecur = fmaxf(ecur, fabsf(e[j]));
+        }
     }
-    // convergence of the last correction, per system: max|e| <= tol max|x|
-    float emax = 0.0f;
+    // convergence per system (refine_ratio) from the largest entries of the
+    // last two corrections and of x over the system's partitions
     double xmax = 0.0;
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        emax = fmaxf(emax, fabsf(e[j]));
-        xmax = fmax(xmax, fabs(xv[j]));
-    }
+    for (int j = 0; j < M; ++j) xmax = fmax(xmax, fabs(xv[j]));
     // a zero or non-finite FP32 pivot sends the system to the FP64 fallback
-    if (bad) emax = __builtin_huge_valf();
+    if (bad) ecur = __builtin_huge_valf();
     __syncthreads();
-    XB[s * xpitch + 2 * p] = (double)emax;
+    XB[s * xpitch + 2 * p] = pack_e(ecur, eprev);
     XB[s * xpitch + 2 * p + 1] = xmax;
     __syncthreads();
-    if (p == 0 && sys.valid) {
-        double em = 0.0, xm = 0.0;
-        for (int q = 0; q < P; ++q) {
-            em = fmax(em, XB[s * xpitch + 2 * q]);
-            xm = fmax(xm, XB[s * xpitch + 2 * q + 1]);
+    // the partition-0 lanes (threads 0 .. S-1) judge their systems; their
+    // wavefronts then record misses with one atomicAdd and the largest ratio
+    // with at most one atomicMax each
+    if ((tid & ~63) < S) {
+        double rel = 0.0;
+        bool miss = false;
+        if (p == 0 && sys.valid) {
+            float em = 0.0f, ep = 0.0f;
+            double xm = 0.0;
+            for (int q = 0; q < P; ++q) {
+                float eq, epq;
+                unpack_e(XB[s * xpitch + 2 * q], eq, epq);
+                em = fmaxf(em, eq);
+                ep = fmaxf(ep, epq);
+                xm = fmax(xm, XB[s * xpitch + 2 * q + 1]);
+            }
+            rel = refine_ratio(state->criterion, iters, (double)em, (double)ep, xm);
+            miss = !(rel <= tol);
         }
-        const double rel = xm > 0.0 ? em / xm : (em > 0.0 ? 1.0 : 0.0);
-        const bool conv = rel <= tol && rel == rel;
-        atomicMax(&state->max_rel_bits, (unsigned long long)__double_as_longlong(rel == rel ? rel : 1e300));
-        if (!conv) {
-            const unsigned long long slot = atomicAdd(&state->not_converged, 1ull);
-            if (state->fallback_list && slot < (unsigned long long)state->list_capacity)
-                state->fallback_list[slot] = (int32_t)sys.id;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+            if (off < (int)blockDim.x) rel = fmax(rel, __shfl_xor(rel, off));
+        const unsigned long long ball = __ballot(miss);
+        if ((tid & 63) == 0) fold_max_rel(state, rel);
+        if (ball) {
+            unsigned long long first = 0;
+            if ((tid & 63) == 0) first = atomicAdd(&state->not_converged, (unsigned long long)__popcll(ball));
+            first = __shfl(first, 0);
+            if (miss) {
+                const unsigned long long slot = first + __popcll(ball & __lanemask_lt());
+                if (state->fallback_list && slot < (unsigned long long)state->list_capacity)
+                    state->fallback_list[slot] = (int32_t)sys.id;
+            }
         }
     }
     if constexpr (!CONTIG) {
@@ -376,11 +399,12 @@ k_polish(SysMap map, Coef coef, const double *d, double *x, const int32_t *list,
     }
 }
 
-__global__ void k_refine_init(RefineState *state, int32_t *list, int64_t capacity) {
+__global__ void k_refine_init(RefineState *state, int32_t *list, int64_t capacity, int criterion) {
     state->not_converged = 0ull;
     state->max_rel_bits = 0ull;
     state->fallback_list = list;
     state->list_capacity = capacity;
+    state->criterion = criterion;
 }
 
 template <int M>
@@ -430,8 +454,9 @@ bool refine_supported(const TileShape &sh, bool like_d) {
     return refine_lds_bytes(sh, like_d) <= 160 * 1024;
 }
 
-hipError_t launch_refine_init(RefineState *state, int32_t *list, int64_t capacity, hipStream_t st) {
-    hipLaunchKernelGGL(k_refine_init, dim3(1), dim3(1), 0, st, state, list, capacity);
+hipError_t launch_refine_init(RefineState *state, int32_t *list, int64_t capacity, int criterion,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_refine_init, dim3(1), dim3(1), 0, st, state, list, capacity, criterion);
     return hipGetLastError();
 }
 

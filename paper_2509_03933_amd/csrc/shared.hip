@@ -780,11 +780,9 @@ k_shared_cstream(Coef coef, const T *d, T *x, int32_t n, int32_t total, int S_lo
 // right-hand sides dv in registers (tables built as FP32, rows past the
 // system's end zero): 1 + iters FP32 solves, the residual r = d - A x and
 // the interface solve in FP64 (coefficient rows in LDS), corrections summed
-// into xv.  Then the per-system convergence test (max|last correction| <=
-// tol max|x|): the systems that miss are appended to the fallback list, and
-// thread 0 gets the tile's largest ratio (0 elsewhere), which the caller
-// folds into the state -- atomics on one address serialise, so kernels issue
-// few of them.  Every thread of the block calls it; it ends with a barrier,
+// into xv.  Then the per-system convergence test (refine_ratio <= tol): the
+// systems that miss are appended to the fallback list, and thread 0 gets the
+// tile's largest ratio (0 elsewhere), which the caller folds into the state.  Every thread of the block calls it; it ends with a barrier,
 // after which the interface exchange buffer is free again, except for the
 // ratios thread 0 reads.
 template <int M, int MODE>
@@ -805,6 +803,7 @@ __device__ __forceinline__ double refine_rows(const SharedLds &L, char *base, in
     const PartTab<float> tab(L, base, p, M);
     const double K0 = PT[p], K1 = PT[P + p];
     float e[M];
+    float ecur = 0.0f, eprev = 0.0f;   // largest entry of the last two corrections
 #pragma unroll
     for (int j = 0; j < M; ++j) xv[j] = 0.0;
     for (int it = 0; it <= iters; ++it) {
@@ -846,19 +845,20 @@ __device__ __forceinline__ double refine_rows(const SharedLds &L, char *base, in
             e[j] = e[j] - ac.x * (float)xf - ac.y * e[j + 1];
         }
         e[0] = (float)xf;
+        eprev = ecur;
+        ecur = 0.0f;
 #pragma unroll
-        for (int j = 0; j < M; ++j) xv[j] += (double)e[j];
+        for (int j = 0; j < M; ++j) {
+            xv[j] += (double)e[j];
+            ecur = fmaxf(ecur, fabsf(e[j]));
+        }
         __syncthreads();   // XD is rewritten by the next exchange
     }
-    float emax = 0.0f;
     double xmax = 0.0;
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        emax = fmaxf(emax, fabsf(e[j]));
-        xmax = fmax(xmax, fabs(xv[j]));
-    }
-    if (bad) emax = __builtin_huge_valf();
-    XD[s * xpitch + 2 * p] = (double)emax;
+    for (int j = 0; j < M; ++j) xmax = fmax(xmax, fabs(xv[j]));
+    if (bad) ecur = __builtin_huge_valf();
+    XD[s * xpitch + 2 * p] = pack_e(ecur, eprev);
     XD[s * xpitch + 2 * p + 1] = xmax;
     // the system's id (-1 past the last system) in its spare exchange slot
     if (p == 0) XD[s * xpitch + 2 * P] = __longlong_as_double(valid ? (long long)sys_id : -1ll);
@@ -868,9 +868,12 @@ __device__ __forceinline__ double refine_rows(const SharedLds &L, char *base, in
     // by butterfly shuffles; the lane of partition 0 judges the system
     {
         const int s2 = tid >> P_log2, p2 = tid & (P - 1);
-        double em = XD[s2 * xpitch + 2 * p2], xm = XD[s2 * xpitch + 2 * p2 + 1];
+        float em, ep;
+        unpack_e(XD[s2 * xpitch + 2 * p2], em, ep);
+        double xm = XD[s2 * xpitch + 2 * p2 + 1];
         for (int off = P >> 1; off >= 1; off >>= 1) {
-            em = fmax(em, __shfl_xor(em, off));
+            em = fmaxf(em, __shfl_xor(em, off));
+            ep = fmaxf(ep, __shfl_xor(ep, off));
             xm = fmax(xm, __shfl_xor(xm, off));
         }
         const long long id = s2 < S ? __double_as_longlong(XD[s2 * xpitch + 2 * P]) : -1ll;
@@ -878,9 +881,8 @@ __device__ __forceinline__ double refine_rows(const SharedLds &L, char *base, in
         double rel = 0.0;
         bool miss = false;
         if (judge) {
-            rel = xm > 0.0 ? em / xm : (em > 0.0 ? 1.0 : 0.0);
-            miss = !(rel <= tol);          // also for NaN
-            if (rel != rel) rel = 1e300;
+            rel = refine_ratio(state->criterion, iters, (double)em, (double)ep, xm);
+            miss = !(rel <= tol);
         }
         // (blocks narrower than a wavefront: only their own lanes)
 #pragma unroll
@@ -959,8 +961,7 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
     double xv[M];
     const double rel = refine_rows<M, PCR_ANY>(L, base, S, P, P_log2, s, p, iters, tol, bad,
                                                sys.valid, sys.id, state, dv, xv);
-    if (tid == 0 && rel > 0.0)
-        atomicMax(&state->max_rel_bits, (unsigned long long)__double_as_longlong(rel));
+    if (tid == 0) fold_max_rel(state, rel);
     if constexpr (!CONTIG) {
         double *px = x + sys.base + (int64_t)r0 * map.row_stride;
         const int64_t rs = map.row_stride;

@@ -128,3 +128,19 @@ def test_streamed_copy_validation(tdma):
     assert copy(strided, dtype=3) == tdma.EINVAL                 # unknown dtype
     assert copy((256, 16, 1, 1, 256, 0)) == tdma.EUNSUPPORTED    # contiguous rows
     assert copy((4096, 16, 1, 16, 1, 0)) == tdma.EUNSUPPORTED    # n beyond the streaming shape
+
+
+def test_refined_options_validation(tdma):
+    """Out-of-range refinement options are refused on the host."""
+    lib = tdma.lib()
+    L = tdma._Layout(64, 4, 1, 1, 64, 0, None)
+    C = tdma._Coeffs(0, 3, 4, 5, None)
+
+    def refined(iters=1, tol=1e-12, fallback=1, criterion=0):
+        o = tdma._RefineOpts(iters, tol, fallback, criterion)
+        return lib.tdma_solve_refined(ctypes.byref(L), ctypes.byref(C), ctypes.c_void_p(1),
+                                      ctypes.c_void_p(2), ctypes.byref(o), None, None)
+    assert refined(iters=4) == tdma.EINVAL
+    assert refined(fallback=2) == tdma.EINVAL
+    assert refined(criterion=2) == tdma.EINVAL
+    assert refined(criterion=-1) == tdma.EINVAL

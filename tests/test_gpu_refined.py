@@ -152,3 +152,46 @@ def test_streaming_form_many_tiles():
     x, rep, _ = _refined(p, max_iters=0)
     assert rep["not_converged"] == p.layout.nsys == rep["fallback_systems"], rep
     assert parity.per_system_error(p.layout, x, ref).max() <= parity.TOL_F64
+
+
+@pytest.mark.parametrize("make", [lambda: configs.adi(64, 32, 256),
+                                  lambda: configs.partitioned(20, 12, 300),
+                                  lambda: configs.sweeps(96, 24, 40)[0]],
+                         ids=["adi_shared", "perrow_strided", "shared_contig"])
+def test_contraction_criterion_well_conditioned(make):
+    """Criterion 1 (remaining error estimated from the contraction between
+    the two refinement corrections) at tol 1e-12 after two steps: no
+    fallback on well-conditioned systems, and the 1e-12 bar met."""
+    p = make()
+    x, rep, (a, b, c, d) = _refined(p, max_iters=2, tol=1e-12, criterion=1)
+    ref = parity.oracle_solution(p, a, b, c, d)
+    err = parity.per_system_error(p.layout, x, ref)
+    assert err.max() <= parity.TOL_REFINED, err.max()
+    assert rep["iterations"] == 2 and rep["fallback_systems"] == 0, rep
+    assert rep["max_rel_correction"] <= 1e-12
+
+
+def test_contraction_criterion_poisson_modes():
+    """On the Poisson modes criterion 1 sends fewer systems to the FP64
+    fallback than criterion 0 (slowly but steadily contracting modes are
+    accepted), and every mode still ends within the conditioned bar."""
+    p = configs.poisson(32, 16, 512)
+    _, rep0, _ = _refined(p, max_iters=2, tol=1e-12, criterion=0)
+    x, rep, _ = _refined(p, max_iters=2, tol=1e-12, criterion=1)
+    for s in range(p.layout.nsys):
+        sa, sb, sc, sd = configs.system_inputs(p, s)
+        ok, e64, eld, eorc = parity.conditioned_error(x[p.layout.sys_rows(s)], sa, sb, sc, sd,
+                                                      parity.TOL_REFINED)
+        assert ok, (s, e64, eld, eorc)
+    assert rep["fallback_systems"] == rep["not_converged"] <= rep0["not_converged"], (rep, rep0)
+
+
+def test_contraction_criterion_needs_two_steps():
+    """With one refinement step there is no contraction between corrections
+    to observe: criterion 1 is criterion 0, and at tol 1e-15 every system
+    falls back (and then meets the FP64 bar)."""
+    p = configs.adi(32, 8, 128)
+    x, rep, (a, b, c, d) = _refined(p, max_iters=1, tol=1e-15, criterion=1)
+    assert rep["not_converged"] == p.layout.nsys == rep["fallback_systems"]
+    ref = parity.oracle_solution(p, a, b, c, d)
+    assert parity.per_system_error(p.layout, x, ref).max() <= parity.TOL_F64
