@@ -1,6 +1,5 @@
 // The fused on-chip tile (load -> Stage A -> Stage B -> Stage C -> store) as a
-// device function, shared by the one-tile-per-block kernel (fused.hip) and
-// the persistent work-queue kernel (persist.hip).
+// device function, used by the generic one-tile-per-block kernel (fused.hip).
 #pragma once
 #include "tile.hip.h"
 

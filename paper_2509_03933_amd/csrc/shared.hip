@@ -11,6 +11,11 @@
 //   per PCR step and interface row: the pre-step couplings and 1/beta.
 // The per-system work is then about five FP64 operations per row, and the
 // interface solve exchanges one value per row instead of three.
+// Kernels: k_shared (one tile per workgroup), k_shared_stream (strided
+// layouts: resident workgroups walk the tiles), k_shared_cstream (the same
+// for contiguous rows of consecutive systems, through an LDS transpose),
+// k_shared_refine (the precision form), k_copy_stream (the streaming
+// kernel's memory traffic alone, for measurement).
 #include "refine.h"
 #include "tile.hip.h"
 

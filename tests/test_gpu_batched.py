@@ -283,3 +283,17 @@ def test_streamed_copy_is_exact(tt):
     s, g = src.view(nz, ny, nx), dst.view(nz, ny, nx)
     assert torch.equal(g[:, :, :18], s[:, :, :18])
     assert torch.isnan(g[:, :, 18:]).all()
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 16, 17, 33])
+def test_shared_streaming_short_systems(n):
+    """Shared operator with very short systems (one or two partitions, most
+    rows identity padding) in both streaming forms: contiguous x-lines of n
+    rows and strided z-lines of n rows."""
+    px, _, _ = configs.sweeps(n, 6, 7)
+    _, _, pz = configs.sweeps(5, 6, n)
+    for p in (px, pz):
+        err, _, _ = _run(p)
+        assert err.max() <= parity.TOL_F64, (p.name, n, err.max())
+        err, _, _ = _run(p, np.float32)
+        assert err.max() <= parity.TOL_F32, (p.name, n, err.max())
