@@ -297,3 +297,17 @@ def test_shared_streaming_short_systems(n):
         assert err.max() <= parity.TOL_F64, (p.name, n, err.max())
         err, _, _ = _run(p, np.float32)
         assert err.max() <= parity.TOL_F32, (p.name, n, err.max())
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, parity.TOL_F64), (np.float32, parity.TOL_F32)])
+def test_sweep_lengths_of_the_large_grid(dtype, tol):
+    """The line lengths of the 768 x 512 x 1536 sweeps with few systems, in
+    the default shapes: x-lines of 768 contiguous rows (contiguous streaming
+    form), y-lines of 512 rows, z-lines of 1536 rows (32 rows x 64
+    partitions per system); every system against the oracle."""
+    px, _, _ = configs.sweeps(768, 12, 10)
+    _, py, _ = configs.sweeps(10, 512, 12)
+    _, _, pz = configs.sweeps(10, 12, 1536)
+    for p in (px, py, pz):
+        err, _, _ = _run(p, dtype)
+        assert err.max() <= tol, (p.name, err.max())

@@ -127,6 +127,45 @@ def test_poisson_1024_cubed_fp64_and_refined():
     torch.cuda.empty_cache()
 
 
+def test_sweeps_full_size_one_by_one():
+    """The 768x512x1536 x -> y -> z sweeps through tdma_solve_batched, one call
+    each (no graph); sampled lines of each sweep against the oracle applied
+    to the GPU's own input to that sweep.  Then the 10,000-system ragged batch,
+    every system against the oracle."""
+    import paper_2509_03933_amd as tdma
+    from workloads import device
+    px, py, pz = configs.sweeps()
+    R, _ = device.device_inputs(px)
+    u1, u2, u3 = (torch.empty_like(R) for _ in range(3))
+    shared = lambda p: dict(mode=1, a=torch.from_numpy(p.a).cuda(), b=torch.from_numpy(p.b).cuda(),
+                            c=torch.from_numpy(p.c).cuda())
+    for p, din, xout in ((px, R, u1), (py, u1, u2), (pz, u2, u3)):
+        print("sweep", p.name, "n", p.layout.n, "systems", p.layout.nsys, flush=True)
+        tdma.solve_batched(p.layout, shared(p), din, xout)
+        tdma.check()
+        assert torch.isfinite(xout).all()
+        worst = 0.0
+        for sys_id in _sample(p.layout.nsys, 24):
+            rows = torch.from_numpy(p.layout.sys_rows(int(sys_id))).cuda()
+            ref = oracle.thomas(p.a, p.b, p.c, din[rows].cpu().numpy())
+            got = xout[rows].cpu().numpy()
+            worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+        print("  max rel err", worst, flush=True)
+        assert worst <= parity.TOL_F64, (p.name, worst)
+    del R, u1, u2, u3
+    torch.cuda.empty_cache()
+    rg = configs.ragged()
+    a, b, c, d = configs.full_arrays(rg)
+    ref = oracle.solve_batch(rg.layout, 0, a, b, c, d)
+    dev = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    tx = torch.full_like(dev(d), float("nan"))
+    print("ragged", rg.layout.nsys, "systems", rg.layout.unknowns(), "unknowns", flush=True)
+    tdma.solve_batched(rg.layout, dict(mode=0, a=dev(a), b=dev(b), c=dev(c)), dev(d), tx)
+    tdma.check()
+    err = parity.per_system_error(rg.layout, tx.cpu().numpy(), ref)
+    assert err.max() <= parity.TOL_F64, err.max()
+
+
 @pytest.mark.skip(reason="the first run of this full-size case (with an earlier batching-form "
                   "design that waited on the device between workgroups) went silent for 180 s "
                   "and was stopped; no cause was shown, so the case stays off the GPU for now")
