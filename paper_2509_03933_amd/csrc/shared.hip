@@ -547,8 +547,9 @@ struct LaneWalk {
 };
 
 // Streaming form of k_shared for uniform strided layouts: each resident
-// block builds the tables once, then walks the tiles blockIdx.x,
-// blockIdx.x + gridDim.x, ... with two register sets in turn: the next
+// block builds the tables once, then walks the tiles t0, t0 + gridDim.x, ...
+// (t0 = blockIdx.x, or its XCD-aware image when a tile row is narrower than
+// a 128-byte line) with two register sets in turn: the next
 // tile's right-hand sides are loaded into one set before the tile in the
 // other set is solved and stored, so loads stay in flight through its
 // barriers and arithmetic.  MODE: the interface exchange (DPP when P <= 16).
@@ -567,7 +568,10 @@ k_shared_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2,
     const SharedLds L = shared_layout(sizeof(T), M, P, S);
     const int32_t step = (int32_t)gridDim.x << S_log2;
     const int32_t nt = (int32_t)ntiles;
-    int32_t t = blockIdx.x;
+    // tile rows narrower than a 128-byte line: first tile XCD-aware
+    // (dev::xcd_tile), so that at every step the blocks of one XCD hold
+    // neighbouring tiles, which share lines, under one L2
+    int32_t t = (int32_t)((S * (int)sizeof(T) < 128) ? dev::xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
     LaneWalk w;
     w.init(map, (t << S_log2) + s, step);
     dev::RowRegs<shared_cr<M>()> cr;
@@ -633,7 +637,10 @@ k_copy_stream(SysMap map, const T *d, T *x, int S_log2, int64_t ntiles) {
     const int64_t rs = map.row_stride;
     const int32_t step = (int32_t)gridDim.x << S_log2;
     const int32_t nt = (int32_t)ntiles;
-    int32_t t = blockIdx.x;
+    // tile rows narrower than a 128-byte line: first tile XCD-aware
+    // (dev::xcd_tile), so that at every step the blocks of one XCD hold
+    // neighbouring tiles, which share lines, under one L2
+    int32_t t = (int32_t)((S * (int)sizeof(T) < 128) ? dev::xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
     LaneWalk w;
     w.init(map, (t << S_log2) + s, step);
     T va[M], vb[M];
