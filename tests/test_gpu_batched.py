@@ -311,3 +311,23 @@ def test_sweep_lengths_of_the_large_grid(dtype, tol):
     for p in (px, py, pz):
         err, _, _ = _run(p, dtype)
         assert err.max() <= tol, (p.name, err.max())
+
+
+def test_ragged_long_systems_fp32():
+    """FP32 ragged systems of 4,000 to 16,384 rows (16 rows per lane beyond
+    6,144 rows, up to 1,024 partitions)."""
+    r = configs.ragged(nsys=60, nmin=4000, nmax=16384)
+    err, _, _ = _run(r, np.float32)
+    assert err.max() <= parity.TOL_F32, err.max()
+
+
+def test_ragged_too_long_for_fp64():
+    """An FP64 ragged system beyond 8,192 rows (more than 1,024 partitions of
+    8 rows) is refused with EUNSUPPORTED before any launch."""
+    import paper_2509_03933_amd as tdma
+    offsets = np.array([0, 100, 100 + 9000], dtype=np.int64)
+    lay = configs.Layout(n=9000, nsys0=2, nsys1=1, offsets=offsets)
+    t = torch.zeros(9100, dtype=torch.float64, device="cuda")
+    with pytest.raises(tdma.TdmaError) as ei:
+        tdma.solve_batched(lay, dict(mode=0, a=t, b=t + 1, c=t), t, torch.empty_like(t))
+    assert ei.value.status == tdma.EUNSUPPORTED
