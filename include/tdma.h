@@ -104,13 +104,15 @@ int tdma_solve_batched(const tdma_layout *layout, const tdma_coeffs *coeffs, int
  * 32 (FP32); systems_per_tile S a power of two; partitions P with M*P >= n;
  * S*P lanes form one workgroup, at most 1024 (512 when M rows of one array
  * fill 128 bytes).  kernel 1 (shared operator: TDMA_COEF_SHARED without
- * b_shift; coefficient factors built once per workgroup in LDS): M = 8, 16,
- * 32 and P a power of two <= 64.  kernel 2: kernel 1 in streaming form: as
+ * b_shift; coefficient factors built once per workgroup in LDS): M = 8, 12,
+ * 16, 24, 32 and P a power of two <= 64; at most 1024 lanes, 512 when M
+ * rows of one array fill 192 bytes.  kernel 2: kernel 1 in streaming form: as
  * many workgroups as fit the device at once each build the factors once and
  * walk the tiles, loading the next tile's right-hand sides while solving the
  * current one.  With contiguous rows it streams when the systems are
  * consecutive (system k at element k*n) and otherwise runs as kernel 1, with
- * the same results.  Uniform layouts only.
+ * the same results; with contiguous rows its lanes are capped at 512 when M
+ * rows fill 128 bytes and 256 when they fill 256.  Uniform layouts only.
  * Errors: EINVAL for a shape outside these rules or with M*P < n.
  */
 typedef struct tdma_tile {

@@ -129,7 +129,7 @@ std::vector<TileShape> fused_candidates(int dtype, const tdma_layout *L, const t
     const bool contig = L->row_stride == 1;
     const bool shared_op = C->mode == TDMA_COEF_SHARED && C->b_shift == nullptr;
     if (shared_op) {
-        for (int M : {8, 16, 32}) {
+        for (int M : {8, 12, 16, 24, 32}) {
             int P = 1;
             while ((int64_t)P * M < n) P <<= 1;
             if (P > 64) continue;

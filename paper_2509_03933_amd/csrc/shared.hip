@@ -103,7 +103,7 @@ __host__ __device__ inline size_t shared_tsys_off(const SharedLds &L, size_t esz
 }
 
 template <typename T, int M>
-constexpr int shared_max_threads() { return (int)sizeof(T) * M >= 256 ? 512 : 1024; }
+constexpr int shared_max_threads() { return (int)sizeof(T) * M >= 192 ? 512 : 1024; }
 
 // Coefficient rows held in registers per thread (tile rows P*M over S*P
 // threads: M/S rows each; rows beyond CR per thread are loaded late).
@@ -1110,7 +1110,7 @@ hipError_t launch_copy_t(const SysMap &map, const TileShape &sh, const void *d, 
 int shared_max_threads(int dtype, int M, int kernel, bool contig) {
     const int esz = dtype == TDMA_F64 ? 8 : 4;
     if (kernel == 2 && contig) return esz * M >= 256 ? 256 : (esz * M >= 128 ? 512 : 1024);
-    return esz * M >= 256 ? 512 : 1024;
+    return esz * M >= 192 ? 512 : 1024;
 }
 
 size_t shared_lds_bytes(int dtype, const TileShape &sh) {
@@ -1123,7 +1123,7 @@ size_t shared_lds_bytes(int dtype, const TileShape &sh) {
 
 bool shared_supported(int dtype, const TileShape &sh) {
     if (sh.P < 1 || sh.P > 64 || (sh.P & (sh.P - 1)) != 0) return false;
-    if (sh.M != 8 && sh.M != 16 && sh.M != 32) return false;
+    if (sh.M != 8 && sh.M != 12 && sh.M != 16 && sh.M != 24 && sh.M != 32) return false;
     if (sh.threads() > shared_max_threads(dtype, sh.M, sh.kernel, sh.contig)) return false;
     return shared_lds_bytes(dtype, sh) <= 160 * 1024;
 }
@@ -1134,13 +1134,17 @@ hipError_t launch_shared(int dtype, const SysMap &map, const Coef &coef, const T
     if (dtype == TDMA_F64) {
         switch (sh.M) {
             case 8: return launch_m<double, 8>(map, coef, sh, d, x, err, lds, st);
+            case 12: return launch_m<double, 12>(map, coef, sh, d, x, err, lds, st);
             case 16: return launch_m<double, 16>(map, coef, sh, d, x, err, lds, st);
+            case 24: return launch_m<double, 24>(map, coef, sh, d, x, err, lds, st);
             case 32: return launch_m<double, 32>(map, coef, sh, d, x, err, lds, st);
         }
     } else if (dtype == TDMA_F32) {
         switch (sh.M) {
             case 8: return launch_m<float, 8>(map, coef, sh, d, x, err, lds, st);
+            case 12: return launch_m<float, 12>(map, coef, sh, d, x, err, lds, st);
             case 16: return launch_m<float, 16>(map, coef, sh, d, x, err, lds, st);
+            case 24: return launch_m<float, 24>(map, coef, sh, d, x, err, lds, st);
             case 32: return launch_m<float, 32>(map, coef, sh, d, x, err, lds, st);
         }
     }
@@ -1200,13 +1204,17 @@ hipError_t launch_copy_streamed(int dtype, const SysMap &map, const TileShape &s
     if (dtype == TDMA_F64) {
         switch (sh.M) {
             case 8: return launch_copy_t<double, 8>(map, sh, d, x, lds, st, blocks);
+            case 12: return launch_copy_t<double, 12>(map, sh, d, x, lds, st, blocks);
             case 16: return launch_copy_t<double, 16>(map, sh, d, x, lds, st, blocks);
+            case 24: return launch_copy_t<double, 24>(map, sh, d, x, lds, st, blocks);
             case 32: return launch_copy_t<double, 32>(map, sh, d, x, lds, st, blocks);
         }
     } else if (dtype == TDMA_F32) {
         switch (sh.M) {
             case 8: return launch_copy_t<float, 8>(map, sh, d, x, lds, st, blocks);
+            case 12: return launch_copy_t<float, 12>(map, sh, d, x, lds, st, blocks);
             case 16: return launch_copy_t<float, 16>(map, sh, d, x, lds, st, blocks);
+            case 24: return launch_copy_t<float, 24>(map, sh, d, x, lds, st, blocks);
             case 32: return launch_copy_t<float, 32>(map, sh, d, x, lds, st, blocks);
         }
     }

@@ -182,7 +182,8 @@ def test_singular_flagged():
 SHAPES_SHARED = [dict(M=16, S=16, P=16, kernel=1), dict(M=8, S=16, P=32, kernel=1),
                  dict(M=32, S=16, P=8, kernel=1), dict(M=8, S=8, P=64, kernel=1),
                  dict(M=16, S=1, P=16, kernel=1), dict(M=16, S=16, P=16, kernel=0),
-                 dict(M=16, S=16, P=16, kernel=2), dict(M=32, S=32, P=8, kernel=2)]
+                 dict(M=16, S=16, P=16, kernel=2), dict(M=32, S=32, P=8, kernel=2),
+                 dict(M=12, S=16, P=32, kernel=1), dict(M=24, S=16, P=16, kernel=1)]
 
 
 @pytest.mark.parametrize("shape", SHAPES_SHARED,
@@ -195,7 +196,8 @@ def test_shared_operator_shapes(shape):
 
 
 STREAM_SHAPES = [dict(M=16, S=1, P=16, kernel=2), dict(M=16, S=4, P=16, kernel=2),
-                 dict(M=8, S=2, P=32, kernel=2), dict(M=32, S=8, P=8, kernel=2)]
+                 dict(M=8, S=2, P=32, kernel=2), dict(M=32, S=8, P=8, kernel=2),
+                 dict(M=12, S=16, P=32, kernel=2), dict(M=24, S=8, P=16, kernel=2)]
 
 
 @pytest.mark.parametrize("dtype,tol", [(np.float64, parity.TOL_F64), (np.float32, parity.TOL_F32)])
@@ -225,7 +227,8 @@ def test_shared_fp32_padding():
 
 CSTREAM_SHAPES = [dict(M=16, S=16, P=16, kernel=2), dict(M=8, S=8, P=32, kernel=2),
                   dict(M=32, S=16, P=8, kernel=2), dict(M=16, S=1, P=16, kernel=2),
-                  dict(M=8, S=4, P=64, kernel=2)]
+                  dict(M=8, S=4, P=64, kernel=2), dict(M=12, S=8, P=32, kernel=2),
+                  dict(M=24, S=8, P=16, kernel=2)]
 
 
 @pytest.mark.parametrize("dtype,tol", [(np.float64, parity.TOL_F64), (np.float32, parity.TOL_F32)])
