@@ -19,6 +19,11 @@ Other workloads (measurement of the remaining configurations):
                (dependent chain + independent ragged branch)
   plain        64 contiguous systems of n = 256
 
+The oracle (``oracle/``) runs only in the cpu_baseline leg: it is timed there
+on a bounded sample of the workload, and the run's recorded GPU results are
+checked against it (the ``max_rel_err_vs_oracle`` fields; null with
+``--no-cpu-baseline``).
+
 Prints ONE JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
 """
 import argparse
@@ -129,23 +134,23 @@ def timed(step, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
-def sampled_error(p, x_host, systems, dtype="f64", ld_fallback=False):
+def grab_rows(p, x_dev, systems):
+    """Host copies (k, n) of the GPU's result rows of the given systems, for
+    the oracle leg to check (one gather on the device)."""
     import numpy as np
-    import oracle
-    from workloads import configs
-    worst = 0.0
-    for s in systems:
-        a, b, c, d = configs.system_inputs(p, int(s))
-        if dtype == "f32":
-            a, b, c, d = [v.astype(np.float32).astype(np.float64) for v in (a, b, c, d)]
-        ref = oracle.thomas(a, b, c, d)
-        got = x_host[p.layout.sys_rows(int(s))]
-        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
-        if ld_fallback and err > 1e-12:
-            ref = oracle.thomas(a, b, c, d, oracle.LONG_DOUBLE)
-            err = min(err, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
-        worst = max(worst, err)
-    return worst
+    import torch
+    lay = p.layout
+    systems = np.asarray(systems, dtype=np.int64)
+    base = (systems % lay.nsys0) * lay.sys_stride0 + (systems // lay.nsys0) * lay.sys_stride1
+    idx = base[:, None] + np.arange(lay.n, dtype=np.int64)[None, :] * lay.row_stride
+    return x_dev[torch.from_numpy(idx).to(x_dev.device)].double().cpu().numpy()
+
+
+def check(path, p, systems, rows, dtype="f64", ld=False):
+    """An error field of the JSON line that the oracle leg fills: the GPU rows
+    of `systems` against the oracle on the same systems."""
+    return {"path": path, "kind": "systems", "p": p, "systems": systems, "rows": rows,
+            "dtype": dtype, "ld": ld}
 
 
 def sample_systems(nsys, k=254, seed=7):
@@ -191,9 +196,9 @@ def bench_adi(args):
     n = len(ds)
     ms = timed(lambda i: tdma.solve_batched(lay, coeffs, ds[i % n], xs[i % n], stream=st),
                args.steps, args.warmup, st)
-    x_last = xs[(args.steps - 1) % n].double().cpu().numpy()
     samp = sample_systems(lay.nsys)
-    err = sampled_error(p, x_last, samp, args.dtype)
+    checks = [check(("max_rel_err_vs_oracle",), p, samp, grab_rows(p, xs[(args.steps - 1) % n], samp),
+                    args.dtype)]
     # the strided shared-operator default is the streaming form of k_shared
     kernel = "k_shared_stream"
     out = {
@@ -202,7 +207,7 @@ def bench_adi(args):
         "config": {"workload": f"adi_viscous_zsweep_{nx}x{ny}x{nz}", "systems": lay.nsys, "n": lay.n,
                    "coefficients": "shared tanh-grid operator", "entry_point": "tdma_solve_batched",
                    "buffer_sets": n},
-        "max_rel_err_vs_oracle": err,
+        "max_rel_err_vs_oracle": None,
         "roofline": roofline(bytes_step, ms, kernel, f"{kernel}_adi{nx}x{ny}x{nz}_{args.dtype}"),
     }
     if args.dtype == "f64" and not args.no_refine:
@@ -212,10 +217,11 @@ def bench_adi(args):
                     args.steps, args.warmup, st)
         rep = tdma.solve_refined(lay, coeffs, ds[0], xs[0], REFINE_ITERS, REFINE_TOL, report=True,
                                  stream=st, criterion=REFINE_CRITERION)
-        xr = xs[0].cpu().numpy()
+        checks.append(check(("fp32_refine", "max_rel_err_vs_oracle"), p, samp,
+                            grab_rows(p, xs[0], samp)))
         out["fp32_refine"] = {
             "value": round(unknowns / (msr * 1e-3) / 1e9, 3), "ms_per_step": round(msr, 6),
-            "max_rel_err_vs_oracle": sampled_error(p, xr, samp), "report": rep,
+            "max_rel_err_vs_oracle": None, "report": rep,
             "entry_point": f"tdma_solve_refined ({REFINE_ITERS} steps, tol {REFINE_TOL:g}, criterion "
                            f"{REFINE_CRITERION}, FP64 fallback)",
             "roofline": roofline(bytes_step, msr, "k_shared_refine",
@@ -231,7 +237,7 @@ def bench_adi(args):
         "GB_s": round(2 * esz * unknowns / (mc * 1e-3) / 1e9, 1),
         "solve_frac_of_copy": round(mc / ms, 4),
     }
-    return p, out
+    return p, out, checks
 
 
 def bench_partitioned(args):
@@ -248,15 +254,16 @@ def bench_partitioned(args):
     ms = timed(lambda i: tdma.solve_partitioned(lay, coeffs, d, x, partitions=8, batch=args.batch,
                                                 nstreams=4, stream=st), steps, min(args.warmup, 2), st)
     unknowns = lay.unknowns()
-    err = sampled_error(p, x.cpu().numpy(), sample_systems(lay.nsys, 62))
+    samp = sample_systems(lay.nsys, 62)
+    checks = [check(("max_rel_err_vs_oracle",), p, samp, grab_rows(p, x, samp))]
     return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
                "dtype": "f64", "steps": steps,
                "config": {"workload": f"partitioned_zlines_{nx}x{ny}x{nz}", "systems": lay.nsys,
                           "n": lay.n, "partitions": 8, "streams": 4, "batch": args.batch or "default",
                           "entry_point": "tdma_solve_partitioned"},
-               "max_rel_err_vs_oracle": err,
+               "max_rel_err_vs_oracle": None,
                "roofline": roofline(40 * unknowns, ms, "k_stage_a", f"partitioned{nx}x{ny}x{nz}_f64",
-                                   note="whole staged solve: 32 batches x (Stage A, B, C)")}
+                                   note="whole staged solve: 32 batches x (Stage A, B, C)")}, checks
 
 
 def bench_poisson(args):
@@ -288,28 +295,28 @@ def bench_poisson(args):
     low = [(kx % nx) + nx * (ky % ny) for kx in range(-3, 4) for ky in range(-3, 4) if (kx, ky) != (0, 0)]
     samp = sorted(set(sample_systems(lay.nsys, 30).tolist() + low) - {0})
     ms = timed(fp64, steps, 1, st)
-    e64 = sampled_error(p, x.cpu().numpy(), samp, ld_fallback=True)
+    checks = [check(("max_rel_err_vs_oracle",), p, samp, grab_rows(p, x, samp), ld=True)]
     msr = timed(refined, steps, 1, st)
     rep = tdma.solve_refined(lay, coeffs, d, x, REFINE_ITERS, REFINE_TOL, report=True, stream=st,
                            criterion=REFINE_CRITERION)
     tdma.solve_refined(pin.layout, pco, d, x, REFINE_ITERS, REFINE_TOL, stream=st,
                        criterion=REFINE_CRITERION)
-    er = sampled_error(p, x.cpu().numpy(), samp, ld_fallback=True)
+    checks.append(check(("fp32_refine", "max_rel_err_vs_oracle"), p, samp, grab_rows(p, x, samp),
+                        ld=True))
     return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
                "dtype": "f64", "steps": steps,
                "config": {"workload": f"fft_poisson_lines_{nx}x{ny}x{nz}", "systems": lay.nsys,
                           "n": lay.n, "entry_point": "tdma_solve_batched (+ pinned mode)"},
-               "max_rel_err_vs_oracle": e64,
+               "max_rel_err_vs_oracle": None,
                "roofline": roofline(16 * unknowns, ms, "k_fused", f"k_fused_poisson{nx}x{ny}x{nz}_f64"),
                "fp32_refine": {"value": round(unknowns / (msr * 1e-3) / 1e9, 3),
-                               "ms_per_step": round(msr, 6), "max_rel_err_vs_oracle": er,
-                               "report": rep, "faster_than_fp64": msr < ms}}
+                               "ms_per_step": round(msr, 6), "max_rel_err_vs_oracle": None,
+                               "report": rep, "faster_than_fp64": msr < ms}}, checks
 
 
 def bench_sweeps(args):
     import numpy as np
     import torch
-    import oracle
     import paper_2509_03933_amd as tdma
     from workloads import configs, device
     # default: half the 768x512x1536 grid along each axis (the full-size
@@ -334,20 +341,21 @@ def bench_sweeps(args):
     ms = timed(lambda i: g.launch(st), steps, min(args.warmup, 3), st)
     unknowns = 3 * px.layout.unknowns() + rg.layout.unknowns()
     bytes_step = 16 * 3 * px.layout.unknowns() + 40 * rg.layout.unknowns()
-    worst = 0.0
-    for p, din, xout in ((px, R, u1), (py, u1, u2), (pz, u2, u3)):
-        for s in sample_systems(p.layout.nsys, 16):
-            rows = torch.from_numpy(p.layout.sys_rows(int(s))).cuda()
-            ref = oracle.thomas(p.a, p.b, p.c, din[rows].cpu().numpy())
-            got = xout[rows].cpu().numpy()
-            worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+    # the oracle leg chains x -> y -> z on the host from the same seeded field
+    # (the device generator's copy, pinned bit for bit to the host one)
+    samps = [sample_systems(p.layout.nsys, 16) for p in (px, py, pz)]
+    checks = [{"path": ("max_rel_err_vs_oracle",), "kind": "chain", "problems": (px, py, pz),
+               "R": R.cpu().numpy(), "systems": samps,
+               "rows": [grab_rows(p, u, sm) for p, u, sm in zip((px, py, pz), (u1, u2, u3), samps)]},
+              {"path": ("ragged_max_rel_err_vs_oracle",), "kind": "ragged", "p": rg,
+               "systems": sample_systems(rg.layout.nsys, 30), "x": tx.cpu().numpy()}]
     g.destroy()
     return px, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
                 "dtype": "f64", "steps": steps,
                 "config": {"workload": f"adi_sweeps_{nx}x{ny}x{nz}_plus_10000_ragged",
                            "entry_point": "tdma_graph_launch"},
-                "max_rel_err_vs_oracle": worst,
-                "roofline": roofline(bytes_step, ms, "graph", f"graph_sweeps{nx}x{ny}x{nz}_f64")}
+                "max_rel_err_vs_oracle": None, "ragged_max_rel_err_vs_oracle": None,
+                "roofline": roofline(bytes_step, ms, "graph", f"graph_sweeps{nx}x{ny}x{nz}_f64")}, checks
 
 
 def bench_plain(args):
@@ -361,12 +369,51 @@ def bench_plain(args):
     ms = timed(lambda i: tdma.solve_batched(p.layout, coeffs, d, x, stream=st), args.steps,
                args.warmup, st)
     unknowns = p.layout.unknowns()
-    err = sampled_error(p, x.cpu().numpy(), range(p.layout.nsys))
+    checks = [check(("max_rel_err_vs_oracle",), p, list(range(p.layout.nsys)),
+                    grab_rows(p, x, list(range(p.layout.nsys))))]
     return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
                "dtype": "f64", "config": {"workload": "plain_64x256_contiguous",
                                           "entry_point": "tdma_solve_batched"},
-               "max_rel_err_vs_oracle": err,
-               "roofline": roofline(40 * unknowns, ms, "k_fused", "k_fused_plain64x256_f64")}
+               "max_rel_err_vs_oracle": None,
+               "roofline": roofline(40 * unknowns, ms, "k_fused", "k_fused_plain64x256_f64")}, checks
+
+
+def oracle_errors(checks):
+    """Largest per-system relative error of the recorded GPU results against
+    the oracle, per check (part of the oracle leg)."""
+    import numpy as np
+    import oracle
+    from workloads import configs
+
+    def rel(got, ref):
+        return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+    errs = {}
+    for c in checks:
+        worst = 0.0
+        if c["kind"] == "systems":
+            p = c["p"]
+            for s, got in zip(c["systems"], c["rows"]):
+                a, b, cc, d = configs.system_inputs(p, int(s))
+                if c["dtype"] == "f32":
+                    a, b, cc, d = [v.astype(np.float32).astype(np.float64) for v in (a, b, cc, d)]
+                e = rel(got, oracle.thomas(a, b, cc, d))
+                if c["ld"] and e > 1e-12:   # ill-conditioned: the long-double oracle decides
+                    e = min(e, rel(got, oracle.thomas(a, b, cc, d, oracle.LONG_DOUBLE)))
+                worst = max(worst, e)
+        elif c["kind"] == "ragged":
+            p = c["p"]
+            for s in c["systems"]:
+                a, b, cc, d = configs.system_inputs(p, int(s))
+                worst = max(worst, rel(c["x"][p.layout.sys_rows(int(s))], oracle.thomas(a, b, cc, d)))
+        elif c["kind"] == "chain":
+            ref = c["R"]
+            for p, systems, rows in zip(c["problems"], c["systems"], c["rows"]):
+                ref = oracle.solve_batch(p.layout, 1, p.a, p.b, p.c, ref)
+                for s, got in zip(systems, rows):
+                    worst = max(worst, rel(got, ref[p.layout.sys_rows(int(s))]))
+        errs[c["path"]] = worst
+    return errs
 
 
 def cpu_baseline(p, target_s, max_systems=None):
@@ -421,7 +468,7 @@ def main():
         return
     fn = {"adi": bench_adi, "partitioned": bench_partitioned, "poisson": bench_poisson,
           "sweeps": bench_sweeps, "plain": bench_plain}[args.workload]
-    p, res = fn(args)
+    p, res, checks = fn(args)
     out = {"metric": METRIC, "value": res.pop("value"), "unit": "G unknowns/s", "n_gpus": 1,
            "steps": res.pop("steps", args.steps), "warmup": args.warmup,
            "ms_per_step": res.pop("ms_per_step"), "higher_is_better": True, "scaling": "weak",
@@ -429,7 +476,14 @@ def main():
            "data": "synthetic (seeded counter-based generator, generated in HBM)"}
     out.update(res)
     if not args.no_cpu_baseline:
+        # the oracle leg: the oracle timed on a bounded sample of the workload,
+        # and the run's GPU results checked against it
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        for path, err in oracle_errors(checks).items():
+            node = out
+            for key in path[:-1]:
+                node = node[key]
+            node[path[-1]] = err
     print(json.dumps(out))
 
 

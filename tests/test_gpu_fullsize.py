@@ -45,6 +45,35 @@ def _check_sampled(p, x_dev, systems, tol, ld_ok=False):
     return worst
 
 
+def _sample_many(nsys, k=65536, seed=11, exclude=()):
+    """At least k distinct systems (first and last included), seeded."""
+    rs = np.random.default_rng(seed)
+    pick = np.unique(np.concatenate([[0, nsys - 1], rs.integers(0, nsys, 2 * k)]))
+    if len(exclude):
+        pick = np.setdiff1d(pick, np.asarray(exclude, dtype=np.int64))
+    return pick[:k] if pick.size > k else pick
+
+
+def _rows(layout, systems):
+    """(k, n) linear element indices of the given systems' rows."""
+    systems = np.asarray(systems, dtype=np.int64)
+    base = (systems % layout.nsys0) * layout.sys_stride0 + (systems // layout.nsys0) * layout.sys_stride1
+    return base[:, None] + np.arange(layout.n, dtype=np.int64)[None, :] * layout.row_stride
+
+
+def _packed(n, k):
+    return configs.Layout(n=n, nsys0=k, nsys1=1, row_stride=1, sys_stride0=n, sys_stride1=0)
+
+
+def _compare_rows(x_dev, idx, ref, tol, what):
+    """Per-system max|x - ref| / max|ref| over the (k, n) rows idx of x_dev."""
+    got = x_dev[torch.from_numpy(idx).cuda()].double().cpu().numpy()
+    ref = ref.reshape(idx.shape)
+    err = np.max(np.abs(got - ref), axis=1) / np.maximum(np.max(np.abs(ref), axis=1), 1e-300)
+    print(f"{what}: {idx.shape[0]} systems, max rel err {err.max():.3e}", flush=True)
+    assert err.max() <= tol, (what, float(err.max()), int(err.argmax()))
+
+
 def test_adi_256_cubed_fp32():
     import paper_2509_03933_amd as tdma
     from workloads import device
@@ -75,15 +104,39 @@ def test_partitioned_1024_cubed():
     tdma.solve_partitioned(p.layout, co, d, x, partitions=8, nstreams=4)
     tdma.check()
     assert torch.isfinite(x).all()
-    _check_sampled(p, x, _sample(p.layout.nsys), parity.TOL_F64)
+    # 65,536 systems against the oracle, inputs from the host generator
+    lay = p.layout
+    systems = _sample_many(lay.nsys)
+    idx = _rows(lay, systems)
+    row = np.broadcast_to(np.arange(lay.n, dtype=np.int64), idx.shape)
+    a, b, c, dd = configs.element_values(p, idx.ravel(), row.ravel(), lay.n)
+    ref = oracle.solve_batch(_packed(lay.n, systems.size), 0, a, b, c, dd)
+    _compare_rows(x, idx, ref, parity.TOL_F64, "partitioned 1024^3")
     del d, co, x
     torch.cuda.empty_cache()
 
 
-def _poisson_sample(p):
+def _poisson_low(p, k=16):
+    """Every mode with |kx|, |ky| <= k (the ill-conditioned end)."""
     nx, ny, _ = p.grid
-    low = [(kx % nx) + nx * (ky % ny) for kx in range(-4, 5) for ky in range(-4, 5)]
-    return np.unique(np.concatenate([_sample(p.layout.nsys, 32), low]))
+    return np.unique([(kx % nx) + nx * (ky % ny) for kx in range(-k, k + 1) for ky in range(-k, k + 1)])
+
+
+def _poisson_sample(p):
+    return np.unique(np.concatenate([_sample(p.layout.nsys, 32), _poisson_low(p)]))
+
+
+def _poisson_bulk_check(p, x, tol, what):
+    """65,536 modes outside |kx|, |ky| <= 16 (well conditioned) against the
+    oracle, vectorized; right-hand sides from the host generator."""
+    lay = p.layout
+    systems = _sample_many(lay.nsys, exclude=_poisson_low(p))
+    idx = _rows(lay, systems)
+    row = np.broadcast_to(np.arange(lay.n, dtype=np.int64), idx.shape)
+    _, _, _, dd = configs.element_values(p, idx.ravel(), row.ravel(), lay.n)
+    ref = oracle.solve_batch(_packed(lay.n, systems.size), 1, p.a, p.b, p.c, dd,
+                             shift=p.shift[systems])
+    _compare_rows(x, idx, ref, tol, what)
 
 
 def test_poisson_1024_cubed_fp64_and_refined():
@@ -105,6 +158,7 @@ def test_poisson_1024_cubed_fp64_and_refined():
     samp = _poisson_sample(p)
     _check_sampled(p, x, samp[samp != 0], parity.TOL_F64, ld_ok=True)
     _check_sampled(pin, x, [0], parity.TOL_F64, ld_ok=True)
+    _poisson_bulk_check(p, x, parity.TOL_F64, "poisson FP64")
     x.fill_(float("nan"))
     rep = tdma.solve_refined(p.layout, co, d, x)
     tdma.solve_refined(pin.layout, pin_co, d, x)
@@ -123,15 +177,17 @@ def test_poisson_1024_cubed_fp64_and_refined():
     print("refine report (2 steps, tol 1e-12, criterion 1)", rep)
     _check_sampled(p, x, samp[samp != 0], parity.TOL_REFINED, ld_ok=True)
     _check_sampled(pin, x, [0], parity.TOL_REFINED, ld_ok=True)
+    _poisson_bulk_check(p, x, parity.TOL_REFINED, "poisson refined (2 steps, criterion 1)")
     del d, co, x
     torch.cuda.empty_cache()
 
 
 def test_sweeps_full_size_one_by_one():
     """The 768x512x1536 x -> y -> z sweeps through tdma_solve_batched, one call
-    each (no graph); sampled lines of each sweep against the oracle applied
-    to the GPU's own input to that sweep.  Then the 10,000-system ragged batch,
-    every system against the oracle."""
+    each (no graph), against the oracle chained on the host from the same
+    seeded field (copied from the device generator, which is pinned bit for
+    bit to the host one): 65,536 lines of each sweep.  Then the
+    10,000-system ragged batch, every system against the oracle."""
     import paper_2509_03933_amd as tdma
     from workloads import device
     px, py, pz = configs.sweeps()
@@ -140,18 +196,16 @@ def test_sweeps_full_size_one_by_one():
     shared = lambda p: dict(mode=1, a=torch.from_numpy(p.a).cuda(), b=torch.from_numpy(p.b).cuda(),
                             c=torch.from_numpy(p.c).cuda())
     for p, din, xout in ((px, R, u1), (py, u1, u2), (pz, u2, u3)):
-        print("sweep", p.name, "n", p.layout.n, "systems", p.layout.nsys, flush=True)
         tdma.solve_batched(p.layout, shared(p), din, xout)
-        tdma.check()
+    tdma.check()
+    print("oracle chain on the host", flush=True)
+    ref = R.cpu().numpy()
+    for p, xout in ((px, u1), (py, u2), (pz, u3)):
+        ref = oracle.solve_batch(p.layout, 1, p.a, p.b, p.c, ref)
         assert torch.isfinite(xout).all()
-        worst = 0.0
-        for sys_id in _sample(p.layout.nsys, 24):
-            rows = torch.from_numpy(p.layout.sys_rows(int(sys_id))).cuda()
-            ref = oracle.thomas(p.a, p.b, p.c, din[rows].cpu().numpy())
-            got = xout[rows].cpu().numpy()
-            worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
-        print("  max rel err", worst, flush=True)
-        assert worst <= parity.TOL_F64, (p.name, worst)
+        systems = _sample_many(p.layout.nsys)
+        idx = _rows(p.layout, systems)
+        _compare_rows(xout, idx, ref[idx], parity.TOL_F64, f"{p.name} n={p.layout.n}")
     del R, u1, u2, u3
     torch.cuda.empty_cache()
     rg = configs.ragged()
