@@ -18,6 +18,8 @@ Other workloads (measurement of the remaining configurations):
                axis) + 10,000 ragged systems recorded into one hipGraph
                (dependent chain + independent ragged branch)
   plain        64 contiguous systems of n = 256
+  autotune     the autotuner on the partitioned configuration (model choice
+               of the batch size against brute force), then the tuned solve
 
 The oracle (``oracle/``) runs only in the cpu_baseline leg: it is timed there
 on a bounded sample of the workload, and the run's recorded GPU results are
@@ -90,7 +92,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="adi",
-                    choices=["adi", "partitioned", "poisson", "sweeps", "plain"])
+                    choices=["adi", "partitioned", "poisson", "sweeps", "plain", "autotune"])
     ap.add_argument("--grid", default=None, help="override the grid, e.g. 256,256,256")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--batch", type=int, default=0, help="partitioned: systems per batch")
@@ -264,6 +266,45 @@ def bench_partitioned(args):
                "max_rel_err_vs_oracle": None,
                "roofline": roofline(40 * unknowns, ms, "k_stage_a", f"partitioned{nx}x{ny}x{nz}_f64",
                                    note="whole staged solve: 32 batches x (Stage A, B, C)")}, checks
+
+
+def bench_autotune(args):
+    """The autotuner on the staged path's configuration: per-stage times of
+    each batch size 2^12..2^18, the pipeline model's choice, and the measured
+    pipeline time of every batch size (brute force); then the solve with the
+    tuned batch, timed."""
+    import torch
+    import paper_2509_03933_amd as tdma
+    from workloads import configs, device
+    nx, ny, nz = (int(v) for v in (args.grid or "1024,1024,1024").split(","))
+    p = configs.partitioned(nx, ny, nz)
+    d, coeffs = device.device_inputs(p)
+    x = torch.empty_like(d)
+    lay = p.layout
+    st = torch.cuda.current_stream()
+    rec = tdma.autotune(lay, coeffs, d, x, what=2, stream=st)
+    by_batch = {c["batch"]: c for c in rec["candidates"]}
+    chosen = by_batch[rec["model_choice"]]["measured_ms"]
+    steps = max(1, min(args.steps, 10))
+    ms = timed(lambda i: tdma.solve_partitioned(lay, coeffs, d, x, stream=st), steps,
+               min(args.warmup, 2), st)
+    unknowns = lay.unknowns()
+    samp = sample_systems(lay.nsys, 62)
+    checks = [check(("max_rel_err_vs_oracle",), p, samp, grab_rows(p, x, samp))]
+    return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
+               "dtype": "f64", "steps": steps,
+               "config": {"workload": f"partitioned_zlines_{nx}x{ny}x{nz}_autotuned", "systems": lay.nsys,
+                          "n": lay.n, "partitions": rec["P"],
+                          "entry_point": "tdma_autotune (what = 2), then tdma_solve_partitioned"},
+               "autotune": {"model_choice": rec["model_choice"], "model_choice_measured_ms": chosen,
+                            "brute_choice": rec["brute_choice"], "brute_ms": rec["brute_ms"],
+                            "model_over_brute": round(chosen / rec["brute_ms"], 4),
+                            "candidates": [{k: c[k] for k in ("batch", "t_a_ms", "t_b_ms", "t_c_ms",
+                                                              "model_ms", "measured_ms")}
+                                           for c in rec["candidates"]]},
+               "max_rel_err_vs_oracle": None,
+               "roofline": roofline(40 * unknowns, ms, "k_stage_a", f"partitioned{nx}x{ny}x{nz}_f64",
+                                    note="whole staged solve with the tuned batch")}, checks
 
 
 def bench_poisson(args):
@@ -467,7 +508,7 @@ def main():
         copy_calibration()
         return
     fn = {"adi": bench_adi, "partitioned": bench_partitioned, "poisson": bench_poisson,
-          "sweeps": bench_sweeps, "plain": bench_plain}[args.workload]
+          "sweeps": bench_sweeps, "plain": bench_plain, "autotune": bench_autotune}[args.workload]
     p, res, checks = fn(args)
     out = {"metric": METRIC, "value": res.pop("value"), "unit": "G unknowns/s", "n_gpus": 1,
            "steps": res.pop("steps", args.steps), "warmup": args.warmup,
