@@ -23,6 +23,13 @@
  *  - A zero or non-finite pivot met on the device sets a sticky per-device
  *    flag, reported as TDMA_ESINGULAR by tdma_check() (which clears it).
  *  - Element counts, strides and offsets are in ELEMENTS, not bytes.
+ *  - Threads: any host thread may call; each device's host-side state (plan
+ *    cache, workspaces, stream and event pools) is locked for a call's host
+ *    work.  The workspaces are per device, so tdma_solve_partitioned,
+ *    tdma_solve_refined and tdma_autotune calls whose GPU work would overlap
+ *    in time (different streams) must be ordered by the caller (same stream
+ *    or events); tdma_solve_batched calls need no such ordering.
+ *    tdma_shutdown must not overlap any other call.
  */
 #ifndef TDMA_H
 #define TDMA_H

@@ -83,8 +83,6 @@ int get_ctx(DeviceCtx **out) {
     return TDMA_OK;
 }
 
-std::mutex &ctx_mutex(DeviceCtx *) { return g_mutex; }
-
 // Device workspace of at least `bytes`, tagged by `slot` (kept across calls).
 int DeviceCtx::workspace(int slot, size_t bytes, void **out) {
     for (auto &w : workspaces) {
@@ -508,6 +506,7 @@ int tdma_solve_batched(const tdma_layout *layout, const tdma_coeffs *coeffs, int
     DeviceCtx *ctx = nullptr;
     rc = get_ctx(&ctx);
     if (rc != TDMA_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     return run_fused(ctx, layout, coeffs, dtype, d, x, (hipStream_t)stream, nullptr);
 }
 
@@ -539,6 +538,7 @@ int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeff
     DeviceCtx *ctx = nullptr;
     rc = get_ctx(&ctx);
     if (rc != TDMA_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     return run_fused(ctx, layout, coeffs, dtype, d, x, (hipStream_t)stream, &sh);
 }
 
@@ -565,6 +565,7 @@ int tdma_copy_streamed(const tdma_layout *layout, int dtype, const void *src, vo
     DeviceCtx *ctx = nullptr;
     rc = get_ctx(&ctx);
     if (rc != TDMA_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     const hipError_t e = launch_copy_streamed(dtype, map, sh, src, dst, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "streamed copy launch");
     return TDMA_OK;
@@ -577,6 +578,7 @@ int tdma_check(void *stream) {
     if (rc != TDMA_OK) return rc;
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    std::lock_guard<std::mutex> lk(ctx->mu);
     int flag[4] = {0, 0, 0, 0};
     e = hipMemcpy(flag, ctx->d_err, sizeof flag, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "read error flag");

@@ -32,6 +32,9 @@ struct Workspace {
 };
 
 struct DeviceCtx {
+    // guards the host-side state below (plan cache, workspaces, stream and
+    // event pools); every entry point holds it for its host work
+    std::mutex mu;
     int dev = 0;
     int num_cus = 256;
     int *d_err = nullptr;

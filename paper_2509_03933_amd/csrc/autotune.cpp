@@ -237,6 +237,7 @@ int tdma_autotune(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtyp
     DeviceCtx *ctx = nullptr;
     rc = get_ctx(&ctx);
     if (rc != TDMA_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     hipStream_t st = (hipStream_t)stream;
     const int64_t nsys = layout->nsys0 * layout->nsys1;
     if (nsys == 0) return TDMA_OK;

@@ -19,6 +19,8 @@
 #include <string>
 #include <vector>
 
+#include <mutex>
+
 #include "api_internal.h"
 
 struct tdma_graph {
@@ -69,6 +71,7 @@ extern "C" int tdma_graph_create(const tdma_work_item *items, int nitems, int dt
     DeviceCtx *ctx = nullptr;
     int rc = get_ctx(&ctx);
     if (rc != TDMA_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     tdma_graph *g = new tdma_graph();
     g->dev = ctx->dev;
     g->dtype = dtype;

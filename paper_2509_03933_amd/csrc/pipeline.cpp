@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <vector>
 
+#include <mutex>
+
 #include "api_internal.h"
 #include "partitioned.h"
 
@@ -166,6 +168,7 @@ extern "C" int tdma_solve_partitioned(const tdma_layout *layout, const tdma_coef
     DeviceCtx *ctx = nullptr;
     rc = get_ctx(&ctx);
     if (rc != TDMA_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     // unset fields: the autotuned values for this shape if cached, else the
     // measured defaults (batches of 32,768 systems, 4 streams, round robin)
     int64_t t_batch = 32768;

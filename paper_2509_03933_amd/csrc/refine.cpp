@@ -2,6 +2,8 @@
 #include <algorithm>
 #include <cstring>
 
+#include <mutex>
+
 #include "api_internal.h"
 #include "refine.h"
 
@@ -95,6 +97,7 @@ extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *
     DeviceCtx *ctx = nullptr;
     rc = get_ctx(&ctx);
     if (rc != TDMA_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     hipStream_t st = (hipStream_t)stream;
     const int64_t capacity = std::min<int64_t>(nsys, (int64_t)1 << 16);
     void *ws = nullptr;

@@ -334,3 +334,45 @@ def test_ragged_too_long_for_fp64():
     with pytest.raises(tdma.TdmaError) as ei:
         tdma.solve_batched(lay, dict(mode=0, a=t, b=t + 1, c=t), t, torch.empty_like(t))
     assert ei.value.status == tdma.EUNSUPPORTED
+
+
+def test_concurrent_host_threads():
+    """Four host threads, each on its own stream, solving a ragged batch and
+    a shared-operator sweep at the same time (the per-device host state is
+    locked per call; each thread has its own outputs): every result matches
+    the oracle."""
+    import threading
+    import paper_2509_03933_amd as tdma
+    r = configs.ragged(nsys=120, nmin=2, nmax=3000)
+    ra, rb, rc, rd = parity.host_problem(r)
+    rref = parity.oracle_solution(r, ra, rb, rc, rd)
+    rco = parity.device_coeffs(r, ra, rb, rc, torch.float64)
+    (trd,) = parity.to_device([rd], torch.float64)
+    z = configs.adi(40, 12, 200)
+    za, zb, zc, zd = parity.host_problem(z)
+    zref = parity.oracle_solution(z, za, zb, zc, zd)
+    zco = parity.device_coeffs(z, za, zb, zc, torch.float64)
+    (tzd,) = parity.to_device([zd], torch.float64)
+    outs = [(torch.full_like(trd, float("nan")), torch.full_like(tzd, float("nan"))) for _ in range(4)]
+    errors = []
+
+    def work(k):
+        try:
+            st = torch.cuda.Stream()
+            for _ in range(5):
+                tdma.solve_batched(r.layout, rco, trd, outs[k][0], stream=st)
+                tdma.solve_batched(z.layout, zco, tzd, outs[k][1], stream=st)
+            st.synchronize()
+        except Exception as e:       # reported below, in the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    tdma.check()
+    for xr, xz in outs:
+        assert parity.per_system_error(r.layout, xr.cpu().numpy(), rref).max() <= parity.TOL_F64
+        assert parity.per_system_error(z.layout, xz.cpu().numpy(), zref).max() <= parity.TOL_F64
