@@ -287,6 +287,8 @@ int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out) {
                         kv.first.second, kv.first.first, fused_max_threads(dtype, kv.first.first));
     RaggedPlan rp;
     rp.nsys = nsys;
+    rp.dtype = dtype;
+    rp.offsets.assign(L->offsets, L->offsets + nsys + 1);
     std::vector<int32_t> all;
     for (auto &kv : buckets) {
         const int M = kv.first.first, P = kv.first.second;
@@ -324,7 +326,8 @@ void free_ragged_plan(RaggedPlan *rp) {
     rp->d_list = nullptr;
 }
 
-// Plans of recently seen ragged layouts, keyed by a hash of the offsets.
+// Plans of recently seen ragged layouts, keyed by a hash of the offsets and
+// confirmed by comparing the offsets and dtype in full.
 int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, const RaggedPlan **out) {
     const int64_t nsys = L->nsys0;
     uint64_t h = 1469598103934665603ull;
@@ -334,18 +337,23 @@ int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, const RaggedPla
     }
     h ^= (uint64_t)dtype * 0x9E3779B97F4A7C15ull;
     auto it = ctx->ragged_cache.find(h);
-    if (it != ctx->ragged_cache.end() && it->second.nsys == nsys) {
+    if (it != ctx->ragged_cache.end() && it->second.nsys == nsys && it->second.dtype == dtype &&
+        std::equal(it->second.offsets.begin(), it->second.offsets.end(), L->offsets)) {
         *out = &it->second;
         return TDMA_OK;
     }
     RaggedPlan rp;
     int rc = build_ragged_plan(L, dtype, &rp);
     if (rc != TDMA_OK) return rc;
-    if (ctx->ragged_cache.size() >= 8) {
+    if (ctx->ragged_cache.size() >= 8 || it != ctx->ragged_cache.end()) {
+        // full (or a hash collision): drop the cached plans (the stream
+        // order keeps launches already issued from them valid: their device
+        // tables are freed only after a device synchronisation)
+        (void)hipDeviceSynchronize();
         for (auto &kv : ctx->ragged_cache) free_ragged_plan(&kv.second);
         ctx->ragged_cache.clear();
     }
-    auto res = ctx->ragged_cache.emplace(h, rp);
+    auto res = ctx->ragged_cache.emplace(h, std::move(rp));
     *out = &res.first->second;
     return TDMA_OK;
 }

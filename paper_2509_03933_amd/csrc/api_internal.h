@@ -20,6 +20,8 @@ struct RaggedBucket {
 
 struct RaggedPlan {
     int64_t nsys = 0;
+    int dtype = -1;
+    std::vector<int64_t> offsets;   // host copy: the plan cache compares it in full
     int64_t *d_offsets = nullptr;
     int32_t *d_list = nullptr;
     std::vector<RaggedBucket> buckets;
