@@ -49,6 +49,7 @@ void DeviceCtx::release() {
     int cur = -1;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();   // nothing issued may still use what is freed
     for (auto &kv : ragged_cache) free_ragged_plan(&kv.second);
     ragged_cache.clear();
     for (auto &w : workspaces) (void)hipFree(w.ptr);
@@ -167,6 +168,13 @@ int validate(const tdma_layout *L, const tdma_coeffs *C, int dtype, const void *
     if (L->row_stride == 0 && L->n > 1) return fail(TDMA_EINVAL, "row_stride is 0");
     if (L->row_stride < 0 || L->sys_stride0 < 0 || L->sys_stride1 < 0)
         return fail(TDMA_EINVAL, "negative stride");
+    // the last element any system reaches, in 128-bit arithmetic: device
+    // index math is 64-bit, so the layout must span fewer than 2^62 elements
+    const __int128 last = (__int128)(L->n - 1) * L->row_stride +
+                          (__int128)(L->nsys0 - 1) * L->sys_stride0 +
+                          (__int128)(L->nsys1 - 1) * L->sys_stride1;
+    if (last >= ((__int128)1 << 62))
+        return fail(TDMA_EINVAL, "the layout spans more than 2^62 elements");
     return TDMA_OK;
 }
 

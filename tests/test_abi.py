@@ -144,3 +144,13 @@ def test_refined_options_validation(tdma):
     assert refined(fallback=2) == tdma.EINVAL
     assert refined(criterion=2) == tdma.EINVAL
     assert refined(criterion=-1) == tdma.EINVAL
+
+
+def test_layout_extent_overflow(tdma):
+    """A layout whose last element lies beyond 2^62 is refused on the host."""
+    lib = tdma.lib()
+    L = tdma._Layout(8, 4, 2, 1 << 61, 1, 1 << 40, None)
+    C = tdma._Coeffs(0, 3, 4, 5, None)
+    assert lib.tdma_solve_batched(ctypes.byref(L), ctypes.byref(C), 0, ctypes.c_void_p(1),
+                                  ctypes.c_void_p(2), None) == tdma.EINVAL
+    assert "2^62" in lib.tdma_last_error().decode()
