@@ -422,8 +422,18 @@ int launch_ragged(const RaggedPlan &rp, const tdma_layout *L, const tdma_coeffs 
     return TDMA_OK;
 }
 
-// Tile shape of a uniform layout: the forced shape, else the autotune cache,
-// else the built-in rules (shared-operator kernel first where it applies).
+// Whether a tile shape can run a uniform layout with these coefficients.
+static bool shape_fits(int dtype, const tdma_layout *L, bool shared_op, const TileShape &sh) {
+    if ((int64_t)sh.P * sh.M < L->n) return false;
+    if (sh.kernel == 1 || sh.kernel == 2) return shared_op && shared_supported(dtype, sh);
+    if (sh.kernel != 0 || !fused_supported(dtype, sh)) return false;
+    return !(sh.contig && fused_lds_bytes(dtype, sh) > 160 * 1024);
+}
+
+// Tile shape of a uniform layout: the forced shape, else the autotune cache
+// (an entry that no longer fits, e.g. from an edited cache file, is
+// ignored), else the built-in rules (shared-operator kernel first where it
+// applies).
 int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dtype,
                  const TileShape *force, TileShape *out) {
     const int64_t nsys = L->nsys0 * L->nsys1;
@@ -432,23 +442,21 @@ int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int
     const bool shared_op = C->mode == TDMA_COEF_SHARED && C->b_shift == nullptr;
     if (force) {
         sh = *force;
-    } else if (!lookup_tuned(ctx->dev, L, C, dtype, &sh)) {
+        if ((int64_t)sh.P * sh.M < L->n)
+            return fail(TDMA_EINVAL, "tile shape M=%d P=%d S=%d does not cover n=%lld", sh.M, sh.P,
+                        1 << sh.S_log2, (long long)L->n);
+        if ((sh.kernel == 1 || sh.kernel == 2) && !shared_op)
+            return fail(TDMA_EINVAL, "the shared-operator kernel needs shared coefficients without "
+                        "a shift (M=%d P=%d S=%d)", sh.M, sh.P, 1 << sh.S_log2);
+        if (!shape_fits(dtype, L, shared_op, sh))
+            return fail(TDMA_EINVAL, "unsupported tile shape M=%d P=%d S=%d (kernel %d)", sh.M, sh.P,
+                        1 << sh.S_log2, sh.kernel);
+    } else if (!(lookup_tuned(ctx->dev, L, C, dtype, &sh) && sh.contig == contig &&
+                 shape_fits(dtype, L, shared_op, sh))) {
         if (!(shared_op && default_shared_shape(dtype, L->n, nsys, contig, &sh)) &&
             !default_shape(dtype, L->n, nsys, contig, &sh))
             return fail(TDMA_EUNSUPPORTED, "n = %lld is too long for the fused path (use "
                         "tdma_solve_partitioned)", (long long)L->n);
-    }
-    if ((int64_t)sh.P * sh.M < L->n)
-        return fail(TDMA_EINVAL, "tile shape M=%d P=%d S=%d does not cover n=%lld", sh.M, sh.P,
-                    1 << sh.S_log2, (long long)L->n);
-    if (sh.kernel == 1 || sh.kernel == 2) {
-        if (!shared_op || !shared_supported(dtype, sh))
-            return fail(TDMA_EINVAL, "the shared-operator kernel needs shared coefficients without "
-                        "a shift and a power-of-two P <= 64 (M=%d P=%d S=%d)", sh.M, sh.P,
-                        1 << sh.S_log2);
-    } else if (!fused_supported(dtype, sh)) {
-        return fail(TDMA_EINVAL, "unsupported tile shape M=%d P=%d S=%d", sh.M, sh.P,
-                    1 << sh.S_log2);
     }
     *out = sh;
     return TDMA_OK;

@@ -60,7 +60,8 @@ std::string key_of(int dev, const tdma_layout *L, const tdma_coeffs *C, int dtyp
     return buf;
 }
 
-// JSON cache: one line per entry, "key kernel M S_log2 P contig batch nstreams schedule"
+// Cache file (TDMA_CACHE): one line per entry, whitespace-separated:
+// "key has_shape kernel M S_log2 P contig batch nstreams schedule P"
 void load_cache_locked() {
     if (g_cache_loaded) return;
     g_cache_loaded = true;
