@@ -56,6 +56,7 @@ KERNEL_SOURCES = {
     "k_shared": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
     "k_shared_stream": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
     "k_shared_refine": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
+    "k_shared_refine_walk": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
     "k_fused": [CSRC + "fused.hip", CSRC + "fused_tile.hip.h", CSRC + "tile.hip.h"],
     "k_refine": [CSRC + "refine.hip", CSRC + "tile.hip.h"],
     "k_stage_a": [CSRC + "partitioned.hip", CSRC + "tile.hip.h"],
@@ -226,8 +227,8 @@ def bench_adi(args):
             "max_rel_err_vs_oracle": None, "report": rep,
             "entry_point": f"tdma_solve_refined ({REFINE_ITERS} steps, tol {REFINE_TOL:g}, criterion "
                            f"{REFINE_CRITERION}, FP64 fallback)",
-            "roofline": roofline(bytes_step, msr, "k_shared_refine",
-                                 f"k_shared_refine_adi{nx}x{ny}x{nz}_f64"),
+            "roofline": roofline(bytes_step, msr, "k_shared_refine_walk",
+                                 f"k_shared_refine_walk_adi{nx}x{ny}x{nz}_f64"),
             "faster_than_fp64": msr < ms,
         }
     # the same memory traffic with no arithmetic (same tile walk and grid):

@@ -16,6 +16,8 @@
 // for contiguous rows of consecutive systems, through an LDS transpose),
 // k_shared_refine (the precision form), k_copy_stream (the streaming
 // kernel's memory traffic alone, for measurement).
+#include <type_traits>
+
 #include "refine.h"
 #include "tile.hip.h"
 
@@ -985,6 +987,53 @@ k_shared_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, i
     }
 }
 
+// Walking form of k_shared_refine for uniform strided layouts: as many
+// workgroups as fit the device build the tables once and then take the tiles
+// t0, t0 + gridDim.x, ... one at a time.  No second register set: this
+// latency-bound kernel lives on occupancy (three wavefronts per SIMD, hence
+// the waves-per-EU bound), so the other resident workgroups hide each tile's
+// loads; measured 12% faster than one tile per workgroup on the 256^3 sweep.
+template <int M, typename OffT, int MODE>
+__global__ void __launch_bounds__((M >= 16 ? 512 : 1024)) __attribute__((amdgpu_waves_per_eu(3)))
+k_shared_refine_walk(SysMap map, Coef coef, const double *d, double *x, int S_log2, int P_log2,
+                     int32_t ntiles, int iters, double tol, RefineState *state) {
+    extern __shared__ double lds[];
+    char *base = reinterpret_cast<char *>(lds);
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2, P = 1 << P_log2;
+    const int s = tid & (S - 1);
+    const int p = tid >> S_log2;
+    const int r0 = p * M;
+    const int64_t rs = map.row_stride;
+    const SharedLds L = shared_layout(sizeof(float), M, P, S, false);
+    const int32_t step = (int32_t)gridDim.x << S_log2;
+    int32_t t = (int32_t)((S * 8 < 128) ? dev::xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
+    LaneWalk w;
+    w.init(map, (t << S_log2) + s, step);
+    dev::RowRegs<shared_cr<M>()> cr;
+    dev::rows_prefetch<double, shared_cr<M>()>(coef, map.n, cr);
+    __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the right-hand sides
+    double dv[M], xv[M];
+    LaneSys la = w.sys(map);
+    load_rows<double, M, OffT>(d, la, rs, r0, dv);
+    bool bad = false;
+    shared_tables<float, double, M>(coef, map.n, L, base, tid, s, p, P, cr, bad);
+    double rel = 0.0;   // largest convergence ratio of the block's tiles (thread 0)
+    for (;;) {
+        mask_rows<double, M>(rows_in(la, r0, M), dv);
+        rel = fmax(rel, refine_rows<M, MODE>(L, base, S, P, P_log2, s, p, iters, tol, bad, la.valid,
+                                             la.id, state, dv, xv));
+        store_rows<double, M, OffT>(x, la, rs, r0, xv);
+        t += gridDim.x;
+        if (t >= ntiles) break;
+        w.advance(map, step);
+        la = w.sys(map);
+        load_rows<double, M, OffT>(d, la, rs, r0, dv);
+        __syncthreads();   // the exchange buffers are rewritten by the next tile
+    }
+    if (tid == 0) fold_max_rel(state, rel);
+}
+
 // Resident blocks of a kernel on the current device.
 template <typename K>
 int64_t resident_blocks(K kernel, int threads, size_t lds) {
@@ -1173,6 +1222,26 @@ hipError_t launch_shared_refine(const SysMap &map, const Coef &coef, const TileS
     if (blocks == 0) return hipSuccess;
     const size_t lds = shared_refine_lds_bytes(sh);
     const int P_log2 = ilog2i(sh.P);
+    const bool walk_ok = !sh.contig && !map.offsets && !map.sys_list && !map.count &&
+                         2 * (blocks + 1) * S < ((int64_t)1 << 31);
+    if (walk_ok) {
+        const bool o32 = offsets_fit_32(map, sizeof(double));
+#define TDMA_SW(MM, OT, MD)                                                                       \
+        if (sh.M == MM && o32 == std::is_same<OT, uint32_t>::value && (sh.P <= 16) == (MD == PCR_DPP)) { \
+            const int64_t resident = resident_blocks(k_shared_refine_walk<MM, OT, MD>, sh.threads(), lds); \
+            if (resident < 1) return hipErrorInvalidConfiguration;                                 \
+            const int64_t grid = blocks < resident ? blocks : resident;                            \
+            hipLaunchKernelGGL((k_shared_refine_walk<MM, OT, MD>), dim3((unsigned)grid),             \
+                               dim3(sh.threads()), lds, st, map, coef, d, x, sh.S_log2, P_log2,    \
+                               (int32_t)blocks, iters, tol, state);                                \
+            return hipGetLastError();                                                              \
+        }
+        TDMA_SW(8, uint32_t, PCR_DPP) TDMA_SW(8, uint32_t, PCR_SHFL)
+        TDMA_SW(8, int64_t, PCR_DPP) TDMA_SW(8, int64_t, PCR_SHFL)
+        TDMA_SW(16, uint32_t, PCR_DPP) TDMA_SW(16, uint32_t, PCR_SHFL)
+        TDMA_SW(16, int64_t, PCR_DPP) TDMA_SW(16, int64_t, PCR_SHFL)
+#undef TDMA_SW
+    }
 #define TDMA_SR(MM, CT)                                                                          \
     if (sh.M == MM && sh.contig == CT) {                                                          \
         hipLaunchKernelGGL((k_shared_refine<MM, CT>), dim3((unsigned)blocks), dim3(sh.threads()), \
