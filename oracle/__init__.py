@@ -59,6 +59,12 @@ def _load():
             lib.oracle_solve_batch.restype = ctypes.c_int64
             lib.oracle_matvec.argtypes = [i64, dp, dp, dp, dp, dp]
             lib.oracle_matvec.restype = None
+            lib.oracle_thomas_z.argtypes = [i64, dp, dp, dp, dp, dp, ctypes.c_int]
+            lib.oracle_thomas_z.restype = ctypes.c_int
+            lib.oracle_solve_batch_z.argtypes = [
+                i64, i64, i64, i64, i64, i64, dp, dp, dp, dp, dp, dp, ctypes.c_int, i64, i64,
+                ctypes.POINTER(ctypes.c_int32)]
+            lib.oracle_solve_batch_z.restype = ctypes.c_int64
             _lib = lib
     return _lib
 
@@ -117,6 +123,51 @@ def solve_batch(layout, mode, a, b, c, d, shift=None, precision=F64, systems=Non
         raise OracleError(f"oracle_solve_batch failed: {failed}")
     if status:
         return x, st
+    if failed:
+        raise OracleError(f"{failed} systems hit a zero or non-finite pivot")
+    return x
+
+
+def _c128(x):
+    return np.ascontiguousarray(x, dtype=np.complex128)
+
+
+def _zptr(x):
+    return x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def thomas_complex(a, b, c, d, precision=F64):
+    """Solve one complex system (1-D arrays of equal length n, any of them
+    complex) by the Thomas recurrences in complex arithmetic."""
+    a, b, c, d = _c128(a), _c128(b), _c128(c), _c128(d)
+    n = d.size
+    if not (a.size == b.size == c.size == n):
+        raise ValueError("a, b, c, d must have equal length")
+    x = np.empty(n, dtype=np.complex128)
+    rc = _load().oracle_thomas_z(n, _zptr(a), _zptr(b), _zptr(c), _zptr(d), _zptr(x), precision)
+    if rc != OK:
+        raise OracleError(f"oracle_thomas_z failed: {rc}")
+    return x
+
+
+def solve_batch_complex(layout, a, b, c, d, shift=None, precision=F64, systems=None, x=None):
+    """Complex right-hand sides over shared real tables a, b, c (+ a real
+    per-system shift): every system of ``layout``, whose strides count complex
+    elements of the complex128 array ``d``.  Returns x (complex128, d's shape)."""
+    d = _c128(d)
+    a, b, c = _f64(a), _f64(b), _f64(c)
+    shift = None if shift is None else _f64(shift)
+    if x is None:
+        x = np.zeros_like(d)
+    nsys = layout.nsys0 * layout.nsys1
+    beg, end = (0, nsys) if systems is None else systems
+    st = np.zeros(nsys, dtype=np.int32)
+    failed = _load().oracle_solve_batch_z(
+        layout.n, layout.nsys0, layout.nsys1, layout.row_stride, layout.sys_stride0,
+        layout.sys_stride1, _ptr(a), _ptr(b), _ptr(c), _ptr(shift), _zptr(d), _zptr(x), precision,
+        beg, end, st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if failed < 0:
+        raise OracleError(f"oracle_solve_batch_z failed: {failed}")
     if failed:
         raise OracleError(f"{failed} systems hit a zero or non-finite pivot")
     return x

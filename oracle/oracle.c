@@ -21,6 +21,7 @@
  * *_ld variant), round to nearest, no fused multiply-add (built with
  * -ffp-contract=off), no fast-math.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -168,6 +169,130 @@ int64_t oracle_solve_batch(int64_t n, int64_t nsys0, int64_t nsys1, int64_t row_
     }
     free(buf);
     free(rows);
+    return failed;
+}
+
+/*
+ * Complex systems (the paper's Poisson data are complex, Sec. 8.1): the same
+ * Thomas recurrences with every quantity complex, in C99 complex arithmetic
+ * (double complex, or long double complex for the extended variant).  Arrays
+ * hold n interleaved (real, imaginary) pairs, the layout C gives a complex
+ * array.  A zero or non-finite pivot fails the system.
+ */
+static int zbad(double complex m)
+{
+    return (creal(m) == 0.0 && cimag(m) == 0.0) || !isfinite(creal(m)) || !isfinite(cimag(m));
+}
+
+static int thomas_z(int64_t n, const double complex *a, const double complex *b,
+                    const double complex *c, const double complex *d, double complex *x,
+                    double complex *cp, double complex *dp)
+{
+    double complex m = b[0];
+    if (zbad(m)) return ORACLE_ESINGULAR;
+    cp[0] = (n > 1) ? c[0] / m : 0.0;
+    dp[0] = d[0] / m;
+    for (int64_t i = 1; i < n; ++i) {
+        m = b[i] - a[i] * cp[i - 1];
+        if (zbad(m)) return ORACLE_ESINGULAR;
+        cp[i] = (i < n - 1) ? c[i] / m : 0.0;
+        dp[i] = (d[i] - a[i] * dp[i - 1]) / m;
+    }
+    x[n - 1] = dp[n - 1];
+    for (int64_t i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
+    return ORACLE_OK;
+}
+
+static int thomas_zld(int64_t n, const double complex *a, const double complex *b,
+                      const double complex *c, const double complex *d, double complex *x,
+                      long double complex *cp, long double complex *dp)
+{
+    long double complex m = b[0];
+    if (zbad((double complex)m)) return ORACLE_ESINGULAR;
+    cp[0] = (n > 1) ? (long double complex)c[0] / m : 0.0L;
+    dp[0] = (long double complex)d[0] / m;
+    for (int64_t i = 1; i < n; ++i) {
+        m = (long double complex)b[i] - (long double complex)a[i] * cp[i - 1];
+        if (zbad((double complex)m)) return ORACLE_ESINGULAR;
+        cp[i] = (i < n - 1) ? (long double complex)c[i] / m : 0.0L;
+        dp[i] = ((long double complex)d[i] - (long double complex)a[i] * dp[i - 1]) / m;
+    }
+    long double complex xn = dp[n - 1];
+    x[n - 1] = (double complex)xn;
+    for (int64_t i = n - 2; i >= 0; --i) {
+        xn = dp[i] - cp[i] * xn;
+        x[i] = (double complex)xn;
+    }
+    return ORACLE_OK;
+}
+
+/* One complex system; a, b, c, d, x each hold n (re, im) pairs.
+ * precision: 0 = FP64, 1 = long double. */
+int oracle_thomas_z(int64_t n, const double *a, const double *b, const double *c,
+                    const double *d, double *x, int precision)
+{
+    if (n < 1 || !a || !b || !c || !d || !x) return ORACLE_EINVAL;
+    int rc;
+    if (precision == 0) {
+        double complex *w = (double complex *)malloc(2 * (size_t)n * sizeof(double complex));
+        if (!w) return ORACLE_ENOMEM;
+        rc = thomas_z(n, (const double complex *)a, (const double complex *)b,
+                      (const double complex *)c, (const double complex *)d, (double complex *)x,
+                      w, w + n);
+        free(w);
+    } else {
+        long double complex *w =
+            (long double complex *)malloc(2 * (size_t)n * sizeof(long double complex));
+        if (!w) return ORACLE_ENOMEM;
+        rc = thomas_zld(n, (const double complex *)a, (const double complex *)b,
+                        (const double complex *)c, (const double complex *)d, (double complex *)x,
+                        w, w + n);
+        free(w);
+    }
+    return rc;
+}
+
+/*
+ * A batch of complex systems over shared REAL coefficient tables a, b, c
+ * (length n) with an optional real per-system diagonal shift -- the Poisson
+ * line solves of Sec. 5.2 after the Fourier transform in x and y, whose
+ * right-hand sides are complex.  Layout as in oracle_solve_batch, counted in
+ * COMPLEX elements: d and x are interleaved (re, im) arrays.  Each system is
+ * gathered, its coefficients widened to complex, solved by oracle_thomas_z and
+ * scattered back.  Returns the number of failed systems (status[s] per
+ * system, may be NULL) or a negative error.
+ */
+int64_t oracle_solve_batch_z(int64_t n, int64_t nsys0, int64_t nsys1, int64_t row_stride,
+                             int64_t sys_stride0, int64_t sys_stride1, const double *a,
+                             const double *b, const double *c, const double *shift,
+                             const double *d, double *x, int precision, int64_t sys_begin,
+                             int64_t sys_end, int32_t *status)
+{
+    if (!a || !b || !c || !d || !x || n < 1) return ORACLE_EINVAL;
+    int64_t nsys = nsys0 * nsys1;
+    if (sys_begin < 0 || sys_end > nsys || sys_begin > sys_end) return ORACLE_EINVAL;
+    double complex *buf = (double complex *)malloc(5 * (size_t)n * sizeof(double complex));
+    if (!buf) return ORACLE_ENOMEM;
+    double complex *sa = buf, *sb = buf + n, *sc = buf + 2 * n, *sd = buf + 3 * n, *sx = buf + 4 * n;
+    const double complex *dz = (const double complex *)d;
+    double complex *xz = (double complex *)x;
+    int64_t failed = 0;
+    for (int64_t s = sys_begin; s < sys_end; ++s) {
+        int64_t s0 = s % nsys0, s1 = s / nsys0;
+        int64_t base = s0 * sys_stride0 + s1 * sys_stride1;
+        for (int64_t i = 0; i < n; ++i) {
+            sa[i] = a[i];
+            sb[i] = shift ? b[i] + shift[s] : b[i];
+            sc[i] = c[i];
+            sd[i] = dz[base + i * row_stride];
+        }
+        int rc = oracle_thomas_z(n, (const double *)sa, (const double *)sb, (const double *)sc,
+                                 (const double *)sd, (double *)sx, precision);
+        if (status) status[s] = rc;
+        if (rc != ORACLE_OK) { ++failed; continue; }
+        for (int64_t i = 0; i < n; ++i) xz[base + i * row_stride] = sx[i];
+    }
+    free(buf);
     return failed;
 }
 

@@ -12,6 +12,8 @@ Five workload families (seed 1000 + k for family k):
                     separate one-system problem.
 5. ``sweeps``       x, y and z ADI sweeps of one grid plus a ragged batch of
                     independent systems with log-uniform lengths.
+6. ``poisson_complex`` the lines of (4) with complex right-hand sides stored as
+                    interleaved (re, im) pairs: two right-hand sides per system.
 
 Every random value is ``workloads.rng.uniform(seed, stream, index, lo, hi)`` of
 the element's linear array index (or system index), so the oracle can rebuild
@@ -95,7 +97,14 @@ class Problem:
     grid: tuple = ()                 # (nx, ny, nz) of the underlying 3-D array, if any
     smooth: dict = field(default_factory=dict)   # 1-D factor tables of the smooth RHS
     margin: Optional[np.ndarray] = None          # ragged: per-system dominance margin
-    pin_row0: Optional[int] = None   # poisson: system whose d_0 is forced to 0
+    pin_row0: Optional[int] = None   # poisson: first element of d forced to 0
+    pin_count: int = 1               # elements pin_row0 .. pin_row0+pin_count-1 are zero
+    nrhs: int = 1                    # right-hand sides per system (shared operator)
+    rhs_stride: int = 0              # elements between a system's right-hand sides
+
+    def extent(self):
+        """Elements an array of d spans, all right-hand sides included."""
+        return self.layout.extent() + (self.nrhs - 1) * self.rhs_stride
 
 
 # ----------------------------------------------------------------------------
@@ -179,6 +188,47 @@ def poisson_pinned(bulk):
                    a=a, b=b, c=c, grid=bulk.grid, pin_row0=0)
 
 
+def poisson_complex(nx=1024, ny=1024, nz=1024, stretch=2.0):
+    """The Poisson line solves with complex right-hand sides (the Fourier
+    coefficients of a real field are complex, Sec. 8.1): the operator and the
+    per-mode shift of ``poisson`` over a complex nx*ny*nz array stored as
+    interleaved (re, im) FP64 pairs.  Counted in real elements, the real parts
+    of mode (i, j) form a z-system with row stride 2*nx*ny and its imaginary
+    parts the same system one element on: two right-hand sides per system,
+    rhs_stride 1.  Both parts of d are U(-1, 1) of the real element index;
+    mode (0, 0) is pinned as in ``poisson`` (both parts of its d_0 zero) and
+    solved separately (``poisson_complex_pinned``)."""
+    base = poisson(nx, ny, nz, stretch)
+    lay = Layout(n=nz, nsys0=nx, nsys1=ny, row_stride=2 * nx * ny, sys_stride0=2,
+                 sys_stride1=2 * nx)
+    return Problem("poisson_complex", lay, MODE_SHARED, SEED_BASE + 6, "uniform_d",
+                   a=base.a, b=base.b, c=base.c, shift=base.shift, grid=(nx, ny, nz),
+                   pin_row0=0, pin_count=2, nrhs=2, rhs_stride=1)
+
+
+def poisson_complex_pinned(bulk):
+    """Mode (0, 0) of ``poisson_complex``: lambda = 0 and row 0 replaced by
+    x_0 = 0, both right-hand sides (the real and imaginary parts)."""
+    nx, ny, nz = bulk.grid
+    a = bulk.a.copy(); b = bulk.b.copy(); c = bulk.c.copy()
+    a[0] = 0.0; c[0] = 0.0; b[0] = 1.0
+    lay = Layout(n=nz, nsys0=1, nsys1=1, row_stride=2 * nx * ny, sys_stride0=2,
+                 sys_stride1=2 * nx)
+    return Problem("poisson_complex_pinned", lay, MODE_SHARED, bulk.seed, "uniform_d",
+                   a=a, b=b, c=c, grid=bulk.grid, pin_row0=0, pin_count=2, nrhs=2,
+                   rhs_stride=1)
+
+
+def complex_layout(p):
+    """The layout of a two-right-hand-side interleaved problem counted in
+    complex elements (the oracle's complex view of the same array)."""
+    lay = p.layout
+    assert p.nrhs == 2 and p.rhs_stride == 1
+    assert lay.row_stride % 2 == 0 and lay.sys_stride0 % 2 == 0 and lay.sys_stride1 % 2 == 0
+    return Layout(n=lay.n, nsys0=lay.nsys0, nsys1=lay.nsys1, row_stride=lay.row_stride // 2,
+                  sys_stride0=lay.sys_stride0 // 2, sys_stride1=lay.sys_stride1 // 2)
+
+
 def sweeps(nx=768, ny=512, nz=1536, stretch=2.0, r_mean=0.5):
     """The three ADI sweeps (x, y uniform r = r_mean; z on the tanh grid), applied
     in sequence to one field: (1-A_x) u1 = R, (1-A_y) u2 = u1, (1-A_z) u3 = u2."""
@@ -243,7 +293,7 @@ def element_values(p, idx, row, nrow, sys_index=None):
     if p.law == "uniform_d":
         d = rng.uniform(p.seed, rng.STREAM_D, idx, -1.0, 1.0)
         if p.pin_row0 is not None:
-            d = np.where(idx == p.pin_row0, 0.0, d)
+            d = np.where((idx >= p.pin_row0) & (idx < p.pin_row0 + p.pin_count), 0.0, d)
         return None, None, None, d
     raise ValueError(f"law {p.law!r} has no closed-form element values")
 
@@ -265,11 +315,21 @@ def system_inputs(p, s):
     return p.a.copy(), b, p.c.copy(), d
 
 
+def system_rhs(p, s):
+    """The p.nrhs right-hand sides of system s (list of contiguous FP64 arrays)."""
+    rows = p.layout.sys_rows(s)
+    out = []
+    for r in range(p.nrhs):
+        _, _, _, d = element_values(p, rows + r * p.rhs_stride, None, rows.size)
+        out.append(d)
+    return out
+
+
 def full_arrays(p):
     """Whole host arrays (a, b, c, d) in the problem's layout.  For MODE_SHARED
     a/b/c are the tables.  Only for sizes that fit comfortably in host memory."""
     lay = p.layout
-    size = lay.extent()
+    size = p.extent()
     idx = np.arange(size, dtype=np.int64)
     if lay.ragged:
         lens = np.diff(lay.offsets)

@@ -64,7 +64,7 @@ def device_inputs(p, dtype=None):
     the device generator; other problems are built on the host and copied."""
     import torch
     lay = p.layout
-    total = lay.extent()
+    total = p.extent()
     L = _load()
     st = _stream()
     dev = "cuda"
@@ -89,6 +89,8 @@ def device_inputs(p, dtype=None):
         else:
             pin = -1 if p.pin_row0 is None else int(p.pin_row0)
             rc = L.wl_uniform_d(p.seed, total, pin, _ptr(d), st)
+            if pin >= 0 and p.pin_count > 1:
+                d[pin + 1:pin + p.pin_count] = 0.0
         if rc:
             raise RuntimeError(f"device generator failed: {rc}")
         coeffs = dict(mode=p.mode, a=torch.from_numpy(p.a).to(dev), b=torch.from_numpy(p.b).to(dev),
