@@ -133,6 +133,31 @@ int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeff
                              const void *d, void *x, const tdma_tile *tile, void *stream);
 
 /*
+ * tdma_solve_multi: several right-hand sides per system over one operator.
+ * System k of `layout` has nrhs right-hand sides; right-hand side r has its
+ * row i at element (start of system k) + i*row_stride + r*rhs_stride of d,
+ * and its solution at the same element of x.  All of a system's right-hand
+ * sides share its coefficients, which must be TDMA_COEF_SHARED tables
+ * (b_shift optional, one value per system).  The paper's Poisson lines are
+ * the case in mind (Sec. 5.2, 8.1): a real operator with complex data, i.e.
+ * nrhs = 2 and rhs_stride = 1 over an array of interleaved (re, im) pairs,
+ * every stride of the layout counted in real elements (twice the complex
+ * index).  One fused launch per two right-hand sides: each lane runs the
+ * operator's recurrences (pivots, a^, c^) of its rows once and the d^
+ * recurrence per right-hand side; the interface system (FP64) is eliminated
+ * once for all of them.  Same results as tdma_solve_batched on each
+ * right-hand side, up to rounding order.
+ * Limits: uniform layouts; n <= 1024 rows in FP64, 2048 in FP32
+ * (TDMA_EUNSUPPORTED beyond, and for per-row coefficients).  Errors: EINVAL
+ * for nrhs < 1, rhs_stride < 0, rhs_stride 0 with nrhs > 1, a ragged layout,
+ * or a span of 2^62 elements or more.  x may alias d.  When nrhs >= 2,
+ * rhs_stride is 1, every stride is even and d and x are aligned to a pair,
+ * each row's two right-hand sides move as one vector access.
+ */
+int tdma_solve_multi(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype, int nrhs,
+                     int64_t rhs_stride, const void *d, void *x, void *stream);
+
+/*
  * tdma_copy_streamed (measurement): dst = src on every system row, moved
  * with the tile walk, lane-to-row mapping and register double-buffering of
  * the streaming shared-operator solve that tdma_solve_batched picks for this

@@ -99,6 +99,8 @@ def lib():
             L.tdma_graph_destroy.restype = None
             L.tdma_autotune.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, vp, vp, i, vp]
             L.tdma_copy_streamed.argtypes = [ctypes.POINTER(_Layout), i, vp, vp, vp]
+            L.tdma_solve_multi.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, i,
+                                           ctypes.c_int64, vp, vp, vp]
             L.tdma_check.argtypes = [vp]
             L.tdma_autotune_last_json.restype = ctypes.c_char_p
             L.tdma_pipeline_model_ms.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
@@ -109,6 +111,7 @@ def lib():
             L.tdma_last_error.restype = ctypes.c_char_p
             L.tdma_shutdown.restype = None
             for f in ("tdma_solve_batched", "tdma_solve_batched_tiled", "tdma_solve_partitioned", "tdma_solve_refined",
+                      "tdma_solve_multi", "tdma_copy_streamed",
                       "tdma_graph_create", "tdma_graph_launch", "tdma_autotune", "tdma_check"):
                 getattr(L, f).restype = ctypes.c_int
             _lib = L
@@ -116,7 +119,7 @@ def lib():
 
 
 EXPORTED_SYMBOLS = ("tdma_solve_batched", "tdma_solve_batched_tiled", "tdma_solve_partitioned", "tdma_solve_refined",
-                    "tdma_copy_streamed",
+                    "tdma_copy_streamed", "tdma_solve_multi",
                     "tdma_graph_create", "tdma_graph_launch", "tdma_graph_destroy",
                     "tdma_autotune", "tdma_autotune_last_json", "tdma_pipeline_model_ms",
                     "tdma_check", "tdma_status_string", "tdma_last_error", "tdma_shutdown")
@@ -252,6 +255,52 @@ def solve_batched_tiled(layout, coeffs, d, x, M, S, P, kernel=0, stream=None):
     _raise(lib().tdma_solve_batched_tiled(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),
                                           ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                           ctypes.byref(t), _stream_handle(stream)))
+
+
+def solve_multi(layout, coeffs, d, x, nrhs, rhs_stride, stream=None):
+    """nrhs right-hand sides per system, rhs_stride elements apart, over one
+    shared operator per system (tdma_solve_multi)."""
+    keep = []
+    nrhs, rhs_stride = int(nrhs), int(rhs_stride)
+    need = _extent(layout)
+    if need and nrhs > 1:
+        need += (nrhs - 1) * rhs_stride
+    _check_tensor("d", d, need)
+    _check_tensor("x", x, need, d.dtype)
+    L = _make_layout(layout, keep)
+    C = _make_coeffs(layout, coeffs, d, need)
+    _raise(lib().tdma_solve_multi(ctypes.byref(L), ctypes.byref(C), _dtype_code(d), nrhs,
+                                  rhs_stride, ctypes.c_void_p(d.data_ptr()),
+                                  ctypes.c_void_p(x.data_ptr()), _stream_handle(stream)))
+
+
+def solve_complex(layout, coeffs, d, x, stream=None):
+    """Complex right-hand sides over a real shared operator: d and x are
+    complex128 (complex64) tensors and ``layout`` counts complex elements; the
+    coefficients are float64 (float32) tables.  The interleaved real and
+    imaginary parts are solved as two right-hand sides (tdma_solve_multi)."""
+    import torch
+    if not (d.is_complex() and x.is_complex() and d.dtype == x.dtype):
+        raise TypeError("d and x must be complex tensors of one dtype")
+    dr = torch.view_as_real(d.reshape(-1) if d.is_contiguous() else d).reshape(-1)
+    xr = torch.view_as_real(x.reshape(-1) if x.is_contiguous() else x).reshape(-1)
+    if dr.data_ptr() != d.data_ptr() or xr.data_ptr() != x.data_ptr():
+        raise ValueError("d and x must be contiguous")
+
+    class _Real:
+        pass
+
+    lr = _Real()
+    lr.n = int(layout.n)
+    lr.nsys0 = int(layout.nsys0)
+    lr.nsys1 = int(getattr(layout, "nsys1", 1))
+    lr.row_stride = 2 * int(getattr(layout, "row_stride", 1))
+    lr.sys_stride0 = 2 * int(getattr(layout, "sys_stride0", 0))
+    lr.sys_stride1 = 2 * int(getattr(layout, "sys_stride1", 0))
+    lr.offsets = None
+    if getattr(layout, "offsets", None) is not None:
+        raise ValueError("complex right-hand sides need a uniform layout")
+    solve_multi(lr, coeffs, dr, xr, 2, 1, stream)
 
 
 def copy_streamed(layout, src, dst, stream=None):

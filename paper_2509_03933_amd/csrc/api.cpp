@@ -595,6 +595,46 @@ int tdma_copy_streamed(const tdma_layout *layout, int dtype, const void *src, vo
     return TDMA_OK;
 }
 
+int tdma_solve_multi(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype, int nrhs,
+                     int64_t rhs_stride, const void *d, void *x, void *stream) {
+    clear_error();
+    int rc = validate(layout, coeffs, dtype, d, x);
+    if (rc != TDMA_OK) return rc;
+    if (layout->offsets) return fail(TDMA_EINVAL, "several right-hand sides need a uniform layout");
+    if (coeffs->mode != TDMA_COEF_SHARED)
+        return fail(TDMA_EUNSUPPORTED, "several right-hand sides share one operator "
+                                       "(mode TDMA_COEF_SHARED)");
+    if (nrhs < 1) return fail(TDMA_EINVAL, "nrhs = %d (< 1)", nrhs);
+    if (rhs_stride < 0) return fail(TDMA_EINVAL, "negative rhs_stride");
+    if (nrhs > 1 && rhs_stride == 0) return fail(TDMA_EINVAL, "rhs_stride is 0 with nrhs = %d", nrhs);
+    const int64_t nsys = layout->nsys0 * layout->nsys1;
+    if (nsys == 0) return TDMA_OK;
+    const __int128 last = (__int128)(layout->n - 1) * layout->row_stride +
+                          (__int128)(layout->nsys0 - 1) * layout->sys_stride0 +
+                          (__int128)(layout->nsys1 - 1) * layout->sys_stride1 +
+                          (__int128)(nrhs - 1) * rhs_stride;
+    if (last >= ((__int128)1 << 62))
+        return fail(TDMA_EINVAL, "the layout and its right-hand sides span more than 2^62 elements");
+    MultiShape sh;
+    if (!multi_shape(dtype, layout->n, nsys, &sh))
+        return fail(TDMA_EUNSUPPORTED, "n = %lld is longer than the %d rows the multi-right-hand-side "
+                    "kernel holds", (long long)layout->n, dtype == TDMA_F64 ? 1024 : 2048);
+    const size_t esz = dtype == TDMA_F64 ? 8 : 4;
+    const auto even = [](int64_t v) { return (v & 1) == 0; };
+    const bool vec = nrhs >= 2 && rhs_stride == 1 && even(layout->row_stride) &&
+                     (layout->nsys0 == 1 || even(layout->sys_stride0)) &&
+                     (layout->nsys1 == 1 || even(layout->sys_stride1)) &&
+                     (uintptr_t)d % (2 * esz) == 0 && (uintptr_t)x % (2 * esz) == 0;
+    DeviceCtx *ctx = nullptr;
+    rc = get_ctx(&ctx);
+    if (rc != TDMA_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const hipError_t e = launch_multi(dtype, make_map(layout), make_coef(coeffs), sh, nrhs,
+                                      rhs_stride, vec, d, x, ctx->d_err, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "multi-right-hand-side launch");
+    return TDMA_OK;
+}
+
 int tdma_check(void *stream) {
     clear_error();
     DeviceCtx *ctx = nullptr;

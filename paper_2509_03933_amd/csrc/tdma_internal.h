@@ -63,4 +63,19 @@ bool copy_streamed_supported(const SysMap &map, const TileShape &shape);
 hipError_t launch_copy_streamed(int dtype, const SysMap &map, const TileShape &shape,
                                 const void *d, void *x, hipStream_t stream);
 
+// several right-hand sides over one shared operator (multi.hip): S systems x
+// P partitions (P <= 64) x M rows per lane, one tile per block
+struct MultiShape {
+    int M = 16;
+    int P_log2 = 0;
+    int S_log2 = 0;
+};
+// built-in shape for systems of n rows (false: n needs more than 64 partitions)
+bool multi_shape(int dtype, int64_t n, int64_t nsys, MultiShape *out);
+size_t multi_lds(int dtype, const MultiShape &shape, int nr);
+// vec: two right-hand sides adjacent (rhs_stride 1) and pair-aligned
+hipError_t launch_multi(int dtype, const SysMap &map, const Coef &coef, const MultiShape &shape,
+                        int nrhs, int64_t rhs_stride, bool vec, const void *d, void *x,
+                        int *err_flag, hipStream_t stream);
+
 }  // namespace tdma

@@ -12,9 +12,12 @@ from workloads import configs
 TOL_F64 = 1e-12      # FP64 bar (relative, per system, infinity norm)
 TOL_F32 = 1e-5       # plain FP32 bar
 TOL_REFINED = 1e-12  # FP32 sweeps + FP64 refinement
-# Ill-conditioned systems (the lowest FFT-Poisson modes, kappa up to ~6e9): where
-# the FP64 oracle itself is further than the bar from the long-double oracle,
-# a candidate passes within ILL_FACTOR times the oracle's own error.
+# Ill-conditioned systems (the lowest FFT-Poisson modes, kappa up to ~6e9): the
+# forward error of any FP64 solve grows like kappa * eps, and the FP64 oracle's
+# own distance from the long-double oracle measures it.  Where that distance
+# exceeds bar / ILL_FACTOR, a candidate passes within ILL_FACTOR times it of
+# the long-double oracle (a partitioned solve carries a few times the error
+# constant of one Thomas sweep).  Well-conditioned systems keep the bar.
 ILL_FACTOR = 10.0
 
 
@@ -25,11 +28,25 @@ def conditioned_error(x, a, b, c, d, tol):
     if err64 <= tol:
         return True, err64, None, None
     ref_ld = oracle.thomas(a, b, c, d, oracle.LONG_DOUBLE)
+    return _ill_conditioned(x, ref, ref_ld, tol, err64)
+
+
+def _ill_conditioned(x, ref, ref_ld, tol, err64):
     scale = np.max(np.abs(ref_ld))
     err_ld = float(np.max(np.abs(x - ref_ld)) / scale)
     e_orc = float(np.max(np.abs(ref - ref_ld)) / scale)
-    bar = max(tol, ILL_FACTOR * e_orc) if e_orc > tol else tol
+    bar = max(tol, ILL_FACTOR * e_orc) if ILL_FACTOR * e_orc > tol else tol
     return err_ld <= bar, err64, err_ld, e_orc
+
+
+def conditioned_error_complex(x, a, b, c, d, tol):
+    """conditioned_error for a complex right-hand side (complex oracle)."""
+    ref = oracle.thomas_complex(a, b, c, d)
+    err64 = float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
+    if err64 <= tol:
+        return True, err64, None, None
+    ref_ld = oracle.thomas_complex(a, b, c, d, oracle.LONG_DOUBLE)
+    return _ill_conditioned(x, ref, ref_ld, tol, err64)
 
 
 def gather_rows(layout, arr):
