@@ -14,6 +14,9 @@ Other workloads (measurement of the remaining configurations):
   partitioned  1024^3 per-row z-lines, tdma_solve_partitioned (P = 8, 4 streams)
   poisson      1024^2 FFT modes x n = 1024, shared operator + shift, FP64 fused
                and FP32+refine, plus the pinned (0,0) mode
+  poisson_complex  the same lines with complex right-hand sides (interleaved
+               re/im pairs), FP64, tdma_solve_multi with two right-hand sides
+               per system; unknowns are complex unknowns (32 B each)
   sweeps       384x256x768 x->y->z ADI sweeps (half the 768x512x1536 grid per
                axis) + 10,000 ragged systems recorded into one hipGraph
                (dependent chain + independent ragged branch)
@@ -59,6 +62,7 @@ KERNEL_SOURCES = {
     "k_shared_refine_walk": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
     "k_fused": [CSRC + "fused.hip", CSRC + "fused_tile.hip.h", CSRC + "tile.hip.h"],
     "k_refine": [CSRC + "refine.hip", CSRC + "tile.hip.h"],
+    "k_multi": [CSRC + "multi.hip", CSRC + "tile.hip.h"],
     "k_stage_a": [CSRC + "partitioned.hip", CSRC + "tile.hip.h"],
     "graph": [CSRC + "graph.cpp", CSRC + "fused.hip", CSRC + "shared.hip", CSRC + "fused_tile.hip.h",
               CSRC + "tile.hip.h"],
@@ -93,7 +97,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="adi",
-                    choices=["adi", "partitioned", "poisson", "sweeps", "plain", "autotune"])
+                    choices=["adi", "partitioned", "poisson", "poisson_complex", "sweeps", "plain",
+                             "autotune"])
     ap.add_argument("--grid", default=None, help="override the grid, e.g. 256,256,256")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--batch", type=int, default=0, help="partitioned: systems per batch")
@@ -356,6 +361,60 @@ def bench_poisson(args):
                                "report": rep, "faster_than_fp64": msr < ms}}, checks
 
 
+def bench_poisson_complex(args):
+    """Complex right-hand sides on the Poisson lines: one tdma_solve_multi call
+    (two right-hand sides per system, interleaved) plus the pinned mode per
+    step; beside it the same data through tdma_solve_batched once per part."""
+    import numpy as np
+    import torch
+    import paper_2509_03933_amd as tdma
+    from workloads import configs, device
+    nx, ny, nz = (int(v) for v in (args.grid or "1024,1024,1024").split(","))
+    p = configs.poisson_complex(nx, ny, nz)
+    pin = configs.poisson_complex_pinned(p)
+    d, coeffs = device.device_inputs(p)
+    pco = dict(mode=1, a=torch.from_numpy(pin.a).cuda(), b=torch.from_numpy(pin.b).cuda(),
+               c=torch.from_numpy(pin.c).cuda())
+    x = torch.empty_like(d)
+    lay = p.layout
+    st = torch.cuda.current_stream()
+    steps = max(1, min(args.steps, 10))
+
+    def step(i):
+        tdma.solve_multi(lay, coeffs, d, x, 2, 1, stream=st)
+        tdma.solve_multi(pin.layout, pco, d, x, 2, 1, stream=st)
+
+    def per_part(i):
+        for off in (0, 1):
+            tdma.solve_batched(lay, coeffs, d[off:], x[off:], stream=st)
+            tdma.solve_batched(pin.layout, pco, d[off:], x[off:], stream=st)
+
+    unknowns = lay.unknowns()
+    low = [(kx % nx) + nx * (ky % ny) for kx in range(-3, 4) for ky in range(-3, 4) if (kx, ky) != (0, 0)]
+    samp = np.array(sorted(set(sample_systems(lay.nsys, 30).tolist() + low) - {0}), dtype=np.int64)
+    ms_parts = timed(per_part, steps, 1, st)
+    ms = timed(step, steps, 1, st)
+    base = (samp % lay.nsys0) * lay.sys_stride0 + (samp // lay.nsys0) * lay.sys_stride1
+    idx = base[:, None] + np.arange(lay.n, dtype=np.int64)[None, :] * lay.row_stride
+    ti = torch.from_numpy(idx).cuda()
+    rows = x[ti].cpu().numpy() + 1j * x[ti + 1].cpu().numpy()
+    checks = [{"path": ("max_rel_err_vs_oracle",), "kind": "complex", "p": p, "systems": samp,
+               "rows": rows}]
+    return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
+               "dtype": "f64", "steps": steps,
+               "config": {"workload": f"fft_poisson_lines_complex_{nx}x{ny}x{nz}", "systems": lay.nsys,
+                          "n": lay.n, "right_hand_sides": "complex, interleaved (re, im)",
+                          "unknowns": "complex unknowns",
+                          "entry_point": "tdma_solve_multi (nrhs 2, rhs_stride 1; + pinned mode)"},
+               "max_rel_err_vs_oracle": None,
+               "roofline": roofline(32 * unknowns, ms, "k_multi",
+                                    f"k_multi_poisson_complex{nx}x{ny}x{nz}_f64"),
+               "per_part_solves": {"entry_point": "tdma_solve_batched on the real and the imaginary "
+                                                  "parts (+ pinned mode)",
+                                   "ms_per_step": round(ms_parts, 6),
+                                   "multi_speedup": round(ms_parts / ms, 3)}}, checks
+
+
 def bench_sweeps(args):
     import numpy as np
     import torch
@@ -443,6 +502,16 @@ def oracle_errors(checks):
                 if c["ld"] and e > 1e-12:   # ill-conditioned: the long-double oracle decides
                     e = min(e, rel(got, oracle.thomas(a, b, cc, d, oracle.LONG_DOUBLE)))
                 worst = max(worst, e)
+        elif c["kind"] == "complex":
+            p = c["p"]
+            for s, got in zip(c["systems"], c["rows"]):
+                re, im = configs.system_rhs(p, int(s))
+                b = p.b + p.shift[int(s)]
+                e = rel(got, oracle.thomas_complex(p.a, b, p.c, re + 1j * im))
+                if e > 1e-12:   # ill-conditioned: the long-double oracle decides
+                    e = min(e, rel(got, oracle.thomas_complex(p.a, b, p.c, re + 1j * im,
+                                                              oracle.LONG_DOUBLE)))
+                worst = max(worst, e)
         elif c["kind"] == "ragged":
             p = c["p"]
             for s in c["systems"]:
@@ -466,6 +535,28 @@ def cpu_baseline(p, target_s, max_systems=None):
     import oracle
     from workloads import configs
     lay = p.layout
+    if p.nrhs == 2:
+        # complex right-hand sides: the oracle's complex Thomas solve per system
+        k = max_systems or 1024
+        systems = []
+        for s in range(k):
+            re, im = configs.system_rhs(p, s)
+            b = p.b + (p.shift[s] if p.shift is not None else 0.0)
+            systems.append((p.a, b, p.c, re + 1j * im))
+        t0 = time.perf_counter()
+        passes = 0
+        while True:
+            for a, b, c, d in systems:
+                oracle.thomas_complex(a, b, c, d)
+            passes += 1
+            el = time.perf_counter() - t0
+            if el >= target_s or passes >= 1000:
+                break
+        unknowns = k * lay.n * passes
+        return {"value": round(unknowns / el / 1e9, 4), "unit": "G complex unknowns/s", "cores": 1,
+                "kind": "oracle",
+                "sample": f"the first {k} systems of the workload, {passes} pass(es), {el:.1f} s "
+                          f"wall, single-threaded C complex Thomas (FP64)"}
     if lay.extent() <= (1 << 25):
         a, b, c, d = configs.full_arrays(p)
         x = None
@@ -509,6 +600,7 @@ def main():
         copy_calibration()
         return
     fn = {"adi": bench_adi, "partitioned": bench_partitioned, "poisson": bench_poisson,
+          "poisson_complex": bench_poisson_complex,
           "sweeps": bench_sweeps, "plain": bench_plain, "autotune": bench_autotune}[args.workload]
     p, res, checks = fn(args)
     out = {"metric": METRIC, "value": res.pop("value"), "unit": "G unknowns/s", "n_gpus": 1,
