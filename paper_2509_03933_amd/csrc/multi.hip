@@ -220,10 +220,17 @@ inline size_t multi_lds_bytes(size_t esz, int S, int P, int M, int NR) {
 // right-hand sides rhs_stride elements apart.  VEC: NR == 2 with rhs_stride
 // 1 and every element pair 2*sizeof(T)-aligned, each row's two right-hand
 // sides moved as one vector.
+// Tile order: with spread > 0, block b takes tile (b * spread) mod nblocks
+// (spread coprime to nblocks: a bijection), so the blocks running at one
+// time hold tiles scattered over the whole system range.  A tile's rows
+// share one offset modulo the row stride; on long power-of-two strides
+// (the 16 MB rows of 1024^2 complex modes) neighbouring tiles then fall on
+// the same memory channels, scattered ones do not.  With spread == 0 the
+// order is XCD-aware (dev::xcd_tile), for tile rows narrower than a line.
 template <typename T, int M, int NR, bool SHIFT, bool VEC>
 __global__ void __launch_bounds__(512)
 k_multi(SysMap map, Coef coef, const T *__restrict__ d, T *__restrict__ x, int64_t rhs_stride,
-        int S_log2, int P_log2, int *err) {
+        int S_log2, int P_log2, int64_t spread, int *err) {
     static_assert(!VEC || NR == 2, "vector form moves two right-hand sides");
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
@@ -233,7 +240,9 @@ k_multi(SysMap map, Coef coef, const T *__restrict__ d, T *__restrict__ x, int64
     const int p = tid >> S_log2;
     const int r0 = p * M;
     const int R = P * M;
-    const int64_t k0 = dev::xcd_tile(blockIdx.x, gridDim.x) << S_log2;
+    const int64_t nb = gridDim.x;
+    const int64_t k0 = (spread > 0 ? ((int64_t)blockIdx.x * spread) % nb
+                                    : dev::xcd_tile(blockIdx.x, nb)) << S_log2;
     const LaneSys sys = dev::lane_system(map, k0 + s);
     const int rows_here = (int)(sys.nrows - r0 < 0 ? 0 : (sys.nrows - r0 > M ? M : sys.nrows - r0));
     T *CO = reinterpret_cast<T *>(lds);
@@ -313,6 +322,24 @@ k_multi(SysMap map, Coef coef, const T *__restrict__ d, T *__restrict__ x, int64
     if (bad && sys.valid) atomicOr(err, 1);
 }
 
+// A stride near nb / phi (the golden ratio) that is coprime to nb, so that
+// b -> b * stride mod nb is a bijection whose consecutive values are spread
+// evenly over [0, nb); 0 (no spreading) below 64 tiles.
+int64_t spread_stride(int64_t nb) {
+    if (nb < 64) return 0;
+    int64_t k = (int64_t)((double)nb * 0.6180339887498949) | 1;
+    auto gcd = [](int64_t a, int64_t b) {
+        while (b) {
+            const int64_t t = a % b;
+            a = b;
+            b = t;
+        }
+        return a;
+    };
+    while (gcd(k, nb) != 1) k += 2;
+    return k;
+}
+
 template <typename T, int M, int NR, bool SHIFT, bool VEC>
 hipError_t launch_t(const SysMap &map, const Coef &coef, const MultiShape &sh, int64_t rhs_stride,
                     const void *d, void *x, int *err, hipStream_t st) {
@@ -320,9 +347,12 @@ hipError_t launch_t(const SysMap &map, const Coef &coef, const MultiShape &sh, i
     const int64_t blocks = (map.nsys + S - 1) / S;
     if (blocks == 0) return hipSuccess;
     const size_t lds = multi_lds_bytes(sizeof(T), (int)S, 1 << sh.P_log2, M, NR);
+    // full 128-byte tile rows: scattered tile order; narrower: XCD-aware
+    const int64_t row_bytes = S * (int64_t)sizeof(T) * (VEC ? 2 : 1);
+    const int64_t spread = row_bytes >= 128 ? spread_stride(blocks) : 0;
     hipLaunchKernelGGL((k_multi<T, M, NR, SHIFT, VEC>), dim3((unsigned)blocks),
                        dim3((unsigned)(S << sh.P_log2)), lds, st, map, coef, (const T *)d, (T *)x,
-                       rhs_stride, sh.S_log2, sh.P_log2, err);
+                       rhs_stride, sh.S_log2, sh.P_log2, spread, err);
     return hipGetLastError();
 }
 

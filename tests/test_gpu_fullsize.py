@@ -263,3 +263,60 @@ def test_sweeps_and_ragged_graph_full_size():
         sl = slice(rg.layout.offsets[s], rg.layout.offsets[s + 1])
         ref = oracle.thomas(ra[sl], rb[sl], rc[sl], rd[sl])
         assert np.max(np.abs(xr[sl] - ref)) / np.max(np.abs(ref)) <= parity.TOL_F64
+
+
+def test_poisson_complex_1024_cubed():
+    """Complex right-hand sides on the 1024^3 Poisson lines through
+    tdma_solve_multi (two interleaved right-hand sides per mode), as the
+    benchmark runs it: every mode with |kx|, |ky| <= 16 against the complex
+    oracle under the conditioned rule, the pinned mode, and 65,536 bulk modes
+    vectorised against the oracle's complex batch solve."""
+    import paper_2509_03933_amd as tdma
+    from workloads import device
+    p = configs.poisson_complex(1024, 1024, 1024)
+    pin = configs.poisson_complex_pinned(p)
+    d, co = device.device_inputs(p)
+    pin_co = dict(mode=1, a=torch.from_numpy(pin.a).cuda(), b=torch.from_numpy(pin.b).cuda(),
+                  c=torch.from_numpy(pin.c).cuda())
+    x = torch.empty_like(d)
+    tdma.solve_multi(p.layout, co, d, x, 2, 1)
+    tdma.solve_multi(pin.layout, pin_co, d, x, 2, 1)
+    tdma.check()
+    assert torch.isfinite(x).all()
+    lay = p.layout
+
+    def got_rows(systems):
+        idx = _rows(lay, systems)
+        ti = torch.from_numpy(idx).cuda()
+        return idx, x[ti].cpu().numpy() + 1j * x[ti + 1].cpu().numpy()
+
+    # the lowest modes and the pinned mode, one by one
+    low = _poisson_low(p)
+    _, rows = got_rows(low)
+    worst = 0.0
+    for s, got in zip(low, rows):
+        re, im = configs.system_rhs(p, int(s))
+        if s == 0:
+            a, b, c = pin.a, pin.b, pin.c
+        else:
+            a, b, c = p.a, p.b + p.shift[int(s)], p.c
+        ok, e64, eld, eorc = parity.conditioned_error_complex(got, a, b, c, re + 1j * im,
+                                                              parity.TOL_F64)
+        if eld is not None:
+            print(f"mode {int(s)}: {e64:.2e} vs FP64 oracle, {eld:.2e} vs long double, "
+                  f"oracle {eorc:.2e}")
+        assert ok, (int(s), e64, eld, eorc)
+        worst = max(worst, e64 if eld is None else min(e64, eld))
+    print(f"complex low modes: {low.size}, worst {worst:.3e}", flush=True)
+    # the bulk, vectorised
+    systems = _sample_many(lay.nsys, exclude=low)
+    idx, got = got_rows(systems)
+    _, _, _, dre = configs.element_values(p, idx.ravel(), None, lay.n)
+    _, _, _, dim = configs.element_values(p, idx.ravel() + 1, None, lay.n)
+    packed = configs.Layout(n=lay.n, nsys0=systems.size, nsys1=1, row_stride=1,
+                            sys_stride0=lay.n, sys_stride1=0)
+    ref = oracle.solve_batch_complex(packed, p.a, p.b, p.c, dre + 1j * dim,
+                                     shift=p.shift[systems]).reshape(idx.shape)
+    err = np.max(np.abs(got - ref), axis=1) / np.maximum(np.max(np.abs(ref), axis=1), 1e-300)
+    print(f"complex bulk: {systems.size} modes, max rel err {err.max():.3e}", flush=True)
+    assert err.max() <= parity.TOL_F64, (float(err.max()), int(systems[err.argmax()]))
