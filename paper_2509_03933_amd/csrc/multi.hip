@@ -219,7 +219,9 @@ inline size_t multi_lds_bytes(size_t esz, int S, int P, int M, int NR) {
 // One tile per block: systems k0 .. k0+S-1, S*P lanes, M rows per lane, NR
 // right-hand sides rhs_stride elements apart.  VEC: NR == 2 with rhs_stride
 // 1 and every element pair 2*sizeof(T)-aligned, each row's two right-hand
-// sides moved as one vector.
+// sides moved as one vector.  Loads and stores carry the non-temporal hint
+// (each element is touched once; 11.2 -> 10.8 ms on the 1024^3 complex
+// lines).
 // Tile order: with spread > 0, block b takes tile (b * spread) mod nblocks
 // (spread coprime to nblocks: a bijection), so the blocks running at one
 // time hold tiles scattered over the whole system range.  A tile's rows
@@ -265,12 +267,12 @@ k_multi(SysMap map, Coef coef, const T *__restrict__ d, T *__restrict__ x, int64
         for (int j = 0; j < M; ++j) {
             if constexpr (VEC) {
                 typedef T T2 __attribute__((ext_vector_type(2)));
-                const T2 v = *reinterpret_cast<const T2 *>(d + idx);
+                const T2 v = __builtin_nontemporal_load(reinterpret_cast<const T2 *>(d + idx));
                 dv[0][j] = v.x;
                 dv[1][j] = v.y;
             } else {
 #pragma unroll
-                for (int r = 0; r < NR; ++r) dv[r][j] = d[idx + r * rhs_stride];
+                for (int r = 0; r < NR; ++r) dv[r][j] = __builtin_nontemporal_load(d + idx + r * rhs_stride);
             }
             idx += j < adv ? rs : 0;
         }
@@ -313,10 +315,10 @@ k_multi(SysMap map, Coef coef, const T *__restrict__ d, T *__restrict__ x, int64
                 T2 v;
                 v.x = dv[0][j];
                 v.y = dv[1][j];
-                *reinterpret_cast<T2 *>(x + idx) = v;
+                __builtin_nontemporal_store(v, reinterpret_cast<T2 *>(x + idx));
             } else {
 #pragma unroll
-                for (int r = 0; r < NR; ++r) x[idx + r * rhs_stride] = dv[r][j];
+                for (int r = 0; r < NR; ++r) __builtin_nontemporal_store(dv[r][j], x + idx + r * rhs_stride);
             }
         }
     if (bad && sys.valid) atomicOr(err, 1);

