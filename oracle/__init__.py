@@ -59,6 +59,8 @@ def _load():
             lib.oracle_solve_batch.restype = ctypes.c_int64
             lib.oracle_matvec.argtypes = [i64, dp, dp, dp, dp, dp]
             lib.oracle_matvec.restype = None
+            lib.oracle_pdd.argtypes = [i64, dp, dp, dp, dp, dp, i64]
+            lib.oracle_pdd.restype = ctypes.c_int
             lib.oracle_thomas_z.argtypes = [i64, dp, dp, dp, dp, dp, ctypes.c_int]
             lib.oracle_thomas_z.restype = ctypes.c_int
             lib.oracle_solve_batch_z.argtypes = [
@@ -125,6 +127,19 @@ def solve_batch(layout, mode, a, b, c, d, shift=None, precision=F64, systems=Non
         return x, st
     if failed:
         raise OracleError(f"{failed} systems hit a zero or non-finite pivot")
+    return x
+
+
+def pdd(a, b, c, d, m):
+    """PDD approximation (partitions of m rows) of one system; see oracle_pdd."""
+    a, b, c, d = _f64(a), _f64(b), _f64(c), _f64(d)
+    n = d.size
+    if not (a.size == b.size == c.size == n):
+        raise ValueError("a, b, c, d must have equal length")
+    x = np.empty(n)
+    rc = _load().oracle_pdd(n, _ptr(a), _ptr(b), _ptr(c), _ptr(d), _ptr(x), int(m))
+    if rc != OK:
+        raise OracleError(f"oracle_pdd failed: {rc}")
     return x
 
 

@@ -296,6 +296,85 @@ int64_t oracle_solve_batch_z(int64_t n, int64_t nsys0, int64_t nsys1, int64_t ro
     return failed;
 }
 
+/*
+ * Parallel diagonally dominant (PDD) approximation (Sun 1989; the paper's
+ * momentum solver, Sec. 5.1) of one contiguous system, partitions of m rows
+ * (the last one shorter when m does not divide n).  Partition k with rows
+ * r0..r1 and its own block A_k of A:
+ *   A_k xt = d_k,   A_k v = a_{r0} e_first,   A_k w = c_{r1} e_last
+ * (v = 0 for the first partition, w = 0 for the last), so that exactly
+ *   x_k = xt - v * x_{r0 - 1} - w * x_{r1 + 1}.
+ * At the interface between partitions k and k+1 the two unknowns
+ * y1 = x_{k,last} and y2 = x_{k+1,first} satisfy, exactly,
+ *   y1 + v_k[last] x_{k-1,last} + w_k[last] y2 = xt_k[last]
+ *   v_{k+1}[first] y1 + y2 + w_{k+1}[first] x_{k+2,first} = xt_{k+1}[first];
+ * PDD drops the two far couplings v_k[last] and w_{k+1}[first] (they decay
+ * geometrically with m for a diagonally dominant A), solves the 2 x 2
+ * systems independently, and then applies the correction above to every row
+ * of every partition with the interface values so found.  With one
+ * partition this is the Thomas solve itself.  Each block solve is
+ * thomas_f64.  Returns ORACLE_OK, or an error (bad arguments, zero pivot).
+ */
+int oracle_pdd(int64_t n, const double *a, const double *b, const double *c, const double *d,
+               double *x, int64_t m)
+{
+    if (n < 1 || m < 1 || !a || !b || !c || !d || !x) return ORACLE_EINVAL;
+    const int64_t np = (n + m - 1) / m;
+    double *xt = (double *)malloc(3 * (size_t)n * sizeof(double));
+    double *w2 = (double *)malloc(5 * (size_t)m * sizeof(double));
+    double *yl = (double *)malloc(2 * (size_t)np * sizeof(double));   /* x_{k,last}, x_{k,first} */
+    if (!xt || !w2 || !yl) { free(xt); free(w2); free(yl); return ORACLE_ENOMEM; }
+    double *v = xt + n, *w = xt + 2 * n;
+    double *cp = w2, *dp = w2 + m, *rhs = w2 + 2 * m, *sb = w2 + 3 * m, *sa = w2 + 4 * m;
+    int rc = ORACLE_OK;
+    for (int64_t k = 0; k < np && rc == ORACLE_OK; ++k) {
+        const int64_t r0 = k * m, len = (r0 + m <= n) ? m : n - r0;
+        /* the block A_k: sub-diagonal without its first entry, super-diagonal
+         * without its last (those couple to the neighbours) */
+        for (int64_t i = 0; i < len; ++i) { sa[i] = (i > 0) ? a[r0 + i] : 0.0; sb[i] = b[r0 + i]; }
+        double *sc = rhs;   /* reuse: super-diagonal of the block */
+        for (int64_t i = 0; i < len; ++i) sc[i] = (i < len - 1) ? c[r0 + i] : 0.0;
+        rc = thomas_f64(len, sa, sb, sc, d + r0, xt + r0, cp, dp);
+        if (rc != ORACLE_OK) break;
+        double *e = (double *)malloc((size_t)len * sizeof(double));
+        if (!e) { rc = ORACLE_ENOMEM; break; }
+        for (int64_t i = 0; i < len; ++i) e[i] = 0.0;
+        if (k > 0) e[0] = a[r0];
+        rc = thomas_f64(len, sa, sb, sc, e, v + r0, cp, dp);
+        for (int64_t i = 0; i < len; ++i) e[i] = 0.0;
+        if (rc == ORACLE_OK && k < np - 1) {
+            e[len - 1] = c[r0 + len - 1];
+            rc = thomas_f64(len, sa, sb, sc, e, w + r0, cp, dp);
+        } else if (rc == ORACLE_OK) {
+            for (int64_t i = 0; i < len; ++i) w[r0 + i] = 0.0;
+        }
+        free(e);
+    }
+    if (rc == ORACLE_OK) {
+        /* interface k | k+1: y1 = x_{k,last}, y2 = x_{k+1,first} */
+        for (int64_t k = 0; k + 1 < np; ++k) {
+            const int64_t last = (k + 1) * m - 1, first = last + 1;
+            const double det = 1.0 - w[last] * v[first];
+            if (det == 0.0 || !isfinite(det)) { rc = ORACLE_ESINGULAR; break; }
+            yl[2 * k] = (xt[last] - w[last] * xt[first]) / det;
+            yl[2 * (k + 1) + 1] = (xt[first] - v[first] * xt[last]) / det;
+        }
+    }
+    if (rc == ORACLE_OK) {
+        for (int64_t k = 0; k < np; ++k) {
+            const int64_t r0 = k * m, len = (r0 + m <= n) ? m : n - r0;
+            const double left = (k > 0) ? yl[2 * (k - 1)] : 0.0;           /* x_{k-1,last} */
+            const double right = (k < np - 1) ? yl[2 * (k + 1) + 1] : 0.0;  /* x_{k+1,first} */
+            for (int64_t i = 0; i < len; ++i)
+                x[r0 + i] = xt[r0 + i] - v[r0 + i] * left - w[r0 + i] * right;
+        }
+    }
+    free(xt);
+    free(w2);
+    free(yl);
+    return rc;
+}
+
 /* y = A x for one contiguous system (FP64, no FMA): the residual check's
  * matrix-vector product.  a[0] and c[n-1] are not read. */
 void oracle_matvec(int64_t n, const double *a, const double *b, const double *c,
