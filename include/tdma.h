@@ -133,6 +133,26 @@ int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeff
                              const void *d, void *x, const tdma_tile *tile, void *stream);
 
 /*
+ * tdma_solve_pdd: the PDD approximation (Sun's parallel diagonally dominant
+ * method; the paper solves its wall-normal momentum systems with it, Sec.
+ * 5.1) in the fused kernel.  Each system is split into partitions of
+ * rows_per_partition rows (the last one shorter); Stage A and C are those of
+ * tdma_solve_batched, Stage B solves, for every pair of neighbouring
+ * partitions, the 2 x 2 system of the last unknown of the one and the first
+ * of the other, with the couplings to the far neighbours dropped (the spike
+ * tips: for a diagonally dominant matrix they decay geometrically with the
+ * partition length, and so does the error against the exact solution; the
+ * caller chooses the length for the accuracy it needs).  One partition
+ * (n <= rows_per_partition) gives the exact solution.
+ * rows_per_partition: 4, 8 or 16 (FP64), also 32 (FP32); at most 1024
+ * partitions (512 for 16 rows in FP64, 32 in FP32).  Any coefficient mode,
+ * uniform layouts.  Errors: EINVAL for another partition length or a ragged
+ * layout, EUNSUPPORTED for too many partitions.  x may alias d.
+ */
+int tdma_solve_pdd(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype,
+                   int rows_per_partition, const void *d, void *x, void *stream);
+
+/*
  * tdma_solve_multi: several right-hand sides per system over one operator.
  * System k of `layout` has nrhs right-hand sides; right-hand side r has its
  * row i at element (start of system k) + i*row_stride + r*rhs_stride of d,

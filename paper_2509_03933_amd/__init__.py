@@ -99,6 +99,7 @@ def lib():
             L.tdma_graph_destroy.restype = None
             L.tdma_autotune.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, vp, vp, i, vp]
             L.tdma_copy_streamed.argtypes = [ctypes.POINTER(_Layout), i, vp, vp, vp]
+            L.tdma_solve_pdd.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, i, vp, vp, vp]
             L.tdma_solve_multi.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, i,
                                            ctypes.c_int64, vp, vp, vp]
             L.tdma_check.argtypes = [vp]
@@ -111,7 +112,7 @@ def lib():
             L.tdma_last_error.restype = ctypes.c_char_p
             L.tdma_shutdown.restype = None
             for f in ("tdma_solve_batched", "tdma_solve_batched_tiled", "tdma_solve_partitioned", "tdma_solve_refined",
-                      "tdma_solve_multi", "tdma_copy_streamed",
+                      "tdma_solve_multi", "tdma_solve_pdd", "tdma_copy_streamed",
                       "tdma_graph_create", "tdma_graph_launch", "tdma_autotune", "tdma_check"):
                 getattr(L, f).restype = ctypes.c_int
             _lib = L
@@ -119,7 +120,7 @@ def lib():
 
 
 EXPORTED_SYMBOLS = ("tdma_solve_batched", "tdma_solve_batched_tiled", "tdma_solve_partitioned", "tdma_solve_refined",
-                    "tdma_copy_streamed", "tdma_solve_multi",
+                    "tdma_copy_streamed", "tdma_solve_multi", "tdma_solve_pdd",
                     "tdma_graph_create", "tdma_graph_launch", "tdma_graph_destroy",
                     "tdma_autotune", "tdma_autotune_last_json", "tdma_pipeline_model_ms",
                     "tdma_check", "tdma_status_string", "tdma_last_error", "tdma_shutdown")
@@ -255,6 +256,15 @@ def solve_batched_tiled(layout, coeffs, d, x, M, S, P, kernel=0, stream=None):
     _raise(lib().tdma_solve_batched_tiled(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),
                                           ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                           ctypes.byref(t), _stream_handle(stream)))
+
+
+def solve_pdd(layout, coeffs, d, x, rows_per_partition, stream=None):
+    """PDD approximation with partitions of rows_per_partition rows
+    (tdma_solve_pdd)."""
+    L, C, keep = _prepare(layout, coeffs, d, x)
+    _raise(lib().tdma_solve_pdd(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),
+                                int(rows_per_partition), ctypes.c_void_p(d.data_ptr()),
+                                ctypes.c_void_p(x.data_ptr()), _stream_handle(stream)))
 
 
 def solve_multi(layout, coeffs, d, x, nrhs, rhs_stride, stream=None):

@@ -595,6 +595,46 @@ int tdma_copy_streamed(const tdma_layout *layout, int dtype, const void *src, vo
     return TDMA_OK;
 }
 
+int tdma_solve_pdd(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype,
+                   int rows_per_partition, const void *d, void *x, void *stream) {
+    clear_error();
+    int rc = validate(layout, coeffs, dtype, d, x);
+    if (rc != TDMA_OK) return rc;
+    if (layout->offsets) return fail(TDMA_EINVAL, "the PDD solve takes uniform layouts");
+    const int m = rows_per_partition;
+    TileShape sh;
+    sh.kernel = 0;
+    sh.M = m;
+    sh.pdd = true;
+    sh.contig = layout->row_stride == 1;
+    sh.S_log2 = 0;
+    sh.P = 1;
+    if (!fused_supported(dtype, sh))
+        return fail(TDMA_EINVAL, "rows_per_partition = %d (4, 8 or 16; 32 too in FP32)", m);
+    const int64_t nsys = layout->nsys0 * layout->nsys1;
+    if (nsys == 0) return TDMA_OK;
+    const int64_t P = (layout->n + m - 1) / m;
+    const int maxt = fused_max_threads(dtype, m);
+    if (P > maxt)
+        return fail(TDMA_EUNSUPPORTED, "n = %lld needs %lld partitions of %d rows (at most %d)",
+                    (long long)layout->n, (long long)P, m, maxt);
+    sh.P = (int)P;
+    const int esz = dtype == TDMA_F64 ? 8 : 4;
+    int S_log2 = sh.contig ? ilog2_floor(std::max<int64_t>(1, 256 / P)) : ilog2_floor(128 / esz);
+    while (S_log2 > 0 && ((int64_t)1 << S_log2) * P > maxt) --S_log2;
+    while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= nsys) --S_log2;
+    sh.S_log2 = S_log2;
+    while (sh.contig && sh.S_log2 > 0 && fused_lds_bytes(dtype, sh) > 96 * 1024) --sh.S_log2;
+    if (sh.contig && fused_lds_bytes(dtype, sh) > 160 * 1024)
+        return fail(TDMA_EUNSUPPORTED, "a tile of n = %lld contiguous rows exceeds the LDS",
+                    (long long)layout->n);
+    DeviceCtx *ctx = nullptr;
+    rc = get_ctx(&ctx);
+    if (rc != TDMA_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    return launch_uniform(sh, layout, coeffs, dtype, d, x, ctx->d_err, (hipStream_t)stream);
+}
+
 int tdma_solve_multi(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype, int nrhs,
                      int64_t rhs_stride, const void *d, void *x, void *stream) {
     clear_error();

@@ -7,16 +7,18 @@ namespace tdma {
 namespace {
 
 // CO: a shared operator whose coefficient rows are held in LDS (fused_tile_co).
-template <typename T, int M, bool LIKE_D, bool SHIFT, bool CONTIG, bool CO>
+// PDD: Stage B by the PDD approximation (its own instantiations, so that the
+// exact kernels keep their register allocation).
+template <typename T, int M, bool LIKE_D, bool SHIFT, bool CONTIG, bool CO, bool PDD>
 __global__ void __launch_bounds__((fused_max_threads<T, M>()))
 k_fused(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P, int *err) {
     extern __shared__ double lds[];
     const int64_t k0 = dev::xcd_tile(blockIdx.x, gridDim.x) << S_log2;
     if (map.count && k0 >= dev::launch_nsys(map)) return;   // whole tile past a device count
     if constexpr (CO)
-        fused_tile_co<T, M, SHIFT, CONTIG>(map, coef, d, x, S_log2, P, k0, err, lds);
+        fused_tile_co<T, M, SHIFT, CONTIG, PDD>(map, coef, d, x, S_log2, P, k0, err, lds);
     else
-        fused_tile<T, M, LIKE_D, SHIFT, CONTIG>(map, coef, d, x, S_log2, P, k0, err, lds);
+        fused_tile<T, M, LIKE_D, SHIFT, CONTIG, PDD>(map, coef, d, x, S_log2, P, k0, err, lds);
 }
 
 template <typename T, int M, bool LIKE_D, bool SHIFT, bool CONTIG, bool CO>
@@ -25,9 +27,14 @@ hipError_t launch_t(const SysMap &map, const Coef &coef, const TileShape &sh, co
     const int64_t S = (int64_t)1 << sh.S_log2;
     const int64_t blocks = (map.nsys + S - 1) / S;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_fused<T, M, LIKE_D, SHIFT, CONTIG, CO>), dim3((unsigned)blocks),
-                       dim3(sh.threads()), lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2,
-                       sh.P, err);
+    if (sh.pdd)
+        hipLaunchKernelGGL((k_fused<T, M, LIKE_D, SHIFT, CONTIG, CO, true>), dim3((unsigned)blocks),
+                           dim3(sh.threads()), lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2,
+                           sh.P, err);
+    else
+        hipLaunchKernelGGL((k_fused<T, M, LIKE_D, SHIFT, CONTIG, CO, false>), dim3((unsigned)blocks),
+                           dim3(sh.threads()), lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2,
+                           sh.P, err);
     return hipGetLastError();
 }
 

@@ -17,12 +17,62 @@ using dev::stage_out;
 template <typename T, int M>
 constexpr int fused_max_threads() { return (int)sizeof(T) * M >= 128 ? 512 : 1024; }
 
+// Stage B replaced by the PDD approximation (Sun's parallel diagonally
+// dominant method, which the paper uses for its momentum solves, Sec. 5.1).
+// A partition's two interface rows, solved for its own first and last
+// unknowns, give the spike form
+//   X_first = xf~ - vf X_left - wf X_right,   X_last = xl~ - vl X_left - wl X_right
+// (X_left: the previous partition's last unknown, X_right: the next one's
+// first; with D = 1 - fc la: xf~ = (fd - fc ld)/D, vf = fa/D, wf = -fc lc/D,
+// xl~ = (ld - la fd)/D, vl = -la fa/D, wl = lc/D).  At each interface the
+// couplings to the far side (vl of the left partition, wf of the right one:
+// spike tips that decay geometrically with the partition length for a
+// diagonally dominant matrix) are dropped, leaving independent 2 x 2 systems
+// in (X_last of p, X_first of p+1); each lane solves the two interfaces it
+// touches from its neighbours' values (one LDS exchange) and applies the
+// spike form.  One partition: exact.  LDS: 4 x S x P doubles.  Every thread
+// of the block calls it.
+__device__ __forceinline__ void pdd_interface(double *lds, int S, int s, int p, int P, Iface f,
+                                              double &x_first, double &x_last, bool &bad) {
+    const double D = 1.0 - f.fc * f.la;
+    bad |= dev::bad_pivot(D);
+    const double iD = dev::recip(D);
+    const double xtf = (f.fd - f.fc * f.ld) * iD, vf = f.fa * iD, wf = -f.fc * f.lc * iD;
+    const double xtl = (f.ld - f.la * f.fd) * iD, vl = -f.la * f.fa * iD, wl = f.lc * iD;
+    const int SP = S * P;
+    double *XTF = lds, *VF = lds + SP, *XTL = lds + 2 * SP, *WL = lds + 3 * SP;
+    const int q = p * S + s;
+    __syncthreads();   // the LDS is free
+    XTF[q] = xtf;
+    VF[q] = vf;
+    XTL[q] = xtl;
+    WL[q] = wl;
+    __syncthreads();
+    double left = 0.0, right = 0.0;
+    if (p > 0) {         // interface p-1 | p: the previous partition's last unknown
+        const double xtl_m = XTL[q - S], wl_m = WL[q - S];
+        const double det = 1.0 - wl_m * vf;
+        bad |= dev::bad_pivot(det);
+        left = (xtl_m - wl_m * xtf) * dev::recip(det);
+    }
+    if (p < P - 1) {     // interface p | p+1: the next partition's first unknown
+        const double xtf_p = XTF[q + S], vf_p = VF[q + S];
+        const double det = 1.0 - wl * vf_p;
+        bad |= dev::bad_pivot(det);
+        right = (xtf_p - vf_p * xtl) * dev::recip(det);
+    }
+    x_first = xtf - vf * left - wf * right;
+    x_last = xtl - vl * left - wl * right;
+}
+
 }  // namespace fused_detail
 using namespace fused_detail;
 
 // One tile of the fused solve: systems k0 .. k0+S-1 of `map`, S*P lanes of the
-// calling block, M rows per lane.  Every thread of the block must call it.
-template <typename T, int M, bool LIKE_D, bool SHIFT, bool CONTIG>
+// calling block, M rows per lane.  PDD: Stage B by the PDD approximation
+// (pdd_interface) instead of the exact interface solve.  Every thread
+// of the block must call it.
+template <typename T, int M, bool LIKE_D, bool SHIFT, bool CONTIG, bool PDD>
 __device__ __forceinline__ void fused_tile(const SysMap &map, const Coef &coef, const T *d, T *x,
                                            int S_log2, int P, int64_t k0, int *err, double *lds) {
 
@@ -109,7 +159,9 @@ __device__ __forceinline__ void fused_tile(const SysMap &map, const Coef &coef, 
     bool bad = false;
     const Iface f = dev::reduce_partition<T, M>(av, bv, cv, dv, bad);
     double xf, xl;
-    if (P <= 64 && (P & (P - 1)) == 0)
+    if constexpr (PDD)
+        pdd_interface(lds, S, s, p, P, f, xf, xl, bad);
+    else if (P <= 64 && (P & (P - 1)) == 0)
         dev::pcr_interface_wave(lds, S, s, p, P, __builtin_ctz(P), f, xf, xl, bad);
     else
         dev::pcr_interface(lds, S, s, p, P, f, xf, xl, bad);
@@ -156,7 +208,7 @@ __host__ __device__ inline size_t fused_co_offset(size_t esz, int S, int P, int 
 // rows in registers (three values per row instead of four), which doubles
 // the blocks a CU holds.  Same arithmetic as fused_tile.  Every thread of
 // the block must call it.
-template <typename T, int M, bool SHIFT, bool CONTIG>
+template <typename T, int M, bool SHIFT, bool CONTIG, bool PDD>
 __device__ __forceinline__ void fused_tile_co(const SysMap &map, const Coef &coef, const T *d, T *x,
                                               int S_log2, int P, int64_t k0, int *err, double *lds) {
     const int tid = threadIdx.x;
@@ -226,7 +278,9 @@ __device__ __forceinline__ void fused_tile_co(const SysMap &map, const Coef &coe
     const Iface f = dev::reduce_partition_rows<T, M, SHIFT>(CO + r0, CO + R + r0, CO + 2 * R + r0, sh,
                                                             rows_here, ah, ch, dv, bad);
     double xf, xl;
-    if (P <= 64 && (P & (P - 1)) == 0)
+    if constexpr (PDD)
+        pdd_interface(lds, S, s, p, P, f, xf, xl, bad);
+    else if (P <= 64 && (P & (P - 1)) == 0)
         dev::pcr_interface_wave(lds, S, s, p, P, __builtin_ctz(P), f, xf, xl, bad);
     else
         dev::pcr_interface(lds, S, s, p, P, f, xf, xl, bad);

@@ -37,6 +37,7 @@ struct TileShape {
     bool contig = false;    // stage loads/stores through LDS (row_stride == 1)
     int kernel = 0;         // 0: generic fused kernel, 1: shared-operator kernel,
                             // 2: its streaming form (resident blocks walk the tiles)
+    bool pdd = false;       // kernel 0 only: Stage B by the PDD approximation
     int threads() const { return (1 << S_log2) * P; }
 };
 
