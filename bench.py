@@ -53,6 +53,9 @@ REFINE_TOL = 1e-12
 # refinement corrections predicts (slowly but steadily converging systems
 # then stay out of the FP64 fallback)
 REFINE_CRITERION = 1
+# PDD leg of the ADI workload: partitions of 16 rows (the longest a lane
+# holds in FP64); its error against the exact solution is reported beside
+PDD_ROWS = 16
 HBM_PEAK_GBS = 8000.0
 CSRC = "paper_2509_03933_amd/csrc/"
 KERNEL_SOURCES = {
@@ -103,6 +106,7 @@ def parse():
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--batch", type=int, default=0, help="partitioned: systems per batch")
     ap.add_argument("--no-refine", action="store_true", help="skip the FP32+refine leg")
+    ap.add_argument("--no-pdd", action="store_true", help="skip the PDD leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
@@ -235,6 +239,20 @@ def bench_adi(args):
             "roofline": roofline(bytes_step, msr, "k_shared_refine_walk",
                                  f"k_shared_refine_walk_adi{nx}x{ny}x{nz}_f64"),
             "faster_than_fp64": msr < ms,
+        }
+    if args.dtype == "f64" and not args.no_pdd:
+        msp = timed(lambda i: tdma.solve_pdd(lay, coeffs, ds[i % n], xs[i % n], PDD_ROWS, stream=st),
+                    args.steps, args.warmup, st)
+        tdma.solve_pdd(lay, coeffs, ds[0], xs[0], PDD_ROWS, stream=st)
+        rows = grab_rows(p, xs[0], samp)
+        checks.append({"path": ("pdd", "max_rel_err_vs_oracle_pdd"), "kind": "pdd", "p": p,
+                       "systems": samp, "rows": rows, "m": PDD_ROWS})
+        checks.append(check(("pdd", "max_rel_err_vs_exact"), p, samp, rows))
+        out["pdd"] = {
+            "value": round(unknowns / (msp * 1e-3) / 1e9, 3), "ms_per_step": round(msp, 6),
+            "entry_point": f"tdma_solve_pdd ({PDD_ROWS} rows per partition; an approximation)",
+            "max_rel_err_vs_oracle_pdd": None, "max_rel_err_vs_exact": None,
+            "roofline": roofline(bytes_step, msp, "k_fused", f"k_fused_pdd_adi{nx}x{ny}x{nz}_f64"),
         }
     # the same memory traffic with no arithmetic (same tile walk and grid):
     # the ceiling of this access pattern on the device
@@ -502,6 +520,11 @@ def oracle_errors(checks):
                 if c["ld"] and e > 1e-12:   # ill-conditioned: the long-double oracle decides
                     e = min(e, rel(got, oracle.thomas(a, b, cc, d, oracle.LONG_DOUBLE)))
                 worst = max(worst, e)
+        elif c["kind"] == "pdd":
+            p = c["p"]
+            for s, got in zip(c["systems"], c["rows"]):
+                a, b, cc, d = configs.system_inputs(p, int(s))
+                worst = max(worst, rel(got, oracle.pdd(a, b, cc, d, c["m"])))
         elif c["kind"] == "complex":
             p = c["p"]
             for s, got in zip(c["systems"], c["rows"]):
