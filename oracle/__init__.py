@@ -5,8 +5,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 (``paper_2509_03933_amd``) and never imports it.
 
 ``oracle.c`` computes x = A^{-1} d per system with the textbook Thomas
-algorithm in FP64 (or long double); see its header for the definition and the
-paper passages it follows.  This module builds ``liboracle.so`` with gcc
+algorithm in FP64 (or long double), real or complex, and the PDD
+approximation per system; see its header for the definitions and the paper
+passages they follow.  This module builds ``liboracle.so`` with gcc
 (``-O2 -ffp-contract=off``, no fast-math) and wraps it with ctypes.
 """
 import ctypes

@@ -16,6 +16,12 @@
  * without pivoting, forward elimination then back substitution; the
  * sequential O(n) method the paper's introduction starts from).
  *
+ * Also here: the same definition for complex systems (oracle_thomas_z and its
+ * batch over shared real tables, for the complex Poisson right-hand sides),
+ * and the PDD approximation (oracle_pdd), which is not x = A^{-1} d but the
+ * published partitioned method the paper uses for its momentum systems; its
+ * header states its steps.
+ *
  * Conventions: a[0] and c[n-1] of every system are never read (there is no
  * x_{-1} or x_n).  Arithmetic is IEEE FP64 (or x87 80-bit long double for the
  * *_ld variant), round to nearest, no fused multiply-add (built with

@@ -320,3 +320,30 @@ def test_poisson_complex_1024_cubed():
     err = np.max(np.abs(got - ref), axis=1) / np.maximum(np.max(np.abs(ref), axis=1), 1e-300)
     print(f"complex bulk: {systems.size} modes, max rel err {err.max():.3e}", flush=True)
     assert err.max() <= parity.TOL_F64, (float(err.max()), int(systems[err.argmax()]))
+
+
+def test_adi_256_cubed_pdd():
+    """The PDD leg of the benchmark (256^3 ADI sweep, 16-row partitions):
+    sampled systems against the oracle's PDD on the same partitions, and
+    the truncation against the exact solution at the level the method
+    predicts for this operator."""
+    import paper_2509_03933_amd as tdma
+    from workloads import device
+    p = configs.adi(256, 256, 256)
+    d, co = device.device_inputs(p)
+    x = torch.empty_like(d)
+    tdma.solve_pdd(p.layout, co, d, x, 16)
+    tdma.check()
+    assert torch.isfinite(x).all()
+    xh = x.double()
+    worst = trunc = 0.0
+    for s in _sample(p.layout.nsys, 64):
+        a, b, c, dd = configs.system_inputs(p, int(s))
+        got = xh[torch.from_numpy(p.layout.sys_rows(int(s))).cuda()].cpu().numpy()
+        ref = oracle.pdd(a, b, c, dd, 16)
+        worst = max(worst, np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        ex = oracle.thomas(a, b, c, dd)
+        trunc = max(trunc, np.max(np.abs(got - ex)) / np.max(np.abs(ex)))
+    print(f"PDD 256^3: vs oracle PDD {worst:.2e}, vs exact {trunc:.2e}", flush=True)
+    assert worst <= parity.TOL_F64
+    assert trunc <= 1e-7
