@@ -23,6 +23,8 @@
  *  - A zero or non-finite pivot met on the device sets a sticky per-device
  *    flag, reported as TDMA_ESINGULAR by tdma_check() (which clears it).
  *  - Element counts, strides and offsets are in ELEMENTS, not bytes.
+ *  - One call takes at most 2^31 - 1 systems (TDMA_EUNSUPPORTED beyond; split
+ *    the batch) and a layout spanning fewer than 2^62 elements (TDMA_EINVAL).
  *  - Threads: any host thread may call; each device's host-side state (plan
  *    cache, workspaces, stream and event pools) is locked for a call's host
  *    work.  The workspaces are per device, so tdma_solve_partitioned,

@@ -148,6 +148,11 @@ int validate(const tdma_layout *L, const tdma_coeffs *C, int dtype, const void *
         return fail(TDMA_EINVAL, "x must not alias the coefficients");
     if (L->nsys0 < 0 || L->nsys1 < 0) return fail(TDMA_EINVAL, "negative system count");
     if (L->nsys1 > 0 && L->nsys0 > INT64_MAX / L->nsys1) return fail(TDMA_EINVAL, "nsys overflows");
+    // one workgroup at most per system and 32-bit system indices in the
+    // streaming kernels: a call takes fewer than 2^31 systems
+    if (L->nsys0 * L->nsys1 > (int64_t)0x7fffffff)
+        return fail(TDMA_EUNSUPPORTED, "%lld systems in one call (at most 2^31 - 1; split the batch)",
+                    (long long)(L->nsys0 * L->nsys1));
     if (L->offsets) {
         if (L->nsys1 != 1) return fail(TDMA_EINVAL, "ragged layout needs nsys1 == 1");
         if (C->mode != TDMA_COEF_LIKE_D)

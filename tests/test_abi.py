@@ -154,3 +154,25 @@ def test_layout_extent_overflow(tdma):
     assert lib.tdma_solve_batched(ctypes.byref(L), ctypes.byref(C), 0, ctypes.c_void_p(1),
                                   ctypes.c_void_p(2), None) == tdma.EINVAL
     assert "2^62" in lib.tdma_last_error().decode()
+
+
+def test_system_count_limit(tdma):
+    """2^31 systems or more in one call are refused on the host (no grid or
+    32-bit system index can overflow), for every entry point that takes a
+    layout."""
+    lib = tdma.lib()
+    L = tdma._Layout(8, 1 << 16, 1 << 15, 1, 0, 0, None)
+    C = tdma._Coeffs(1, 3, 4, 5, None)
+    assert lib.tdma_solve_batched(ctypes.byref(L), ctypes.byref(C), 0, ctypes.c_void_p(1),
+                                  ctypes.c_void_p(2), None) == tdma.EUNSUPPORTED
+    assert "2^31" in lib.tdma_last_error().decode()
+    assert lib.tdma_solve_multi(ctypes.byref(L), ctypes.byref(C), 0, 2, 1, ctypes.c_void_p(1),
+                                ctypes.c_void_p(2), None) == tdma.EUNSUPPORTED
+    assert lib.tdma_solve_pdd(ctypes.byref(L), ctypes.byref(C), 0, 8, ctypes.c_void_p(1),
+                              ctypes.c_void_p(2), None) == tdma.EUNSUPPORTED
+    # 2^31 - 1 systems pass the count check (the call then stops at the next
+    # host check: x aliasing a)
+    L = tdma._Layout(8, (1 << 31) - 1, 1, 1, 0, 0, None)
+    assert lib.tdma_solve_batched(ctypes.byref(L), ctypes.byref(C), 0, ctypes.c_void_p(1),
+                                  ctypes.c_void_p(3), None) == tdma.EINVAL
+    assert "alias" in lib.tdma_last_error().decode()
