@@ -155,6 +155,36 @@ int tdma_solve_pdd(const tdma_layout *layout, const tdma_coeffs *coeffs, int dty
                    int rows_per_partition, const void *d, void *x, void *stream);
 
 /*
+ * The FFT-Poisson step (the paper's Poisson solve, Sec. 5.2): for a real
+ * field q on an nx x ny x nz grid (x fastest, then y, then z; periodic in x
+ * and y), phi solves  (Dxx + Dyy + Dz) phi = q  where Dxx, Dyy are the
+ * periodic second differences whose Fourier symbols are the caller's shifts
+ * and Dz the tridiagonal z operator (a, b, c; Neumann walls make mode (0, 0)
+ * singular).  Steps: a batched real-to-complex 2-D FFT over (y, x) for every
+ * z (hipFFT), one complex tridiagonal solve per wavenumber pair
+ * (tdma_solve_multi, the real and imaginary parts as two right-hand sides,
+ * diagonal b + shift[mode]), the inverse FFT.  Mode (0, 0) is solved with its
+ * row 0 replaced by x_0 = d_0 (this fixes the additive constant).
+ * tdma_poisson_create: a, b, c are HOST arrays of nz values (a[0], c[nz-1]
+ * unused); shift is a HOST array of ny * (nx/2 + 1) values, mode (kx, ky) at
+ * ky * (nx/2 + 1) + kx (the negated modified wavenumber, so that the mode's
+ * operator is a, b + shift, c).  The plan owns two half-spectrum buffers of
+ * nz * ny * (nx/2 + 1) complex doubles and the hipFFT plans; it is made on
+ * the current device.  nz <= 1024.  Errors: EINVAL (arguments), EUNSUPPORTED
+ * (nz > 1024), ENOMEM, EHIP (hipFFT).
+ * tdma_poisson_solve: q and phi are DEVICE arrays of nx*ny*nz doubles; q may
+ * be used as scratch by the forward transform (its content afterwards is
+ * unspecified).  Stream-ordered; calls on one plan share its buffers and
+ * must be ordered by the caller.
+ * tdma_poisson_destroy: synchronises the device, then frees the plan.
+ */
+typedef struct tdma_poisson tdma_poisson;
+int tdma_poisson_create(int nx, int ny, int nz, const double *a, const double *b, const double *c,
+                        const double *shift, tdma_poisson **out);
+int tdma_poisson_solve(tdma_poisson *plan, const double *q, double *phi, void *stream);
+void tdma_poisson_destroy(tdma_poisson *plan);
+
+/*
  * tdma_solve_multi: several right-hand sides per system over one operator.
  * System k of `layout` has nrhs right-hand sides; right-hand side r has its
  * row i at element (start of system k) + i*row_stride + r*rhs_stride of d,

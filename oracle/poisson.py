@@ -13,18 +13,14 @@ returns the field.  Here, in the order the paper states it:
      plus the mode's diagonal shift; mode (0, 0), singular with Neumann walls,
      is pinned by replacing its row 0 with Phi_0 = Q_0 (a0 = c0 = 0, b0 = 1);
   3. phi = the inverse 2-D DFT (numpy.fft.irfft2, scaled by 1/(nx ny)).
-The shift of mode (kx, ky) is shift[ky * (nx // 2 + 1) + kx] (only kx <= nx/2
-exist in the half spectrum).
+The shift of mode (kx, ky) is shift_half[ky * (nx // 2 + 1) + kx] (only
+kx <= nx/2 exist in the half spectrum; the table is an input, from
+``workloads.grids.fft_half_shift``).
 """
 import numpy as np
 
 import oracle
 from workloads import configs
-
-
-def half_spectrum_shift(full_shift, nx, ny):
-    """The shifts of the half spectrum kx = 0..nx/2 from a full (ny, nx) table."""
-    return np.ascontiguousarray(full_shift.reshape(ny, nx)[:, :nx // 2 + 1]).reshape(-1)
 
 
 def poisson_fft(q, nx, ny, nz, a, b, c, shift_half, precision=oracle.F64):

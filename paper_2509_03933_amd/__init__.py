@@ -99,6 +99,10 @@ def lib():
             L.tdma_graph_destroy.restype = None
             L.tdma_autotune.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, vp, vp, i, vp]
             L.tdma_copy_streamed.argtypes = [ctypes.POINTER(_Layout), i, vp, vp, vp]
+            L.tdma_poisson_create.argtypes = [i, i, i, vp, vp, vp, vp, ctypes.POINTER(vp)]
+            L.tdma_poisson_solve.argtypes = [vp, vp, vp, vp]
+            L.tdma_poisson_destroy.argtypes = [vp]
+            L.tdma_poisson_destroy.restype = None
             L.tdma_solve_pdd.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, i, vp, vp, vp]
             L.tdma_solve_multi.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), i, i,
                                            ctypes.c_int64, vp, vp, vp]
@@ -113,6 +117,7 @@ def lib():
             L.tdma_shutdown.restype = None
             for f in ("tdma_solve_batched", "tdma_solve_batched_tiled", "tdma_solve_partitioned", "tdma_solve_refined",
                       "tdma_solve_multi", "tdma_solve_pdd", "tdma_copy_streamed",
+                      "tdma_poisson_create", "tdma_poisson_solve",
                       "tdma_graph_create", "tdma_graph_launch", "tdma_autotune", "tdma_check"):
                 getattr(L, f).restype = ctypes.c_int
             _lib = L
@@ -121,6 +126,7 @@ def lib():
 
 EXPORTED_SYMBOLS = ("tdma_solve_batched", "tdma_solve_batched_tiled", "tdma_solve_partitioned", "tdma_solve_refined",
                     "tdma_copy_streamed", "tdma_solve_multi", "tdma_solve_pdd",
+                    "tdma_poisson_create", "tdma_poisson_solve", "tdma_poisson_destroy",
                     "tdma_graph_create", "tdma_graph_launch", "tdma_graph_destroy",
                     "tdma_autotune", "tdma_autotune_last_json", "tdma_pipeline_model_ms",
                     "tdma_check", "tdma_status_string", "tdma_last_error", "tdma_shutdown")
@@ -256,6 +262,42 @@ def solve_batched_tiled(layout, coeffs, d, x, M, S, P, kernel=0, stream=None):
     _raise(lib().tdma_solve_batched_tiled(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),
                                           ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                           ctypes.byref(t), _stream_handle(stream)))
+
+
+class PoissonPlan:
+    """The FFT-Poisson step (tdma_poisson_create / _solve / _destroy).  a, b, c:
+    the z operator (nz values), shift: ny * (nx//2 + 1) values, mode (kx, ky)
+    at ky * (nx//2 + 1) + kx; host arrays (numpy)."""
+
+    def __init__(self, nx, ny, nz, a, b, c, shift):
+        arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in (a, b, c, shift)]
+        if any(v.size != nz for v in arrs[:3]) or arrs[3].size != ny * (nx // 2 + 1):
+            raise ValueError("a, b, c need nz values and shift ny * (nx // 2 + 1)")
+        self.shape = (int(nx), int(ny), int(nz))
+        h = ctypes.c_void_p()
+        _raise(lib().tdma_poisson_create(int(nx), int(ny), int(nz),
+                                         *[ctypes.c_void_p(v.ctypes.data) for v in arrs],
+                                         ctypes.byref(h)))
+        self._h = h
+
+    def solve(self, q, phi, stream=None):
+        import torch
+        nx, ny, nz = self.shape
+        for nm, t in (("q", q), ("phi", phi)):
+            _check_tensor(nm, t, nx * ny * nz, torch.float64)
+        _raise(lib().tdma_poisson_solve(self._h, ctypes.c_void_p(q.data_ptr()),
+                                        ctypes.c_void_p(phi.data_ptr()), _stream_handle(stream)))
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            lib().tdma_poisson_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def solve_pdd(layout, coeffs, d, x, rows_per_partition, stream=None):

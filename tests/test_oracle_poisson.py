@@ -28,7 +28,7 @@ def test_manufactured_field_recovered(grid):
     nx, ny, nz = grid
     dx, dy = 1.0 / nx, 1.0 / ny
     a, b, c = grids.poisson_line_coeffs(nz, 2.0)
-    shift = op.half_spectrum_shift(grids.fft_mode_shift(nx, ny, dx, dy), nx, ny)
+    shift = grids.fft_half_shift(nx, ny, dx, dy)
     rs = np.random.default_rng(nx * 100 + nz)
     phi = rs.uniform(-1, 1, nx * ny * nz)
     q = _apply(phi, nx, ny, nz, dx, dy, a, b, c)
@@ -45,7 +45,7 @@ def test_single_mode_in_single_mode_out():
     dx, dy = 1.0 / nx, 1.0 / ny
     a, b, c = grids.poisson_line_coeffs(nz, 2.0)
     full = grids.fft_mode_shift(nx, ny, dx, dy)
-    shift = op.half_spectrum_shift(full, nx, ny)
+    shift = grids.fft_half_shift(nx, ny, dx, dy)
     kx, ky = 3, 2
     i = np.arange(nx); j = np.arange(ny)
     g = np.random.default_rng(4).uniform(-1, 1, nz)

@@ -88,3 +88,10 @@ def fft_mode_shift(nx, ny, dx, dy):
     ly = (2.0 - 2.0 * np.cos(2.0 * np.pi * ky / ny)) / (dy * dy)
     lam = ly[:, None] + lx[None, :]
     return -(lam.reshape(-1))
+
+
+def fft_half_shift(nx, ny, dx, dy):
+    """``fft_mode_shift`` on the half spectrum of a real-to-complex transform
+    in x: kx = 0..nx/2, mode (kx, ky) at ky * (nx//2 + 1) + kx."""
+    full = fft_mode_shift(nx, ny, dx, dy).reshape(ny, nx)
+    return np.ascontiguousarray(full[:, :nx // 2 + 1]).reshape(-1)
