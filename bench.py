@@ -17,6 +17,9 @@ Other workloads (measurement of the remaining configurations):
   poisson_complex  the same lines with complex right-hand sides (interleaved
                re/im pairs), FP64, tdma_solve_multi with two right-hand sides
                per system; unknowns are complex unknowns (32 B each)
+  poisson_fft  the FFT-Poisson step on a 512^3 grid (periodic x, y; stretched z with
+               Neumann walls): hipFFT real-to-complex in (y, x), the complex z-lines
+               by tdma_solve_multi, inverse transform; unknowns are grid points
   sweeps       384x256x768 x->y->z ADI sweeps (half the 768x512x1536 grid per
                axis) + 10,000 ragged systems recorded into one hipGraph
                (dependent chain + independent ragged branch)
@@ -100,8 +103,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="adi",
-                    choices=["adi", "partitioned", "poisson", "poisson_complex", "sweeps", "plain",
-                             "autotune"])
+                    choices=["adi", "partitioned", "poisson", "poisson_complex", "poisson_fft", "sweeps",
+                             "plain", "autotune"])
     ap.add_argument("--grid", default=None, help="override the grid, e.g. 256,256,256")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--batch", type=int, default=0, help="partitioned: systems per batch")
@@ -433,6 +436,71 @@ def bench_poisson_complex(args):
                                    "multi_speedup": round(ms_parts / ms, 3)}}, checks
 
 
+class FieldProblem:
+    """The Poisson step's inputs for the oracle leg: the grid, the z tables,
+    the half-spectrum shifts and the host copy of q (the device generator's
+    output, which the host generator reproduces bit for bit)."""
+
+    def __init__(self, nx, ny, nz, a, b, c, shift, q):
+        self.grid, self.a, self.b, self.c, self.shift, self.q = (nx, ny, nz), a, b, c, shift, q
+
+
+def bench_poisson_fft(args):
+    import ctypes
+    import numpy as np
+    import torch
+    import paper_2509_03933_amd as tdma
+    from workloads import configs, device, grids
+    nx, ny, nz = (int(v) for v in (args.grid or "512,512,512").split(","))
+    a, b, c = grids.poisson_line_coeffs(nz, 2.0)
+    shift = grids.fft_half_shift(nx, ny, 1.0 / nx, 1.0 / ny)
+    total = nx * ny * nz
+    q0 = torch.empty(total, dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    rc = device._load().wl_uniform_d(configs.SEED_BASE + 7, total, -1, ctypes.c_void_p(q0.data_ptr()),
+                                     ctypes.c_void_p(st.cuda_stream))
+    if rc:
+        raise RuntimeError(f"device generator failed: {rc}")
+    q = q0.clone()
+    phi = torch.empty_like(q0)
+    plan = tdma.PoissonPlan(nx, ny, nz, a, b, c, shift)
+    steps = max(1, min(args.steps, 20))
+    ms = timed(lambda i: plan.solve(q, phi, stream=st), steps, min(args.warmup, 3), st)
+    # the z solve alone, on a half spectrum of the same shape (the kernel the
+    # roofline is taken on), and the transforms' share by difference
+    h = nx // 2 + 1
+    spec = torch.zeros(2 * nz * ny * h, dtype=torch.float64, device="cuda")
+    spec_x = torch.empty_like(spec)
+    lay = configs.Layout(n=nz, nsys0=h, nsys1=ny, row_stride=2 * ny * h, sys_stride0=2, sys_stride1=2 * h)
+    co = dict(mode=1, a=torch.from_numpy(a * (nx * ny)).cuda(), b=torch.from_numpy(b * (nx * ny)).cuda(),
+              c=torch.from_numpy(c * (nx * ny)).cuda(),
+              shift=torch.from_numpy(np.concatenate([[shift[1] if shift.size > 1 else -1.0], shift[1:]])
+                                     * (nx * ny)).cuda())
+    spec.copy_(torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, spec.numel())))
+    ms_z = timed(lambda i: tdma.solve_multi(lay, co, spec, spec_x, 2, 1, stream=st), steps,
+                 min(args.warmup, 3), st)
+    q.copy_(q0)
+    plan.solve(q, phi, stream=st)
+    torch.cuda.synchronize()
+    tdma.check(st)
+    fp = FieldProblem(nx, ny, nz, a, b, c, shift, q0.cpu().numpy())
+    checks = [{"path": ("max_rel_err_vs_oracle",), "kind": "field", "phi": phi.cpu().numpy(),
+               "problem": fp}]
+    plan.destroy()
+    modes_unknowns = h * ny * nz
+    return fp, {"value": round(total / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
+                "dtype": "f64", "steps": steps,
+                "config": {"workload": f"fft_poisson_step_{nx}x{ny}x{nz}", "unknowns": "grid points",
+                           "entry_point": "tdma_poisson_solve (hipFFT D2Z, tdma_solve_multi on the "
+                                          "half spectrum + pinned mode, hipFFT Z2D)"},
+                "max_rel_err_vs_oracle": None,
+                "z_solve": {"ms": round(ms_z, 6), "share": round(ms_z / ms, 4),
+                            "transforms_ms": round(ms - ms_z, 6)},
+                "roofline": roofline(32 * modes_unknowns, ms_z, "k_multi",
+                                     f"k_multi_poisson_fft{nx}x{ny}x{nz}_f64",
+                                     note="the z solve of one step (half spectrum, complex)")}, checks
+
+
 def bench_sweeps(args):
     import numpy as np
     import torch
@@ -510,6 +578,13 @@ def oracle_errors(checks):
     errs = {}
     for c in checks:
         worst = 0.0
+        if c["kind"] == "field":
+            from oracle import poisson as op
+            fp = c["problem"]
+            nx, ny, nz = fp.grid
+            ref = op.poisson_fft(fp.q, nx, ny, nz, fp.a, fp.b, fp.c, fp.shift)
+            errs[c["path"]] = rel(c["phi"], ref)
+            continue
         if c["kind"] == "systems":
             p = c["p"]
             for s, got in zip(c["systems"], c["rows"]):
@@ -557,6 +632,22 @@ def cpu_baseline(p, target_s, max_systems=None):
     import numpy as np
     import oracle
     from workloads import configs
+    if isinstance(p, FieldProblem):
+        # the oracle's FFT-Poisson step on the whole field, repeated
+        from oracle import poisson as op
+        nx, ny, nz = p.grid
+        t0 = time.perf_counter()
+        passes = 0
+        while True:
+            op.poisson_fft(p.q, nx, ny, nz, p.a, p.b, p.c, p.shift)
+            passes += 1
+            el = time.perf_counter() - t0
+            if el >= target_s or passes >= 100:
+                break
+        return {"value": round(nx * ny * nz * passes / el / 1e9, 4), "unit": "G unknowns/s",
+                "cores": 1, "kind": "oracle",
+                "sample": f"{passes} full pass(es) of the step ({nx * ny * nz} grid points), {el:.1f} s "
+                          f"wall: numpy FFTs and the C complex Thomas solve, one thread"}
     lay = p.layout
     if p.nrhs == 2:
         # complex right-hand sides: the oracle's complex Thomas solve per system
@@ -623,7 +714,7 @@ def main():
         copy_calibration()
         return
     fn = {"adi": bench_adi, "partitioned": bench_partitioned, "poisson": bench_poisson,
-          "poisson_complex": bench_poisson_complex,
+          "poisson_complex": bench_poisson_complex, "poisson_fft": bench_poisson_fft,
           "sweeps": bench_sweeps, "plain": bench_plain, "autotune": bench_autotune}[args.workload]
     p, res, checks = fn(args)
     out = {"metric": METRIC, "value": res.pop("value"), "unit": "G unknowns/s", "n_gpus": 1,
