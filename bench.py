@@ -707,7 +707,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the systems shard across GPUs with no communication; see DESIGN.md).",
+              "(the systems shard across GPUs with no communication).",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
