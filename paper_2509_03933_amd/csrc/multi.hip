@@ -229,10 +229,11 @@ inline size_t multi_lds_bytes(size_t esz, int S, int P, int M, int NR) {
 // (the 16 MB rows of 1024^2 complex modes) neighbouring tiles then fall on
 // the same memory channels, scattered ones do not.  With spread == 0 the
 // order is XCD-aware (dev::xcd_tile), for tile rows narrower than a line.
+// x may alias d: a block reads all of its tile before it writes any of it.
 template <typename T, int M, int NR, bool SHIFT, bool VEC>
 __global__ void __launch_bounds__(512)
-k_multi(SysMap map, Coef coef, const T *__restrict__ d, T *__restrict__ x, int64_t rhs_stride,
-        int S_log2, int P_log2, int64_t spread, int *err) {
+k_multi(SysMap map, Coef coef, const T *d, T *x, int64_t rhs_stride, int S_log2, int P_log2,
+        int64_t spread, int *err) {
     static_assert(!VEC || NR == 2, "vector form moves two right-hand sides");
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
