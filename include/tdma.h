@@ -175,7 +175,8 @@ int tdma_solve_pdd(const tdma_layout *layout, const tdma_coeffs *coeffs, int dty
  * tdma_poisson_solve: q and phi are DEVICE arrays of nx*ny*nz doubles; q may
  * be used as scratch by the forward transform (its content afterwards is
  * unspecified).  Stream-ordered; calls on one plan share its buffers and
- * must be ordered by the caller.
+ * must be ordered by the caller; the plan's device must be current (else
+ * EINVAL).
  * tdma_poisson_destroy: synchronises the device, then frees the plan.
  */
 typedef struct tdma_poisson tdma_poisson;

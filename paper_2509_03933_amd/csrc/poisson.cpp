@@ -112,6 +112,11 @@ int tdma_poisson_create(int nx, int ny, int nz, const double *a, const double *b
 int tdma_poisson_solve(tdma_poisson *pl, const double *q, double *phi, void *stream) {
     clear_error();
     if (!pl || !q || !phi) return fail(TDMA_EINVAL, "plan, q and phi must be non-NULL");
+    int cur = -1;
+    const hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != pl->dev)
+        return fail(TDMA_EINVAL, "the plan was made on device %d, device %d is current", pl->dev, cur);
     const hipStream_t st = (hipStream_t)stream;
     const int nz = pl->nz, h = pl->h;
     hipfftResult r = hipfftSetStream(pl->fwd, st);
