@@ -32,7 +32,7 @@ on a bounded sample of the workload, and the run's recorded GPU results are
 checked against it (the ``max_rel_err_vs_oracle`` fields; null with
 ``--no-cpu-baseline``).
 
-Prints ONE JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
+Prints ONE JSON line.  ``--gpus`` above 1 is refused: the library runs on one GPU.
 """
 import argparse
 import hashlib
@@ -706,7 +706,7 @@ def cpu_baseline(p, target_s, max_systems=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(the systems shard across GPUs with no communication).",
               file=sys.stderr)
         sys.exit(2)
