@@ -269,6 +269,36 @@ bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileS
     return found;
 }
 
+// Shared operator with a per-system shift on a strided layout (the
+// FFT-Poisson lines): M = 32 rows per lane (else 16, 8), P a power of two
+// <= 64 with P*M >= n, and S = 16 consecutive systems per tile in FP64, 32 in
+// FP32 (128-byte tile rows), as far as the lanes allow (512 for FP64 at
+// M = 32, else 1024); the rolling walk (kernel 3).  Measured on the 1024^3
+// Poisson lines in FP64: 16 x 32 partitions x 32 rows 4.8 ms, 16 x 64 x 16
+// 6.0 ms, 8 x 32 x 32 7.3 ms.
+static bool default_shift_shape(int dtype, int64_t n, int64_t nsys, TileShape *out) {
+    const int Ms[] = {32, 16, 8};
+    for (int M : Ms) {
+        int64_t P = 1;
+        while (P * M < n) P <<= 1;
+        if (P > 64) continue;
+        TileShape sh;
+        sh.kernel = 3;
+        sh.M = M;
+        sh.P = (int)P;
+        sh.contig = false;
+        const int64_t maxt = dtype == TDMA_F64 && M == 32 ? 512 : 1024;
+        int S_log2 = dtype == TDMA_F64 ? 4 : 5;
+        while (S_log2 > 0 && ((int64_t)1 << S_log2) * P > maxt) --S_log2;
+        while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= nsys) --S_log2;
+        sh.S_log2 = S_log2;
+        if (!shift_supported(dtype, sh)) continue;
+        *out = sh;
+        return true;
+    }
+    return false;
+}
+
 // Ragged layout: systems are bucketed by the power-of-two partition count
 // they need; one launch per non-empty bucket (contiguous rows, LDS-staged).
 // build_ragged_plan allocates the plan's device tables and uploads them
@@ -428,8 +458,14 @@ int launch_ragged(const RaggedPlan &rp, const tdma_layout *L, const tdma_coeffs 
 }
 
 // Whether a tile shape can run a uniform layout with these coefficients.
-static bool shape_fits(int dtype, const tdma_layout *L, bool shared_op, const TileShape &sh) {
+static bool shape_fits(int dtype, const tdma_layout *L, bool shared_op, const TileShape &sh,
+                       bool shifted_op) {
     if ((int64_t)sh.P * sh.M < L->n) return false;
+    if (sh.kernel == 3 || sh.kernel == 4) {
+        if (!shifted_op || !shift_supported(dtype, sh)) return false;
+        const SysMap m = make_map(L);
+        return shift_layout_ok(m, sh);
+    }
     if (sh.kernel == 1 || sh.kernel == 2) return shared_op && shared_supported(dtype, sh);
     if (sh.kernel != 0 || !fused_supported(dtype, sh)) return false;
     return !(sh.contig && fused_lds_bytes(dtype, sh) > 160 * 1024);
@@ -445,6 +481,7 @@ int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int
     TileShape sh;
     const bool contig = L->row_stride == 1;
     const bool shared_op = C->mode == TDMA_COEF_SHARED && C->b_shift == nullptr;
+    const bool shifted_op = C->mode == TDMA_COEF_SHARED && C->b_shift != nullptr;
     if (force) {
         sh = *force;
         if ((int64_t)sh.P * sh.M < L->n)
@@ -453,13 +490,20 @@ int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int
         if ((sh.kernel == 1 || sh.kernel == 2) && !shared_op)
             return fail(TDMA_EINVAL, "the shared-operator kernel needs shared coefficients without "
                         "a shift (M=%d P=%d S=%d)", sh.M, sh.P, 1 << sh.S_log2);
-        if (!shape_fits(dtype, L, shared_op, sh))
+        if ((sh.kernel == 3 || sh.kernel == 4) && !shifted_op)
+            return fail(TDMA_EINVAL, "the shifted-operator kernel needs shared coefficients with "
+                        "a shift (M=%d P=%d S=%d)", sh.M, sh.P, 1 << sh.S_log2);
+        if (!shape_fits(dtype, L, shared_op, sh, shifted_op))
             return fail(TDMA_EINVAL, "unsupported tile shape M=%d P=%d S=%d (kernel %d)", sh.M, sh.P,
                         1 << sh.S_log2, sh.kernel);
     } else if (!(lookup_tuned(ctx->dev, L, C, dtype, &sh) && sh.contig == contig &&
-                 shape_fits(dtype, L, shared_op, sh))) {
-        if (!(shared_op && default_shared_shape(dtype, L->n, nsys, contig, &sh)) &&
-            !default_shape(dtype, L->n, nsys, contig, &sh))
+                 shape_fits(dtype, L, shared_op, sh, shifted_op))) {
+        TileShape ssh;
+        if (shifted_op && !contig && default_shift_shape(dtype, L->n, nsys, &ssh) &&
+            shift_layout_ok(make_map(L), ssh))
+            sh = ssh;
+        else if (!(shared_op && default_shared_shape(dtype, L->n, nsys, contig, &sh)) &&
+                 !default_shape(dtype, L->n, nsys, contig, &sh))
             return fail(TDMA_EUNSUPPORTED, "n = %lld is too long for the fused path (use "
                         "tdma_solve_partitioned)", (long long)L->n);
     }
@@ -472,8 +516,13 @@ int launch_uniform(const TileShape &sh, const tdma_layout *L, const tdma_coeffs 
     const SysMap m = make_map(L);
     if (m.nsys == 0) return TDMA_OK;
     const Coef coef = make_coef(C);
-    const hipError_t e = sh.kernel != 0 ? launch_shared(dtype, m, coef, sh, d, x, err, st)
-                                        : launch_fused(dtype, m, coef, sh, d, x, err, st);
+    hipError_t e;
+    if (sh.kernel == 3 || sh.kernel == 4)
+        e = launch_shift(dtype, m, coef, sh, d, x, err, st);
+    else if (sh.kernel != 0)
+        e = launch_shared(dtype, m, coef, sh, d, x, err, st);
+    else
+        e = launch_fused(dtype, m, coef, sh, d, x, err, st);
     if (e != hipSuccess) return hip_fail(e, "fused launch");
     return TDMA_OK;
 }
@@ -555,10 +604,12 @@ int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeff
     while ((1 << sh.S_log2) < S) ++sh.S_log2;
     sh.contig = layout->row_stride == 1;
     sh.kernel = tile->kernel;
-    if (sh.kernel < 0 || sh.kernel > 2) return fail(TDMA_EINVAL, "unknown kernel %d", sh.kernel);
+    if (sh.kernel < 0 || sh.kernel > 4) return fail(TDMA_EINVAL, "unknown kernel %d", sh.kernel);
     if (sh.kernel == 0 && !fused_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported tile M=%d S=%d P=%d", sh.M, S, sh.P);
-    if (sh.kernel != 0 && !shared_supported(dtype, sh))
+    if (sh.kernel >= 3 && !shift_supported(dtype, sh))
+        return fail(TDMA_EINVAL, "unsupported shifted-operator tile M=%d S=%d P=%d", sh.M, S, sh.P);
+    if ((sh.kernel == 1 || sh.kernel == 2) && !shared_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported shared-operator tile M=%d S=%d P=%d", sh.M, S, sh.P);
     if ((int64_t)sh.M * sh.P < layout->n) return fail(TDMA_EINVAL, "tile covers %lld rows < n = %lld",
                                                       (long long)sh.M * sh.P, (long long)layout->n);

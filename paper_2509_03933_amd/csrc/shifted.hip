@@ -1,0 +1,528 @@
+// Shared operator with a per-system diagonal shift on strided layouts: the
+// FFT-Poisson z-lines of Sec. 5.2, one system per wavenumber pair, where a, b,
+// c are the stretched-grid tables shared by every mode and the diagonal of
+// mode k is b + shift[k] (shift = -lambda of the mode).
+//
+// The factors of such a system depend on its shift, so they are per system.
+// What a lane keeps per row is only its right-hand side d_j and the pivot
+// reciprocal g_j:
+//  Stage A streams the modified Thomas recurrences of tile.hip.h over the
+//    lane's M rows with O(1) running state (d^, a^, c^ of the previous row and
+//    the running products of the first-row spike) and records g_j;
+//  Stage B solves the 2P-row interface system (FP64 PCR inside wavefronts,
+//    one system per P consecutive lanes, coefficients and right-hand sides);
+//  Stage C re-solves the partition's interior rows 1..M-2 from d with the
+//    interface values x_0 and x_{M-1} as known boundary values: forward
+//    e_j = g_j (d_j - a_j e_{j-1}) from e_0 = x_0, backward
+//    x_j = e_j - g_j c_j x_{j+1} from x_{M-1}.  From row 1 on, the pivots of
+//    the modified Thomas sweep are those of plain Thomas on the interior, and
+//    e_j = d^_j - a^_j x_0, so this is the substitution x = x~ - Y y of the
+//    paper's Stage C written without the stored spike a^.
+// Two values per row instead of the three (d^, a^, c^) of the generic fused
+// kernel, so a tile of 16 FP64 systems (128-byte rows) at 32 rows per lane
+// fits 512 lanes.
+//
+// Memory pipeline (measured on the 1024^3 Poisson lines, FP64, 16 x 32 x 32
+// tiles): resident workgroups walk the tiles; each row of x is stored as soon
+// as the backward pass produces it, and the register it frees is refilled at
+// once with a row of the next tile's right-hand side, in the order the next
+// tile's Stage A reads them (so the row order in registers alternates
+// between tiles).  Loads and stores are thus spread over the pass instead of
+// issued in bursts: 4.79 ms against 5.38 ms for whole-tile loads and stores,
+// and 4.98 ms for a second register set filled during the interface solve
+// (a set filled at the start of a tile measured 6.83 ms).
+#include <type_traits>
+
+#include "tile.hip.h"
+
+namespace tdma {
+namespace {
+
+using dev::Iface;
+
+template <typename T> struct Pair2;
+template <> struct Pair2<double> { using type = double2; };
+template <> struct Pair2<float> { using type = float2; };
+
+__host__ __device__ inline size_t al16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+// LDS carve-up (byte offsets): the operator's rows per partition with a pitch
+// of M+1 rows (the partitions a wavefront reads at once then sit on different
+// banks) as pairs AB = (a_j, b_j) and CM = (c_j, m_j), where m_j is 1 on the
+// system's rows and 0 on the identity rows that pad it to P*M (the shift is
+// not added there); then the interface exchange (S systems x 2P rows x (a, c,
+// d), pitch 2P+1).
+struct ShiftLds {
+    size_t ab, cm, xc, end;
+};
+
+__host__ __device__ inline ShiftLds shift_layout(size_t esz, int M, int P, int S) {
+    ShiftLds L;
+    const size_t rows = (size_t)P * (M + 1) * 2 * esz;
+    L.ab = 0;
+    L.cm = al16(L.ab + rows);
+    L.xc = al16(L.cm + rows);
+    L.end = al16(L.xc + (size_t)3 * S * (2 * P + 1) * sizeof(double));
+    return L;
+}
+
+// System of a lane in a uniform layout (fewer than 2^31 systems) stepped by
+// a fixed number of systems without a division per step.
+struct Walk {
+    int32_t k, s0, s1, q, r;
+    __device__ void init(int32_t nsys0, int32_t k0, int32_t step) {
+        k = k0;
+        s1 = k0 / nsys0;
+        s0 = k0 - s1 * nsys0;
+        q = step / nsys0;
+        r = step - q * nsys0;
+    }
+    __device__ void advance(int32_t nsys0, int32_t step) {
+        k += step;
+        s0 += r;
+        s1 += q;
+        if (s0 >= nsys0) { s0 -= nsys0; ++s1; }
+    }
+};
+
+// The tile's operator rows into LDS (once per workgroup), identity rows past n.
+template <typename T>
+__device__ __forceinline__ void build_rows(const Coef &coef, int64_t n, int M, int P, char *base,
+                                           const ShiftLds &L) {
+    using T2 = typename Pair2<T>::type;
+    const T *A = (const T *)coef.a, *B = (const T *)coef.b, *C = (const T *)coef.c;
+    T2 *AB = reinterpret_cast<T2 *>(base + L.ab);
+    T2 *CM = reinterpret_cast<T2 *>(base + L.cm);
+    const int R = P * M;
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        const bool in = r < n;
+        const int p = r / M, j = r - p * M;
+        const int q = p * (M + 1) + j;
+        AB[q] = T2{in && r > 0 ? A[r] : T(0), in ? B[r] : T(1)};
+        CM[q] = T2{in && r < n - 1 ? C[r] : T(0), in ? T(1) : T(0)};
+    }
+    __syncthreads();
+}
+
+// One PCR elimination step on a unit-diagonal row (a, c, d) with its
+// neighbours at distance h below (al, cl, dl) and above (au, cu, du);
+// renormalised to unit diagonal.  Missing neighbours are zero rows.
+__device__ __forceinline__ void pcr_step_row(double &a, double &c, double &d, double al, double cl,
+                                             double dl, double au, double cu, double du,
+                                             bool &bad) {
+    const double beta = 1.0 - a * cl - c * au;
+    bad |= dev::bad_pivot(beta);
+    const double ib = dev::recip(beta);
+    const double na = -a * al, nc = -c * cu, nd = d - a * dl - c * du;
+    a = na * ib;
+    c = nc * ib;
+    d = nd * ib;
+}
+
+// Stage B: the interface rows of the tile's S systems go through LDS to P
+// consecutive lanes per system (P a power of two <= 64), which run the PCR
+// steps with wavefront shuffles; the solution comes back through LDS.  For
+// a distance of two rows or more, row 2p meets only the neighbours' rows 2p
+// and row 2p+1 only their rows 2p+1, so the two rows are stepped one after
+// the other, which holds half the neighbour values at a time.  Every thread
+// of the block calls it; returns X_{2p} and X_{2p+1} of the caller's system.
+__device__ __forceinline__ void shift_pcr(double *XC, int S, int s, int p, int P, int P_log2,
+                                          const Iface &f, double &x_first, double &x_last,
+                                          bool &bad) {
+    const int R2 = 2 * P;
+    const int pitch = R2 + 1;
+    double *ra = XC, *rc = XC + S * pitch, *rd = XC + 2 * S * pitch;
+    __syncthreads();   // the exchange is free (previous tile done reading it)
+    {
+        const int q = s * pitch + 2 * p;
+        ra[q] = f.fa; rc[q] = f.fc; rd[q] = f.fd;
+        ra[q + 1] = f.la; rc[q + 1] = f.lc; rd[q + 1] = f.ld;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int s2 = t >> P_log2;
+    const int p2 = t & (P - 1);
+    const int q2 = s2 * pitch + 2 * p2;
+    double a0 = ra[q2], c0 = rc[q2], d0 = rd[q2];
+    double a1 = ra[q2 + 1], c1 = rc[q2 + 1], d1 = rd[q2 + 1];
+    const int lane = t & 63;
+    {
+        // distance 1: row 2p2 meets row 2p2-1 (lane-1) and its own row 2p2+1;
+        // row 2p2+1 meets its own row 2p2 and row 2p2+2 (lane+1)
+        const bool has_lo = p2 > 0, has_hi = p2 < P - 1;
+        const int lo = has_lo ? lane - 1 : lane, hi = has_hi ? lane + 1 : lane;
+        double am = __shfl(a1, lo), cm = __shfl(c1, lo), dm = __shfl(d1, lo);
+        double ap = __shfl(a0, hi), cp = __shfl(c0, hi), dp = __shfl(d0, hi);
+        if (!has_lo) { am = 0.0; cm = 0.0; dm = 0.0; }
+        if (!has_hi) { ap = 0.0; cp = 0.0; dp = 0.0; }
+        const double oa0 = a0, oc0 = c0, od0 = d0;
+        pcr_step_row(a0, c0, d0, am, cm, dm, a1, c1, d1, bad);
+        pcr_step_row(a1, c1, d1, oa0, oc0, od0, ap, cp, dp, bad);
+    }
+    for (int h = 2; h < R2; h <<= 1) {
+        const int dl = h >> 1;          // rows 2p2+e +- h live in lanes p2 +- h/2
+        const bool has_lo = p2 >= dl, has_hi = p2 + dl < P;
+        const int lo = has_lo ? lane - dl : lane, hi = has_hi ? lane + dl : lane;
+        {
+            double la = __shfl(a0, lo), lc = __shfl(c0, lo), ld = __shfl(d0, lo);
+            double ua = __shfl(a0, hi), uc = __shfl(c0, hi), ud = __shfl(d0, hi);
+            if (!has_lo) { la = lc = ld = 0.0; }
+            if (!has_hi) { ua = uc = ud = 0.0; }
+            pcr_step_row(a0, c0, d0, la, lc, ld, ua, uc, ud, bad);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        {
+            double la = __shfl(a1, lo), lc = __shfl(c1, lo), ld = __shfl(d1, lo);
+            double ua = __shfl(a1, hi), uc = __shfl(c1, hi), ud = __shfl(d1, hi);
+            if (!has_lo) { la = lc = ld = 0.0; }
+            if (!has_hi) { ua = uc = ud = 0.0; }
+            pcr_step_row(a1, c1, d1, la, lc, ld, ua, uc, ud, bad);
+        }
+    }
+    // each lane overwrites only its own two slots: no barrier needed before
+    rd[q2] = d0;
+    rd[q2 + 1] = d1;
+    __syncthreads();
+    x_first = rd[s * pitch + 2 * p];
+    x_last = rd[s * pitch + 2 * p + 1];
+}
+
+// A value the compiler cannot see through (it is then recomputed or
+// re-read where it is used instead of being kept live from an earlier point).
+template <typename V>
+__device__ __forceinline__ V opaque(V v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Where the x rows of a lane go and, when the walk rolls on, where the next
+// tile's right-hand side rows come from.
+template <typename T>
+struct LaneIo {
+    T *x;              // row 0 of the lane's partition in x
+    const T *next;     // row 0 of the lane's partition of the next tile's d (ROLL)
+    int64_t rs;        // row stride (elements)
+    int nrow;          // rows of the partition inside the system (0..M)
+    bool valid;        // the lane's system exists (else nothing is stored)
+};
+
+// Stage A, B and C of one tile on the lane's M rows (right-hand sides in;
+// rows at or past the system's end must hold 0).  Logical row j lives in
+// register slot j, or M-1-j when FL is 1.  Each row of x is stored as soon as
+// the backward pass produces it; with ROLL the freed slot is refilled with
+// row M-1-j of the next tile (ascending order), which puts that tile in the
+// other layout (FL of the next call = 1 - FL).  Every thread of the block
+// calls it.
+template <typename T, int M, int FL, bool ROLL>
+__device__ __forceinline__ void shift_solve(const char *base, const ShiftLds &L, int S, int s,
+                                            int p, int P, int P_log2, T sh, T (&v)[M],
+                                            const LaneIo<T> &io, bool &bad) {
+    static_assert(M >= 4, "a partition needs rows 0, M-1 and an interior");
+    using T2 = typename Pair2<T>::type;
+    auto slot = [](int j) { return FL == 1 ? M - 1 - j : j; };
+    // The operator rows are the same for every tile.  Each group of four rows
+    // reads them through a row offset the compiler cannot see through, so the
+    // reads are neither hoisted out of the tile walk nor merged between Stage
+    // A and Stage C, either of which would hold them in registers (up to
+    // eight per row) across the interface solve.
+    const int q0 = p * (M + 1);
+    const T2 *AB0 = reinterpret_cast<const T2 *>(base + L.ab);
+    const T2 *CM0 = reinterpret_cast<const T2 *>(base + L.cm);
+    const T2 *AB = AB0 + opaque(q0), *CM = CM0 + opaque(q0);
+    auto rows_group = [&] {
+        const int q = opaque(q0);
+        AB = AB0 + q;
+        CM = CM0 + q;
+    };
+    double *XC = reinterpret_cast<double *>(const_cast<char *>(base) + L.xc);
+
+    // Stage A: row 0 normalised and set aside, rows 1.. eliminated with x_0
+    // as a parameter; g_j kept for the interior rows 1..M-2
+    T g[M];
+    T2 ab = AB[0], cm = CM[0];
+    T piv = ab.y + cm.y * sh;
+    bad |= dev::bad_pivot(piv);
+    T gj = dev::recip(piv);
+    const T a0 = ab.x * gj, c0 = cm.x * gj, d0 = v[slot(0)] * gj;
+    ab = AB[1];
+    cm = CM[1];
+    piv = ab.y + cm.y * sh;
+    bad |= dev::bad_pivot(piv);
+    gj = dev::recip(piv);
+    g[1] = gj;
+    T dh = v[slot(1)] * gj, ah = ab.x * gj, ch = cm.x * gj;
+    // first-row spike: x_1 = dt1 - at1 x_0 - ct1 x_{M-1} with running
+    // products pi_1 = 1, pi_{j+1} = -c^_j pi_j:  dt1 = sum_{j=1}^{M-2} pi_j d^_j,
+    // at1 = sum pi_j a^_j, ct1 = -pi_{M-1}
+    T pi = T(1), dt1 = dh, at1 = ah;
+#pragma unroll
+    for (int j = 2; j < M; ++j) {
+        if ((j & 3) == 0) rows_group();
+        ab = AB[j];
+        cm = CM[j];
+        piv = (ab.y + cm.y * sh) - ab.x * ch;
+        bad |= dev::bad_pivot(piv);
+        gj = dev::recip(piv);
+        dh = (v[slot(j)] - ab.x * dh) * gj;
+        ah = -(ab.x * gj) * ah;
+        pi = -ch * pi;
+        ch = cm.x * gj;
+        if (j <= M - 2) {
+            g[j] = gj;
+            dt1 += pi * dh;
+            at1 += pi * ah;
+        }
+        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    Iface f;
+    {
+        const double ct1 = -(double)pi;
+        const double den = 1.0 - (double)c0 * (double)at1;
+        bad |= dev::bad_pivot(den);
+        const double rho = dev::recip(den);
+        f.fa = rho * (double)a0;
+        f.fc = -rho * (double)c0 * ct1;
+        f.fd = rho * ((double)d0 - (double)c0 * (double)dt1);
+        f.la = (double)ah;
+        f.lc = (double)ch;
+        f.ld = (double)dh;
+    }
+
+    // Stage B
+    double xfd, xld;
+    shift_pcr(XC, S, s, p, P, P_log2, f, xfd, xld, bad);
+
+    // Stage C, forward: e_j in place of d_j
+    const T xf = (T)xfd;
+    T e = xf;
+#pragma unroll
+    for (int j = 1; j <= M - 2; ++j) {
+        if ((j & 3) == 1) rows_group();
+        e = (v[slot(j)] - AB[j].x * e) * g[j];
+        v[slot(j)] = e;
+        if ((j & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+    }
+    // backward: x_j, stored at once (pointer stepped just in time); with ROLL
+    // the slot takes the next tile's row M-1-j
+    T *xq = io.x + (int64_t)(M - 1) * io.rs;
+    const T *nq = io.next;
+    T xn = (T)xld;
+    if (io.valid && M - 1 < io.nrow) __builtin_nontemporal_store(xn, xq);
+    if constexpr (ROLL) v[slot(M - 1)] = __builtin_nontemporal_load(nq);
+#pragma unroll
+    for (int j = M - 2; j >= 1; --j) {
+        if (j == M - 2 || (j & 3) == 0) rows_group();
+        T xj = v[slot(j)] - (CM[j].x * g[j]) * xn;
+        // computed here, row by row: not sunk into the store's branch, where
+        // all rows' operator reads would be issued at once
+        xj = opaque(xj);
+        xq = opaque(xq - io.rs);
+        if (io.valid && j < io.nrow) __builtin_nontemporal_store(xj, xq);
+        if constexpr (ROLL) {
+            nq = opaque(nq + io.rs);
+            v[slot(j)] = __builtin_nontemporal_load(nq);
+        } else {
+            v[slot(j)] = xj;
+        }
+        xn = xj;
+        if ((j & 3) == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (io.valid && 0 < io.nrow) __builtin_nontemporal_store(xf, io.x);
+    if constexpr (ROLL)
+        v[slot(0)] = __builtin_nontemporal_load(nq + io.rs);
+    else
+        v[slot(0)] = xf;
+}
+
+// The lane's M rows of d (system base `sb` in elements, `valid` false past the
+// last system; a lane past the last system reads the start of the array).
+// The loads stop at row n-1 and the rows at or past n are zeroed.  Every
+// element is read once per solve (non-temporal hint).
+template <typename T, int M>
+__device__ __forceinline__ void load_lane(const T *d, int64_t sb, bool valid, int64_t rs, int r0,
+                                          int64_t n, T (&v)[M]) {
+    const int64_t first = r0 < n - 1 ? r0 : n - 1;
+    const int adv = (int)(n - 1 - first < M ? n - 1 - first : M);   // rows the pointer advances
+    const T *src = d + (valid ? sb : 0) + first * rs;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        v[j] = __builtin_nontemporal_load(src);
+        src += j < adv ? rs : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+        if (r0 + j >= n) v[j] = T(0);
+}
+
+// Lanes per workgroup: 1024 (up to 128 registers per lane), 512 when a
+// lane's M rows of one array fill 256 bytes (FP64 M = 32: up to 256).
+template <typename T, int M>
+constexpr int shift_max_threads() { return (int)sizeof(T) * M >= 256 ? 512 : 1024; }
+
+// Resident workgroups walk the tiles t0, t0 + G, ... (t0 = blockIdx.x, or its
+// XCD-aware image when a tile row is narrower than a 128-byte line, so that
+// tiles sharing lines run under one L2).  ROLL (P*M == n): the next tile's
+// right-hand sides are loaded row by row into the registers that Stage C
+// frees (shift_solve), alternating the register layout between tiles;
+// otherwise each tile is loaded whole at its start.
+template <typename T, int M, bool ROLL>
+__global__ void __launch_bounds__((shift_max_threads<T, M>()))
+k_shift_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int32_t ntiles,
+               int *err) {
+    extern __shared__ double lds[];
+    char *base = reinterpret_cast<char *>(lds);
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2, P = 1 << P_log2;
+    const int s = tid & (S - 1);
+    const int p = tid >> S_log2;
+    const int r0 = p * M;
+    const int64_t n = map.n, rs = map.row_stride;
+    const int32_t nsys0 = (int32_t)map.nsys0;
+    const int32_t nsys = (int32_t)map.nsys;
+    const ShiftLds L = shift_layout(sizeof(T), M, P, S);
+    const T *SH = (const T *)coef.shift;
+    const int32_t step = (int32_t)gridDim.x << S_log2;
+    int32_t t = (int32_t)((S * (int)sizeof(T) < 128) ? dev::xcd_tile(blockIdx.x, gridDim.x)
+                                                      : blockIdx.x);
+    Walk w;
+    w.init(nsys0, (t << S_log2) + s, step);
+    auto sbase = [&](const Walk &ww) {
+        return (int64_t)ww.s0 * map.sys_stride0 + (int64_t)ww.s1 * map.sys_stride1;
+    };
+    const int nrow = (int)(n - r0 < 0 ? 0 : (n - r0 > M ? M : n - r0));
+    bool bad = false;
+    build_rows<T>(coef, n, M, P, base, L);
+    T v[M];
+    int64_t b = sbase(w);
+    bool ok = w.k < nsys;
+    T sh = SH[ok ? w.k : 0];
+    load_lane<T, M>(d, b, ok, rs, r0, n, v);
+    if constexpr (ROLL) {
+        // one tile in layout F; the next tile's rows arrive in layout 1 - F
+        auto one = [&](auto layout) {
+            constexpr int F = decltype(layout)::value;
+            w.advance(nsys0, step);
+            const int64_t nb = sbase(w);
+            const bool nok = w.k < nsys;
+            const T nsh = SH[nok ? w.k : 0];   // issued before the rolled row loads
+            LaneIo<T> io;
+            io.x = x + b + (int64_t)r0 * rs;
+            io.next = d + (nok ? nb : 0) + (int64_t)r0 * rs;
+            io.rs = rs;
+            io.nrow = M;
+            io.valid = ok;
+            shift_solve<T, M, F, true>(base, L, S, s, p, P, P_log2, sh, v, io, bad);
+            b = nb;
+            ok = nok;
+            sh = nsh;
+        };
+        for (;;) {
+            one(std::integral_constant<int, 0>{});
+            t += gridDim.x;
+            if (t >= ntiles) break;
+            one(std::integral_constant<int, 1>{});
+            t += gridDim.x;
+            if (t >= ntiles) break;
+        }
+    } else {
+        for (;;) {
+            LaneIo<T> io;
+            io.x = x + b + (int64_t)r0 * rs;
+            io.next = nullptr;
+            io.rs = rs;
+            io.nrow = nrow;
+            io.valid = ok;
+            shift_solve<T, M, 0, false>(base, L, S, s, p, P, P_log2, sh, v, io, bad);
+            t += gridDim.x;
+            if (t >= ntiles) break;
+            w.advance(nsys0, step);
+            b = sbase(w);
+            ok = w.k < nsys;
+            sh = SH[ok ? w.k : 0];
+            load_lane<T, M>(d, b, ok, rs, r0, n, v);
+        }
+    }
+    if (bad) atomicOr(err, 1);
+}
+
+template <typename K>
+int64_t resident_of(K kernel, int threads, size_t lds) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess)
+        return 0;
+    return (int64_t)cus * per_cu;
+}
+
+template <typename T, int M, bool ROLL>
+hipError_t launch_t(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d, void *x,
+                    int *err, hipStream_t st) {
+    const int S = 1 << sh.S_log2;
+    const int P_log2 = __builtin_ctz((unsigned)sh.P);
+    const size_t lds = shift_layout(sizeof(T), M, sh.P, S).end;
+    const int64_t ntiles = (map.nsys + S - 1) / S;
+    if (ntiles == 0) return hipSuccess;
+    const int64_t resident = resident_of(k_shift_stream<T, M, ROLL>, sh.threads(), lds);
+    if (resident < 1) return hipErrorInvalidConfiguration;
+    const int64_t grid = ntiles < resident ? ntiles : resident;
+    hipLaunchKernelGGL((k_shift_stream<T, M, ROLL>), dim3((unsigned)grid), dim3(sh.threads()), lds,
+                       st, map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, (int32_t)ntiles, err);
+    return hipGetLastError();
+}
+
+template <typename T, int M>
+hipError_t launch_m(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d, void *x,
+                    int *err, hipStream_t st) {
+    // kernel 3 rolls the walk on when the partitions cover n exactly; kernel 4
+    // (and padded lengths) load each tile at its start
+    const bool roll = sh.kernel == 3 && (int64_t)sh.P * M == map.n;
+    return roll ? launch_t<T, M, true>(map, coef, sh, d, x, err, st)
+                : launch_t<T, M, false>(map, coef, sh, d, x, err, st);
+}
+
+}  // namespace
+
+size_t shift_lds_bytes(int dtype, const TileShape &sh) {
+    const size_t esz = dtype == TDMA_F64 ? 8 : 4;
+    return shift_layout(esz, sh.M, sh.P, 1 << sh.S_log2).end;
+}
+
+bool shift_supported(int dtype, const TileShape &sh) {
+    if (sh.kernel != 3 && sh.kernel != 4) return false;
+    if (sh.contig || sh.pdd) return false;
+    if (sh.P < 1 || sh.P > 64 || (sh.P & (sh.P - 1)) != 0) return false;
+    const int maxt = dtype == TDMA_F64 && sh.M == 32 ? 512 : 1024;
+    if (sh.S_log2 < 0 || sh.threads() > maxt || sh.threads() < 1) return false;
+    if (dtype == TDMA_F64 && sh.M != 8 && sh.M != 16 && sh.M != 32) return false;
+    if (dtype == TDMA_F32 && sh.M != 8 && sh.M != 16 && sh.M != 32) return false;
+    return shift_lds_bytes(dtype, sh) <= 160 * 1024;
+}
+
+// Uniform strided layouts whose walk stays in 32-bit system indices (a lane's
+// index reaches at most two grid strides past the last tile).
+bool shift_layout_ok(const SysMap &m, const TileShape &sh) {
+    if (m.offsets || m.sys_list || m.count || m.row_stride == 1) return false;
+    const int64_t S = (int64_t)1 << sh.S_log2;
+    const int64_t ntiles = (m.nsys + S - 1) / S;
+    return 3 * (ntiles + 1) * S < ((int64_t)1 << 31);
+}
+
+hipError_t launch_shift(int dtype, const SysMap &map, const Coef &coef, const TileShape &sh,
+                        const void *d, void *x, int *err, hipStream_t st) {
+    if (!shift_supported(dtype, sh) || !shift_layout_ok(map, sh) || coef.mode != TDMA_COEF_SHARED ||
+        coef.shift == nullptr)
+        return hipErrorInvalidValue;
+    if (dtype == TDMA_F64) {
+        if (sh.M == 8) return launch_m<double, 8>(map, coef, sh, d, x, err, st);
+        if (sh.M == 16) return launch_m<double, 16>(map, coef, sh, d, x, err, st);
+        if (sh.M == 32) return launch_m<double, 32>(map, coef, sh, d, x, err, st);
+    } else {
+        if (sh.M == 8) return launch_m<float, 8>(map, coef, sh, d, x, err, st);
+        if (sh.M == 16) return launch_m<float, 16>(map, coef, sh, d, x, err, st);
+        if (sh.M == 32) return launch_m<float, 32>(map, coef, sh, d, x, err, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tdma

@@ -36,7 +36,10 @@ struct TileShape {
     int P = 4;
     bool contig = false;    // stage loads/stores through LDS (row_stride == 1)
     int kernel = 0;         // 0: generic fused kernel, 1: shared-operator kernel,
-                            // 2: its streaming form (resident blocks walk the tiles)
+                            // 2: its streaming form (resident blocks walk the tiles),
+                            // 3: shared operator + per-system shift, streaming with the
+                            // next tile's rows loaded as Stage C frees registers, 4: the
+                            // same loading each tile at its start (shifted.hip)
     bool pdd = false;       // kernel 0 only: Stage B by the PDD approximation
     int threads() const { return (1 << S_log2) * P; }
 };
@@ -63,6 +66,13 @@ size_t shared_lds_bytes(int dtype, const TileShape &shape);
 bool copy_streamed_supported(const SysMap &map, const TileShape &shape);
 hipError_t launch_copy_streamed(int dtype, const SysMap &map, const TileShape &shape,
                                 const void *d, void *x, hipStream_t stream);
+
+// shared operator with a per-system shift, strided layouts (shifted.hip)
+bool shift_supported(int dtype, const TileShape &shape);
+bool shift_layout_ok(const SysMap &map, const TileShape &shape);
+size_t shift_lds_bytes(int dtype, const TileShape &shape);
+hipError_t launch_shift(int dtype, const SysMap &map, const Coef &coef, const TileShape &shape,
+                        const void *d, void *x, int *err_flag, hipStream_t stream);
 
 // several right-hand sides over one shared operator (multi.hip): S systems x
 // P partitions (P <= 64) x M rows per lane, one tile per block
