@@ -1,35 +1,39 @@
 """Benchmark: G unknowns/s and % of HBM roofline of the batched tridiagonal solve
 on one MI355X, beside the CPU oracle.
 
-Default workload (``--workload adi``): the ADI viscous z-sweep of a 256^3 grid
-(65,536 strided z-lines of n = 256, one shared tanh-grid operator, smooth RHS
-+ noise), FP64, through tdma_solve_batched (fused on-chip Stage A/B/C).  One
-step = one full solve of the workload.  The same workload is also timed
-through tdma_solve_refined (FP32 sweeps + FP64 refinement), reported beside
-the FP64 value.  Inputs are resident in HBM before timing; the steps cycle
-over several input/output buffer sets (>= 1 GiB in total) so the 256 MB
-Infinity Cache cannot serve a step from the previous one.
+Default workload (``--workload poisson``): the FFT-Poisson line solves of a
+1024^3 grid -- one z-system of n = 1024 per wavenumber pair (kx, ky), 2^20
+systems whose rows are 2^20 elements (8 MB) apart, a shared stretched-grid
+operator with the mode's -lambda added to the diagonal, mode (0, 0) pinned
+(x_0 = 0) and solved as its own system.  One step = the bulk solve plus the
+pinned one.  ``value`` is the FP64 path (tdma_solve_batched); the precision
+form (tdma_solve_refined: FP32 sweeps, FP64 residual and interface solve,
+FP64 fallback) is timed on the same step and reported beside it
+(``fp32_refine``).  Inputs are resident in HBM before timing (the 16 GB
+working set is far larger than the 256 MB Infinity Cache).
 
 Other workloads (measurement of the remaining configurations):
+  adi          ADI viscous z-sweep of a 256^3 grid (shared tanh-grid operator),
+               FP64 and FP32+refine, PDD leg, same-pattern copy
   partitioned  1024^3 per-row z-lines, tdma_solve_partitioned (P = 8, 4 streams)
-  poisson      1024^2 FFT modes x n = 1024, shared operator + shift, FP64 fused
-               and FP32+refine, plus the pinned (0,0) mode
-  poisson_complex  the same lines with complex right-hand sides (interleaved
+  poisson_complex  the Poisson lines with complex right-hand sides (interleaved
                re/im pairs), FP64, tdma_solve_multi with two right-hand sides
                per system; unknowns are complex unknowns (32 B each)
   poisson_fft  the FFT-Poisson step on a 512^3 grid (periodic x, y; stretched z with
                Neumann walls): hipFFT real-to-complex in (y, x), the complex z-lines
                by tdma_solve_multi, inverse transform; unknowns are grid points
-  sweeps       384x256x768 x->y->z ADI sweeps (half the 768x512x1536 grid per
-               axis) + 10,000 ragged systems recorded into one hipGraph
-               (dependent chain + independent ragged branch)
+  sweeps       768x512x1536 x->y->z ADI sweeps + 10,000 ragged systems recorded
+               into one hipGraph (dependent chain + independent ragged branch)
   plain        64 contiguous systems of n = 256
   autotune     the autotuner on the partitioned configuration (model choice
                of the batch size against brute force), then the tuned solve
 
 The oracle (``oracle/``) runs only in the cpu_baseline leg: it is timed there
-on a bounded sample of the workload, and the run's recorded GPU results are
-checked against it (the ``max_rel_err_vs_oracle`` fields; null with
+on a bounded sample of the workload on one thread and on all host threads
+this process may use (at most 16), and the run's recorded GPU results are
+checked against it (the ``max_rel_err_vs_oracle`` fields, against the FP64
+oracle; for the Poisson lines also a per-mode table of the modes with
+|kx|, |ky| <= 3 against the FP64 and the long-double oracle; null with
 ``--no-cpu-baseline``).
 
 Prints ONE JSON line.  ``--gpus`` above 1 is refused: the library runs on one GPU.
@@ -67,6 +71,7 @@ KERNEL_SOURCES = {
     "k_shared_refine": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
     "k_shared_refine_walk": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
     "k_fused": [CSRC + "fused.hip", CSRC + "fused_tile.hip.h", CSRC + "tile.hip.h"],
+    "k_shift_stream": [CSRC + "shifted.hip", CSRC + "tile.hip.h"],
     "k_refine": [CSRC + "refine.hip", CSRC + "tile.hip.h"],
     "k_multi": [CSRC + "multi.hip", CSRC + "tile.hip.h"],
     "k_stage_a": [CSRC + "partitioned.hip", CSRC + "tile.hip.h"],
@@ -102,7 +107,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="adi",
+    ap.add_argument("--workload", default="poisson",
                     choices=["adi", "partitioned", "poisson", "poisson_complex", "poisson_fft", "sweeps",
                              "plain", "autotune"])
     ap.add_argument("--grid", default=None, help="override the grid, e.g. 256,256,256")
@@ -161,11 +166,11 @@ def grab_rows(p, x_dev, systems):
     return x_dev[torch.from_numpy(idx).to(x_dev.device)].double().cpu().numpy()
 
 
-def check(path, p, systems, rows, dtype="f64", ld=False):
+def check(path, p, systems, rows, dtype="f64"):
     """An error field of the JSON line that the oracle leg fills: the GPU rows
-    of `systems` against the oracle on the same systems."""
+    of `systems` against the (FP64) oracle on the same systems."""
     return {"path": path, "kind": "systems", "p": p, "systems": systems, "rows": rows,
-            "dtype": dtype, "ld": ld}
+            "dtype": dtype}
 
 
 def sample_systems(nsys, k=254, seed=7):
@@ -279,14 +284,13 @@ def bench_partitioned(args):
     x = torch.empty_like(d)
     lay = p.layout
     st = torch.cuda.current_stream()
-    steps = max(1, min(args.steps, 10))
     ms = timed(lambda i: tdma.solve_partitioned(lay, coeffs, d, x, partitions=8, batch=args.batch,
-                                                nstreams=4, stream=st), steps, min(args.warmup, 2), st)
+                                                nstreams=4, stream=st), args.steps, args.warmup, st)
     unknowns = lay.unknowns()
     samp = sample_systems(lay.nsys, 62)
     checks = [check(("max_rel_err_vs_oracle",), p, samp, grab_rows(p, x, samp))]
     return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
-               "dtype": "f64", "steps": steps,
+               "dtype": "f64",
                "config": {"workload": f"partitioned_zlines_{nx}x{ny}x{nz}", "systems": lay.nsys,
                           "n": lay.n, "partitions": 8, "streams": 4, "batch": args.batch or "default",
                           "entry_point": "tdma_solve_partitioned"},
@@ -312,14 +316,13 @@ def bench_autotune(args):
     rec = tdma.autotune(lay, coeffs, d, x, what=2, stream=st)
     by_batch = {c["batch"]: c for c in rec["candidates"]}
     chosen = by_batch[rec["model_choice"]]["measured_ms"]
-    steps = max(1, min(args.steps, 10))
-    ms = timed(lambda i: tdma.solve_partitioned(lay, coeffs, d, x, stream=st), steps,
-               min(args.warmup, 2), st)
+    ms = timed(lambda i: tdma.solve_partitioned(lay, coeffs, d, x, stream=st), args.steps,
+               args.warmup, st)
     unknowns = lay.unknowns()
     samp = sample_systems(lay.nsys, 62)
     checks = [check(("max_rel_err_vs_oracle",), p, samp, grab_rows(p, x, samp))]
     return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
-               "dtype": "f64", "steps": steps,
+               "dtype": "f64",
                "config": {"workload": f"partitioned_zlines_{nx}x{ny}x{nz}_autotuned", "systems": lay.nsys,
                           "n": lay.n, "partitions": rec["P"],
                           "entry_point": "tdma_autotune (what = 2), then tdma_solve_partitioned"},
@@ -334,7 +337,20 @@ def bench_autotune(args):
                                     note="whole staged solve with the tuned batch")}, checks
 
 
+def low_mode_systems(nx, ny, reach=3):
+    """System indices of the modes (kx, ky) with |kx|, |ky| <= reach, (0, 0)
+    first (its result is the pinned solve's)."""
+    modes = [(kx, ky) for ky in range(-reach, reach + 1) for kx in range(-reach, reach + 1)]
+    modes.sort(key=lambda m: (m != (0, 0), abs(m[0]) + abs(m[1]), m))
+    return modes, [(kx % nx) + nx * (ky % ny) for kx, ky in modes]
+
+
 def bench_poisson(args):
+    """The FFT-Poisson line solves of a 1024^3 grid (2^20 modes x n = 1024,
+    shared stretched-grid operator + per-mode shift, mode (0, 0) pinned and
+    solved as its own system): one step = the bulk solve plus the pinned one,
+    in FP64 (tdma_solve_batched) and in the precision form
+    (tdma_solve_refined)."""
     import torch
     import paper_2509_03933_amd as tdma
     from workloads import configs, device
@@ -345,41 +361,63 @@ def bench_poisson(args):
     pco = dict(mode=1, a=torch.from_numpy(pin.a).cuda(), b=torch.from_numpy(pin.b).cuda(),
                c=torch.from_numpy(pin.c).cuda())
     x = torch.empty_like(d)
+    xr = torch.empty_like(d)
     lay = p.layout
     st = torch.cuda.current_stream()
-    steps = max(1, min(args.steps, 10))
 
     def fp64(i):
         tdma.solve_batched(lay, coeffs, d, x, stream=st)
         tdma.solve_batched(pin.layout, pco, d, x, stream=st)
 
     def refined(i):
-        tdma.solve_refined(lay, coeffs, d, x, REFINE_ITERS, REFINE_TOL, report=False, stream=st,
+        tdma.solve_refined(lay, coeffs, d, xr, REFINE_ITERS, REFINE_TOL, report=False, stream=st,
                            criterion=REFINE_CRITERION)
-        tdma.solve_refined(pin.layout, pco, d, x, REFINE_ITERS, REFINE_TOL, report=False, stream=st,
+        tdma.solve_refined(pin.layout, pco, d, xr, REFINE_ITERS, REFINE_TOL, report=False, stream=st,
                            criterion=REFINE_CRITERION)
 
     unknowns = lay.unknowns()
-    low = [(kx % nx) + nx * (ky % ny) for kx in range(-3, 4) for ky in range(-3, 4) if (kx, ky) != (0, 0)]
-    samp = sorted(set(sample_systems(lay.nsys, 30).tolist() + low) - {0})
-    ms = timed(fp64, steps, 1, st)
-    checks = [check(("max_rel_err_vs_oracle",), p, samp, grab_rows(p, x, samp), ld=True)]
-    msr = timed(refined, steps, 1, st)
-    rep = tdma.solve_refined(lay, coeffs, d, x, REFINE_ITERS, REFINE_TOL, report=True, stream=st,
-                           criterion=REFINE_CRITERION)
-    tdma.solve_refined(pin.layout, pco, d, x, REFINE_ITERS, REFINE_TOL, stream=st,
+    bytes_bulk = 16 * unknowns + 3 * 8 * lay.n + 8 * lay.nsys
+    ms = timed(fp64, args.steps, args.warmup, st)
+    # the dominant kernel alone (the bulk launch), for the roofline
+    ms_bulk = timed(lambda i: tdma.solve_batched(lay, coeffs, d, x, stream=st), args.steps, args.warmup,
+                    st)
+    fp64(0)
+    msr = timed(refined, args.steps, args.warmup, st)
+    msr_bulk = timed(lambda i: tdma.solve_refined(lay, coeffs, d, xr, REFINE_ITERS, REFINE_TOL,
+                                                  report=False, stream=st, criterion=REFINE_CRITERION),
+                     args.steps, args.warmup, st)
+    rep = tdma.solve_refined(lay, coeffs, d, xr, REFINE_ITERS, REFINE_TOL, report=True, stream=st,
+                             criterion=REFINE_CRITERION)
+    tdma.solve_refined(pin.layout, pco, d, xr, REFINE_ITERS, REFINE_TOL, stream=st,
                        criterion=REFINE_CRITERION)
-    checks.append(check(("fp32_refine", "max_rel_err_vs_oracle"), p, samp, grab_rows(p, x, samp),
-                        ld=True))
+    torch.cuda.synchronize()
+    modes, low = low_mode_systems(nx, ny)
+    samp = sorted(set(sample_systems(lay.nsys, 62).tolist()) - set(low))
+    checks = [check(("max_rel_err_vs_oracle",), p, samp, grab_rows(p, x, samp)),
+              check(("fp32_refine", "max_rel_err_vs_oracle"), p, samp, grab_rows(p, xr, samp)),
+              {"path": ("low_modes",), "kind": "modes", "p": p, "pin": pin, "modes": modes,
+               "systems": low, "rows": {"fp64": grab_rows(p, x, low), "fp32_refine": grab_rows(p, xr, low)}}]
+    kernel = "k_shift_stream"
     return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
-               "dtype": "f64", "steps": steps,
+               "dtype": "f64",
                "config": {"workload": f"fft_poisson_lines_{nx}x{ny}x{nz}", "systems": lay.nsys,
-                          "n": lay.n, "entry_point": "tdma_solve_batched (+ pinned mode)"},
+                          "n": lay.n, "coefficients": "shared stretched-grid operator + per-mode shift",
+                          "entry_point": "tdma_solve_batched (bulk) + tdma_solve_batched (pinned mode)"},
                "max_rel_err_vs_oracle": None,
-               "roofline": roofline(16 * unknowns, ms, "k_fused", f"k_fused_poisson{nx}x{ny}x{nz}_f64"),
+               "roofline": roofline(bytes_bulk, ms_bulk, kernel, f"{kernel}_poisson{nx}x{ny}x{nz}_f64",
+                                    note="bulk launch (all modes), timed alone"),
                "fp32_refine": {"value": round(unknowns / (msr * 1e-3) / 1e9, 3),
                                "ms_per_step": round(msr, 6), "max_rel_err_vs_oracle": None,
-                               "report": rep, "faster_than_fp64": msr < ms}}, checks
+                               "report": rep,
+                               "entry_point": f"tdma_solve_refined ({REFINE_ITERS} steps, tol {REFINE_TOL:g}, "
+                                              f"criterion {REFINE_CRITERION}, FP64 fallback + polish), "
+                                              f"bulk + pinned mode",
+                               "roofline": roofline(bytes_bulk, msr_bulk, "k_refine",
+                                                    f"k_refine_poisson{nx}x{ny}x{nz}_f64",
+                                                    note="bulk call (refinement kernel + fallback), "
+                                                         "timed alone"),
+                               "faster_than_fp64": msr < ms},
+               "low_modes": None}, checks
 
 
 def bench_poisson_complex(args):
@@ -399,8 +437,6 @@ def bench_poisson_complex(args):
     x = torch.empty_like(d)
     lay = p.layout
     st = torch.cuda.current_stream()
-    steps = max(1, min(args.steps, 10))
-
     def step(i):
         tdma.solve_multi(lay, coeffs, d, x, 2, 1, stream=st)
         tdma.solve_multi(pin.layout, pco, d, x, 2, 1, stream=st)
@@ -413,8 +449,8 @@ def bench_poisson_complex(args):
     unknowns = lay.unknowns()
     low = [(kx % nx) + nx * (ky % ny) for kx in range(-3, 4) for ky in range(-3, 4) if (kx, ky) != (0, 0)]
     samp = np.array(sorted(set(sample_systems(lay.nsys, 30).tolist() + low) - {0}), dtype=np.int64)
-    ms_parts = timed(per_part, steps, 1, st)
-    ms = timed(step, steps, 1, st)
+    ms_parts = timed(per_part, args.steps, args.warmup, st)
+    ms = timed(step, args.steps, args.warmup, st)
     base = (samp % lay.nsys0) * lay.sys_stride0 + (samp // lay.nsys0) * lay.sys_stride1
     idx = base[:, None] + np.arange(lay.n, dtype=np.int64)[None, :] * lay.row_stride
     ti = torch.from_numpy(idx).cuda()
@@ -422,7 +458,7 @@ def bench_poisson_complex(args):
     checks = [{"path": ("max_rel_err_vs_oracle",), "kind": "complex", "p": p, "systems": samp,
                "rows": rows}]
     return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
-               "dtype": "f64", "steps": steps,
+               "dtype": "f64",
                "config": {"workload": f"fft_poisson_lines_complex_{nx}x{ny}x{nz}", "systems": lay.nsys,
                           "n": lay.n, "right_hand_sides": "complex, interleaved (re, im)",
                           "unknowns": "complex unknowns",
@@ -464,8 +500,7 @@ def bench_poisson_fft(args):
     q = q0.clone()
     phi = torch.empty_like(q0)
     plan = tdma.PoissonPlan(nx, ny, nz, a, b, c, shift)
-    steps = max(1, min(args.steps, 20))
-    ms = timed(lambda i: plan.solve(q, phi, stream=st), steps, min(args.warmup, 3), st)
+    ms = timed(lambda i: plan.solve(q, phi, stream=st), args.steps, args.warmup, st)
     # the z solve alone, on a half spectrum of the same shape (the kernel the
     # roofline is taken on), and the transforms' share by difference
     h = nx // 2 + 1
@@ -477,8 +512,8 @@ def bench_poisson_fft(args):
               shift=torch.from_numpy(np.concatenate([[shift[1] if shift.size > 1 else -1.0], shift[1:]])
                                      * (nx * ny)).cuda())
     spec.copy_(torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, spec.numel())))
-    ms_z = timed(lambda i: tdma.solve_multi(lay, co, spec, spec_x, 2, 1, stream=st), steps,
-                 min(args.warmup, 3), st)
+    ms_z = timed(lambda i: tdma.solve_multi(lay, co, spec, spec_x, 2, 1, stream=st), args.steps,
+                 args.warmup, st)
     q.copy_(q0)
     plan.solve(q, phi, stream=st)
     torch.cuda.synchronize()
@@ -489,7 +524,7 @@ def bench_poisson_fft(args):
     plan.destroy()
     modes_unknowns = h * ny * nz
     return fp, {"value": round(total / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
-                "dtype": "f64", "steps": steps,
+                "dtype": "f64",
                 "config": {"workload": f"fft_poisson_step_{nx}x{ny}x{nz}", "unknowns": "grid points",
                            "entry_point": "tdma_poisson_solve (hipFFT D2Z, tdma_solve_multi on the "
                                           "half spectrum + pinned mode, hipFFT Z2D)"},
@@ -524,8 +559,7 @@ def bench_sweeps(args):
                            dict(layout=rg.layout, coeffs=dict(mode=0, a=dev(ra), b=dev(rb), c=dev(rc)),
                                 d=td, x=tx)])
     st = torch.cuda.current_stream()
-    steps = max(1, min(args.steps, 20))
-    ms = timed(lambda i: g.launch(st), steps, min(args.warmup, 3), st)
+    ms = timed(lambda i: g.launch(st), args.steps, args.warmup, st)
     unknowns = 3 * px.layout.unknowns() + rg.layout.unknowns()
     bytes_step = 16 * 3 * px.layout.unknowns() + 40 * rg.layout.unknowns()
     # the oracle leg chains x -> y -> z on the host from the same seeded field
@@ -538,7 +572,7 @@ def bench_sweeps(args):
                "systems": sample_systems(rg.layout.nsys, 30), "x": tx.cpu().numpy()}]
     g.destroy()
     return px, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
-                "dtype": "f64", "steps": steps,
+                "dtype": "f64",
                 "config": {"workload": f"adi_sweeps_{nx}x{ny}x{nz}_plus_10000_ragged",
                            "entry_point": "tdma_graph_launch"},
                 "max_rel_err_vs_oracle": None, "ragged_max_rel_err_vs_oracle": None,
@@ -585,31 +619,52 @@ def oracle_errors(checks):
             ref = op.poisson_fft(fp.q, nx, ny, nz, fp.a, fp.b, fp.c, fp.shift)
             errs[c["path"]] = rel(c["phi"], ref)
             continue
+        if c["kind"] == "modes":
+            # per mode: the GPU rows against the FP64 oracle and against the
+            # long-double oracle, and the FP64 oracle's own distance from the
+            # long-double one (how ill-conditioned the mode is)
+            p, pin = c["p"], c["pin"]
+            table = {"modes": [list(m) for m in c["modes"]], "oracle_vs_long_double": []}
+            for key in c["rows"]:
+                table[key + "_vs_oracle"] = []
+                table[key + "_vs_long_double"] = []
+            for i, s in enumerate(c["systems"]):
+                a, b, cc, d = configs.system_inputs(pin if c["modes"][i] == (0, 0) else p,
+                                                    0 if c["modes"][i] == (0, 0) else int(s))
+                ref = oracle.thomas(a, b, cc, d)
+                ref_ld = oracle.thomas(a, b, cc, d, oracle.LONG_DOUBLE)
+                table["oracle_vs_long_double"].append(rel(ref, ref_ld))
+                for key, rows in c["rows"].items():
+                    table[key + "_vs_oracle"].append(rel(rows[i], ref))
+                    table[key + "_vs_long_double"].append(rel(rows[i], ref_ld))
+            for key in list(table):
+                if key != "modes":
+                    table[key] = [float("%.3g" % v) for v in table[key]]
+            errs[c["path"]] = table
+            continue
         if c["kind"] == "systems":
             p = c["p"]
             for s, got in zip(c["systems"], c["rows"]):
+                # FP32 results too against the oracle on the FP64 inputs (the
+                # error then includes that of rounding the inputs)
                 a, b, cc, d = configs.system_inputs(p, int(s))
-                if c["dtype"] == "f32":
-                    a, b, cc, d = [v.astype(np.float32).astype(np.float64) for v in (a, b, cc, d)]
-                e = rel(got, oracle.thomas(a, b, cc, d))
-                if c["ld"] and e > 1e-12:   # ill-conditioned: the long-double oracle decides
-                    e = min(e, rel(got, oracle.thomas(a, b, cc, d, oracle.LONG_DOUBLE)))
-                worst = max(worst, e)
+                worst = max(worst, rel(got, oracle.thomas(a, b, cc, d)))
         elif c["kind"] == "pdd":
             p = c["p"]
             for s, got in zip(c["systems"], c["rows"]):
                 a, b, cc, d = configs.system_inputs(p, int(s))
                 worst = max(worst, rel(got, oracle.pdd(a, b, cc, d, c["m"])))
         elif c["kind"] == "complex":
+            # against the FP64 oracle; the long-double oracle's figure beside
             p = c["p"]
+            worst_ld = 0.0
             for s, got in zip(c["systems"], c["rows"]):
                 re, im = configs.system_rhs(p, int(s))
                 b = p.b + p.shift[int(s)]
-                e = rel(got, oracle.thomas_complex(p.a, b, p.c, re + 1j * im))
-                if e > 1e-12:   # ill-conditioned: the long-double oracle decides
-                    e = min(e, rel(got, oracle.thomas_complex(p.a, b, p.c, re + 1j * im,
-                                                              oracle.LONG_DOUBLE)))
-                worst = max(worst, e)
+                worst = max(worst, rel(got, oracle.thomas_complex(p.a, b, p.c, re + 1j * im)))
+                worst_ld = max(worst_ld, rel(got, oracle.thomas_complex(p.a, b, p.c, re + 1j * im,
+                                                                        oracle.LONG_DOUBLE)))
+            errs[c["path"][:-1] + ("max_rel_err_vs_long_double",)] = worst_ld
         elif c["kind"] == "ragged":
             p = c["p"]
             for s in c["systems"]:
@@ -625,25 +680,66 @@ def oracle_errors(checks):
     return errs
 
 
+def host_threads():
+    """Host threads the oracle leg uses: the CPUs this process may run on,
+    at most 16 (a one-GPU machine's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def timed_passes(fn, target_s, max_passes=1000):
+    t0 = time.perf_counter()
+    passes = 0
+    while True:
+        fn()
+        passes += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or passes >= max_passes:
+            return passes, el
+
+
+def packed_sample(p, k):
+    """The first k systems of a uniform real problem packed contiguously
+    (system s at s*n) with their coefficients, for timing the oracle on the
+    arithmetic alone: (layout, mode, a, b, c, d, shift)."""
+    import numpy as np
+    from workloads import configs
+    lay = p.layout
+    s = np.arange(k, dtype=np.int64)
+    base = (s % lay.nsys0) * lay.sys_stride0 + (s // lay.nsys0) * lay.sys_stride1
+    rows = (base[:, None] + np.arange(lay.n, dtype=np.int64)[None, :] * lay.row_stride).ravel()
+    i = np.tile(np.arange(lay.n, dtype=np.int64), k)
+    packed = configs.Layout(n=lay.n, nsys0=k, nsys1=1, row_stride=1, sys_stride0=lay.n, sys_stride1=0)
+    if p.mode == configs.MODE_LIKE_D:
+        a, b, c, d = configs.element_values(p, rows, i, lay.n)
+        return packed, p.mode, a, b, c, d, None
+    _, _, _, d = configs.element_values(p, rows, None, lay.n)
+    shift = None if p.shift is None else np.ascontiguousarray(p.shift[:k])
+    return packed, p.mode, p.a, p.b, p.c, d, shift
+
+
 def cpu_baseline(p, target_s, max_systems=None):
-    """The oracle (plain C FP64 Thomas, one thread) on the same workload's host
-    inputs: whole passes when they are small, else a bounded slice of the
-    systems, repeated until about target_s of CPU time."""
+    """The oracle (plain C FP64 Thomas) on the same workload's host inputs,
+    timed on one thread and on all the host threads this process may use
+    (systems split evenly, one oracle call per thread: the calls release the
+    interpreter lock): whole passes when the workload is small, else the
+    first systems packed contiguously (the arithmetic alone), repeated until
+    about target_s/2 of wall time each."""
+    import concurrent.futures as cf
     import numpy as np
     import oracle
     from workloads import configs
+    nthr = host_threads()
     if isinstance(p, FieldProblem):
-        # the oracle's FFT-Poisson step on the whole field, repeated
+        # the oracle's FFT-Poisson step on the whole field (numpy transforms:
+        # one thread), repeated
         from oracle import poisson as op
         nx, ny, nz = p.grid
-        t0 = time.perf_counter()
-        passes = 0
-        while True:
-            op.poisson_fft(p.q, nx, ny, nz, p.a, p.b, p.c, p.shift)
-            passes += 1
-            el = time.perf_counter() - t0
-            if el >= target_s or passes >= 100:
-                break
+        passes, el = timed_passes(lambda: op.poisson_fft(p.q, nx, ny, nz, p.a, p.b, p.c, p.shift),
+                                  target_s, 100)
         return {"value": round(nx * ny * nz * passes / el / 1e9, 4), "unit": "G unknowns/s",
                 "cores": 1, "kind": "oracle",
                 "sample": f"{passes} full pass(es) of the step ({nx * ny * nz} grid points), {el:.1f} s "
@@ -651,56 +747,52 @@ def cpu_baseline(p, target_s, max_systems=None):
     lay = p.layout
     if p.nrhs == 2:
         # complex right-hand sides: the oracle's complex Thomas solve per system
-        k = max_systems or 1024
-        systems = []
-        for s in range(k):
-            re, im = configs.system_rhs(p, s)
-            b = p.b + (p.shift[s] if p.shift is not None else 0.0)
-            systems.append((p.a, b, p.c, re + 1j * im))
-        t0 = time.perf_counter()
-        passes = 0
-        while True:
-            for a, b, c, d in systems:
-                oracle.thomas_complex(a, b, c, d)
-            passes += 1
-            el = time.perf_counter() - t0
-            if el >= target_s or passes >= 1000:
-                break
-        unknowns = k * lay.n * passes
-        return {"value": round(unknowns / el / 1e9, 4), "unit": "G complex unknowns/s", "cores": 1,
-                "kind": "oracle",
-                "sample": f"the first {k} systems of the workload, {passes} pass(es), {el:.1f} s "
-                          f"wall, single-threaded C complex Thomas (FP64)"}
-    if lay.extent() <= (1 << 25):
+        k = min(lay.nsys, max_systems or 16384)
+        s = np.arange(k, dtype=np.int64)
+        base = (s % lay.nsys0) * lay.sys_stride0 + (s // lay.nsys0) * lay.sys_stride1
+        rows = base[:, None] + np.arange(lay.n, dtype=np.int64)[None, :] * lay.row_stride
+        _, _, _, re = configs.element_values(p, rows.ravel(), None, lay.n)
+        _, _, _, im = configs.element_values(p, rows.ravel() + p.rhs_stride, None, lay.n)
+        dz = (re + 1j * im)
+        packed = configs.Layout(n=lay.n, nsys0=k, nsys1=1, row_stride=1, sys_stride0=lay.n,
+                                sys_stride1=0)
+        shift = None if p.shift is None else np.ascontiguousarray(p.shift[:k])
+        xz = np.zeros_like(dz)
+        run = lambda beg, end: oracle.solve_batch_complex(packed, p.a, p.b, p.c, dz, shift=shift,
+                                                          systems=(beg, end), x=xz)
+        unit, what = "G complex unknowns/s", "C complex Thomas (FP64)"
+        unknowns_pass = k * lay.n
+        sample = f"the first {k} systems of the workload packed contiguously"
+    elif lay.ragged or lay.extent() <= (1 << 25):
         a, b, c, d = configs.full_arrays(p)
-        x = None
-        t0 = time.perf_counter()
-        passes = 0
-        while True:
-            x = oracle.solve_batch(lay, p.mode, a, b, c, d, x=x)
-            passes += 1
-            el = time.perf_counter() - t0
-            if el >= target_s or passes >= 1000:
-                break
-        unknowns = lay.unknowns() * passes
-        sample = f"{passes} full pass(es) of the workload ({lay.unknowns()} unknowns each)"
+        xs = np.zeros_like(d)
+        k = lay.nsys
+        run = lambda beg, end: oracle.solve_batch(lay, p.mode, a, b, c, d, shift=p.shift,
+                                                  systems=(beg, end), x=xs)
+        unit, what = "G unknowns/s", "C Thomas (FP64)"
+        unknowns_pass = lay.unknowns()
+        sample = f"whole passes of the workload ({lay.unknowns()} unknowns each, its own layout)"
     else:
-        k = max_systems or 2048
-        systems = [configs.system_inputs(p, int(s)) for s in range(k)]
-        t0 = time.perf_counter()
-        passes = 0
-        while True:
-            for a, b, c, d in systems:
-                oracle.thomas(a, b, c, d)
-            passes += 1
-            el = time.perf_counter() - t0
-            if el >= target_s or passes >= 1000:
-                break
-        unknowns = k * lay.n * passes
-        sample = f"the first {k} systems of the workload, {passes} pass(es)"
-    return {"value": round(unknowns / el / 1e9, 4), "unit": "G unknowns/s", "cores": 1,
+        k = min(lay.nsys, max_systems or 65536)
+        packed, mode, a, b, c, d, shift = packed_sample(p, k)
+        xs = np.zeros_like(d)
+        run = lambda beg, end: oracle.solve_batch(packed, mode, a, b, c, d, shift=shift,
+                                                  systems=(beg, end), x=xs)
+        unit, what = "G unknowns/s", "C Thomas (FP64)"
+        unknowns_pass = k * lay.n
+        sample = f"the first {k} systems of the workload ({k * lay.n} unknowns) packed contiguously"
+    passes1, el1 = timed_passes(lambda: run(0, k), target_s / 2)
+    cuts = [k * i // nthr for i in range(nthr + 1)]
+    with cf.ThreadPoolExecutor(nthr) as ex:
+        def all_threads():
+            list(ex.map(lambda i: run(cuts[i], cuts[i + 1]), range(nthr)))
+        passesn, eln = timed_passes(all_threads, target_s / 2)
+    return {"value": round(unknowns_pass * passesn / eln / 1e9, 4), "unit": unit, "cores": nthr,
             "kind": "oracle",
-            "sample": f"{sample}, {el:.1f} s wall, single-threaded C Thomas (FP64)"}
+            "sample": f"{sample}: {passesn} pass(es) in {eln:.1f} s wall on {nthr} threads (systems "
+                      f"split evenly); one thread: {passes1} pass(es) in {el1:.1f} s; {what}",
+            "single_thread": {"value": round(unknowns_pass * passes1 / el1 / 1e9, 4), "unit": unit,
+                              "cores": 1}}
 
 
 def main():
