@@ -52,10 +52,14 @@ if ROOT not in sys.path:
 
 METRIC = "G unknowns/s & % HBM peak: FP32+refine vs FP64 at ≤1e-12 rel err, 1 GPU"
 # Precision form at the metric's error bar: two refinement steps, a system
-# converged when its last correction is <= 1e-12 of its solution (else the
-# FP64 fallback takes it); the error against the oracle is reported beside.
+# accepted when the error its convergence predicts is <= 1e-13 of its solution
+# (else the FP64 fallback takes it); the error against the oracle is reported
+# beside.  The tolerance sits a decade under the 1e-12 bar because the
+# prediction is an estimate: at tol 1e-12 a low Poisson mode was accepted at
+# 1.1e-12 (1024^3 lines; at 1e-13: 719 of 2^20 systems fall back, worst
+# error 2.7e-13, 11.7 against 11.6 ms).
 REFINE_ITERS = 2
-REFINE_TOL = 1e-12
+REFINE_TOL = 1e-13
 # convergence judged by the remaining error the contraction between the two
 # refinement corrections predicts (slowly but steadily converging systems
 # then stay out of the FP64 fallback)

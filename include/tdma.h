@@ -277,7 +277,9 @@ int tdma_solve_partitioned(const tdma_layout *layout, const tdma_coeffs *coeffs,
  *             q = max|dx_k| / max|dx_{k-1}| (q >= 1 never converges); it
  *             needs max_iters >= 2 and is criterion 0 below that.  It keeps
  *             systems that converge slowly but steadily (ill-conditioned
- *             ones) out of the FP64 fallback.
+ *             ones) out of the FP64 fallback.  The ratio is an estimate:
+ *             for a bar B on the error, tol = B/10 keeps a margin (at
+ *             tol = B a Poisson mode was accepted at 1.02 B).
  */
 typedef struct tdma_refine_opts {
     int max_iters;

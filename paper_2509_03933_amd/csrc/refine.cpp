@@ -67,6 +67,31 @@ static bool default_shared_refine_shape(int64_t n, int64_t nsys, bool contig, Ti
     return false;
 }
 
+// Shared operator with a per-system shift on a strided layout (the FFT-Poisson
+// lines): M = 32 rows per lane (else 16), P a power of two <= 64 with
+// P*M >= n, S = 16 consecutive systems (128-byte FP64 rows) as far as the
+// lanes allow (512 at M = 32, else 1024).
+static bool default_shift_refine_shape(const SysMap &map, TileShape *out) {
+    for (int M : {32, 16}) {
+        int64_t P = 1;
+        while (P * M < map.n) P <<= 1;
+        if (P > 64) continue;
+        TileShape sh;
+        sh.M = M;
+        sh.P = (int)P;
+        sh.contig = false;
+        int S_log2 = 4;
+        const int64_t maxt = M == 32 ? 512 : 1024;
+        while (S_log2 > 0 && ((int64_t)1 << S_log2) * P > maxt) --S_log2;
+        while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= map.nsys) --S_log2;
+        sh.S_log2 = S_log2;
+        if (!shift_refine_supported(map, sh)) continue;
+        *out = sh;
+        return true;
+    }
+    return false;
+}
+
 }  // namespace tdma
 
 using namespace tdma;
@@ -113,6 +138,9 @@ extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *
     if (coeffs->mode == TDMA_COEF_SHARED && coeffs->b_shift == nullptr &&
         default_shared_refine_shape(layout->n, nsys, layout->row_stride == 1, &ssh))
         e = launch_shared_refine(map, coef, ssh, d, x, iters, tol, state, st);
+    else if (coeffs->mode == TDMA_COEF_SHARED && coeffs->b_shift != nullptr &&
+             layout->row_stride != 1 && default_shift_refine_shape(map, &ssh))
+        e = launch_shift_refine(map, coef, ssh, d, x, iters, tol, state, st);
     else
         e = launch_refine(map, coef, sh, d, x, iters, tol, state, st);
     if (e != hipSuccess) return hip_fail(e, "refine launch");

@@ -70,6 +70,12 @@ hipError_t launch_polish(const SysMap &map, const Coef &coef, const double *d, d
                          const int32_t *list, const unsigned long long *count, int64_t capacity,
                          int steps, hipStream_t st);
 
+// shared operator + per-system shift, strided layouts (shifted.hip)
+bool shift_refine_supported(const SysMap &map, const TileShape &sh);
+hipError_t launch_shift_refine(const SysMap &map, const Coef &coef, const TileShape &sh,
+                               const double *d, double *x, int iters, double tol,
+                               RefineState *state, hipStream_t st);
+
 // shared-operator variant (shared.hip)
 size_t shared_refine_lds_bytes(const TileShape &sh);
 bool shared_refine_supported(const TileShape &sh);

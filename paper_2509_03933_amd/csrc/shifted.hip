@@ -33,6 +33,7 @@
 // (a set filled at the start of a tile measured 6.83 ms).
 #include <type_traits>
 
+#include "refine.h"
 #include "tile.hip.h"
 
 namespace tdma {
@@ -196,11 +197,16 @@ __device__ __forceinline__ V opaque(V v) {
 }
 
 // Where the x rows of a lane go and, when the walk rolls on, where the next
-// tile's right-hand side rows come from.
+// tile's right-hand side rows come from.  Addresses are the kernel's array
+// arguments plus element offsets: stepped through opaque() as integers, the
+// accesses stay global-memory instructions (an opaque pointer would be a
+// generic one, whose flat accesses also count against the LDS wait counter).
 template <typename T>
 struct LaneIo {
-    T *x;              // row 0 of the lane's partition in x
-    const T *next;     // row 0 of the lane's partition of the next tile's d (ROLL)
+    T *x;              // the x array
+    const T *d;        // the d array (ROLL)
+    int64_t xo;        // row 0 of the lane's partition in x (elements)
+    int64_t no;        // row 0 of the lane's partition of the next tile in d (ROLL)
     int64_t rs;        // row stride (elements)
     int nrow;          // rows of the partition inside the system (0..M)
     bool valid;        // the lane's system exists (else nothing is stored)
@@ -302,13 +308,13 @@ __device__ __forceinline__ void shift_solve(const char *base, const ShiftLds &L,
         v[slot(j)] = e;
         if ((j & 3) == 0) __builtin_amdgcn_sched_barrier(0);
     }
-    // backward: x_j, stored at once (pointer stepped just in time); with ROLL
+    // backward: x_j, stored at once (offset stepped just in time); with ROLL
     // the slot takes the next tile's row M-1-j
-    T *xq = io.x + (int64_t)(M - 1) * io.rs;
-    const T *nq = io.next;
+    int64_t xo = io.xo + (int64_t)(M - 1) * io.rs;
+    int64_t no = io.no;
     T xn = (T)xld;
-    if (io.valid && M - 1 < io.nrow) __builtin_nontemporal_store(xn, xq);
-    if constexpr (ROLL) v[slot(M - 1)] = __builtin_nontemporal_load(nq);
+    if (io.valid && M - 1 < io.nrow) __builtin_nontemporal_store(xn, io.x + xo);
+    if constexpr (ROLL) v[slot(M - 1)] = __builtin_nontemporal_load(io.d + no);
 #pragma unroll
     for (int j = M - 2; j >= 1; --j) {
         if (j == M - 2 || (j & 3) == 0) rows_group();
@@ -316,20 +322,20 @@ __device__ __forceinline__ void shift_solve(const char *base, const ShiftLds &L,
         // computed here, row by row: not sunk into the store's branch, where
         // all rows' operator reads would be issued at once
         xj = opaque(xj);
-        xq = opaque(xq - io.rs);
-        if (io.valid && j < io.nrow) __builtin_nontemporal_store(xj, xq);
+        xo = opaque(xo - io.rs);
+        if (io.valid && j < io.nrow) __builtin_nontemporal_store(xj, io.x + xo);
         if constexpr (ROLL) {
-            nq = opaque(nq + io.rs);
-            v[slot(j)] = __builtin_nontemporal_load(nq);
+            no = opaque(no + io.rs);
+            v[slot(j)] = __builtin_nontemporal_load(io.d + no);
         } else {
             v[slot(j)] = xj;
         }
         xn = xj;
         if ((j & 3) == 1) __builtin_amdgcn_sched_barrier(0);
     }
-    if (io.valid && 0 < io.nrow) __builtin_nontemporal_store(xf, io.x);
+    if (io.valid && 0 < io.nrow) __builtin_nontemporal_store(xf, io.x + io.xo);
     if constexpr (ROLL)
-        v[slot(0)] = __builtin_nontemporal_load(nq + io.rs);
+        v[slot(0)] = __builtin_nontemporal_load(io.d + (no + io.rs));
     else
         v[slot(0)] = xf;
 }
@@ -406,8 +412,10 @@ k_shift_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, 
             const bool nok = w.k < nsys;
             const T nsh = SH[nok ? w.k : 0];   // issued before the rolled row loads
             LaneIo<T> io;
-            io.x = x + b + (int64_t)r0 * rs;
-            io.next = d + (nok ? nb : 0) + (int64_t)r0 * rs;
+            io.x = x;
+            io.d = d;
+            io.xo = b + (int64_t)r0 * rs;
+            io.no = (nok ? nb : 0) + (int64_t)r0 * rs;
             io.rs = rs;
             io.nrow = M;
             io.valid = ok;
@@ -427,8 +435,10 @@ k_shift_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, 
     } else {
         for (;;) {
             LaneIo<T> io;
-            io.x = x + b + (int64_t)r0 * rs;
-            io.next = nullptr;
+            io.x = x;
+            io.d = d;
+            io.xo = b + (int64_t)r0 * rs;
+            io.no = 0;
             io.rs = rs;
             io.nrow = nrow;
             io.valid = ok;
@@ -443,6 +453,329 @@ k_shift_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, 
         }
     }
     if (bad) atomicOr(err, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Precision form on the shifted operator: FP64 d and x per row, FP32 pivot
+// reciprocals g32 and an FP32 work row; per tile
+//   x = 0, r = d;  repeat 1 + iters times:
+//     solve A e = r with FP32 sweeps (Stage A / C in FP32, the interface
+//     system in FP64), x += e, r = d - A x (FP64, operator rows from LDS);
+// the FP32 pivots and the interface coefficients are built by the first
+// solve and kept; later solves run only the right-hand-side recurrences of
+// Stage A.  A system's convergence is judged from its last two corrections
+// (refine_ratio) and the systems that miss tol are listed for the FP64
+// fallback.  Registers per row: 2 + 2 (d, x) + 1 + 1 (g32, work).
+
+// Second LDS part of the refinement, after the FP64 layout: FP32 copies of
+// the operator rows (a, b, c, m per row, pitch M+1 per partition), then the
+// lanes' FP32 pivot reciprocals (M rows x S*P lanes, lane-contiguous: the
+// registers they would take are what the FP64 d and x need).
+__host__ __device__ inline size_t shift_refine_lds(int M, int P, int S, size_t *f32_off,
+                                                   size_t *g_off = nullptr) {
+    const ShiftLds L = shift_layout(sizeof(double), M, P, S);
+    *f32_off = L.end;
+    const size_t g = al16(L.end + (size_t)P * (M + 1) * 4 * sizeof(float));
+    if (g_off) *g_off = g;
+    return al16(g + (size_t)M * S * P * sizeof(float));
+}
+
+template <int M>
+__device__ __forceinline__ double shift_refine_tile(const char *base, const ShiftLds &L,
+                                                    const float4 *R32, float *G, int S, int s, int p, int P,
+                                                    int P_log2, double sh, const double (&dv)[M],
+                                                    double (&xv)[M], int iters, double tol,
+                                                    bool valid, int64_t sys_id, RefineState *state) {
+    const int tid = threadIdx.x;
+    // operator rows through offsets the compiler cannot see through, renewed
+    // every four rows (see shift_solve): the rows are the same in every pass
+    // and every tile, and hoisted reads would hold them all in registers
+    const int q0 = p * (M + 1);
+    const double2 *AB0 = reinterpret_cast<const double2 *>(base + L.ab);
+    const double2 *CM0 = reinterpret_cast<const double2 *>(base + L.cm);
+    const double2 *AB = AB0 + opaque(q0), *CM = CM0 + opaque(q0);
+    const float4 *R4 = R32 + opaque(q0);
+    auto rows_group = [&] {
+        const int q = opaque(q0);
+        AB = AB0 + q;
+        CM = CM0 + q;
+        R4 = R32 + q;
+    };
+    double *XC = reinterpret_cast<double *>(const_cast<char *>(base) + L.xc);
+    const int pitch = 2 * P + 1;
+    const float shf = (float)sh;
+    bool bad = false;
+    float e[M];
+    // this lane's pivot reciprocals in LDS: row j at G[j * lanes]
+    float *GL = G + tid;
+    const int lanes = (int)blockDim.x;
+    auto gput = [&](int j, float v) { GL[j * lanes] = v; };
+    auto gget = [&](int j) { return GL[j * lanes]; };
+    // interface coefficients and first-row factors of the FP32 factorisation
+    double fa = 0.0, fc = 0.0, la = 0.0, lc = 0.0, rho = 0.0;
+    float g0 = 0.0f, c0h = 0.0f;
+    float ecur = 0.0f, eprev = 0.0f;   // largest entry of the last two corrections
+#pragma unroll
+    for (int j = 0; j < M; ++j) xv[j] = 0.0;
+    for (int it = 0; it <= iters; ++it) {
+        if (it == 0) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) e[j] = (float)dv[j];
+        } else {
+            // r = d - A x in FP64; the neighbours' outer rows through the exchange
+            __syncthreads();
+            XC[s * pitch + 2 * p] = xv[0];
+            XC[s * pitch + 2 * p + 1] = xv[M - 1];
+            __syncthreads();
+            const double xlo = p > 0 ? XC[s * pitch + 2 * p - 1] : 0.0;
+            const double xhi = p < P - 1 ? XC[s * pitch + 2 * p + 2] : 0.0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if ((j & 3) == 0) rows_group();
+                const double2 ab = AB[j], cm = CM[j];
+                const double xm = j == 0 ? xlo : xv[j > 0 ? j - 1 : 0];
+                const double xp = j == M - 1 ? xhi : xv[j < M - 1 ? j + 1 : M - 1];
+                e[j] = (float)(dv[j] - ab.x * xm - (ab.y + cm.y * sh) * xv[j] - cm.x * xp);
+                if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // Stage A (FP32): on the first pass the factorisation and the
+        // interface coefficients, then the right-hand-side recurrences only
+        const float r0v = e[0];
+        float dh, dt1, pi = 1.0f;
+        rows_group();
+        if (it == 0) {
+            float4 q = R4[0];
+            float piv = q.y + q.w * shf;
+            bad |= dev::bad_pivot(piv);
+            g0 = dev::recip(piv);
+            const float a0h = q.x * g0;
+            c0h = q.z * g0;
+            q = R4[1];
+            piv = q.y + q.w * shf;
+            bad |= dev::bad_pivot(piv);
+            float gj = dev::recip(piv);
+            gput(1, gj);
+            dh = e[1] * gj;
+            float ah = q.x * gj, ch = q.z * gj;
+            float at1 = ah;
+            dt1 = dh;
+#pragma unroll
+            for (int j = 2; j < M; ++j) {
+                if ((j & 3) == 0) rows_group();
+                q = R4[j];
+                piv = (q.y + q.w * shf) - q.x * ch;
+                bad |= dev::bad_pivot(piv);
+                gj = dev::recip(piv);
+                gput(j, gj);
+                dh = (e[j] - q.x * dh) * gj;
+                ah = -(q.x * gj) * ah;
+                pi = -ch * pi;
+                ch = q.z * gj;
+                if (j <= M - 2) {
+                    dt1 += pi * dh;
+                    at1 += pi * ah;
+                }
+                if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+            const double den = 1.0 - (double)c0h * (double)at1;
+            bad |= dev::bad_pivot(den);
+            rho = dev::recip(den);
+            fa = rho * (double)a0h;
+            fc = rho * (double)c0h * (double)pi;   // -rho c^_0 ct1, ct1 = -pi_{M-1}
+            la = (double)ah;
+            lc = (double)ch;
+        } else {
+            const float g1 = gget(1);
+            dh = e[1] * g1;
+            dt1 = dh;
+            float ch = R4[1].z * g1;
+#pragma unroll
+            for (int j = 2; j < M; ++j) {
+                if ((j & 3) == 0) rows_group();
+                const float4 q = R4[j];
+                const float gj = gget(j);
+                dh = (e[j] - q.x * dh) * gj;
+                pi = -ch * pi;
+                ch = q.z * gj;
+                if (j <= M - 2) dt1 += pi * dh;
+                if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        Iface f;
+        f.fa = fa;
+        f.fc = fc;
+        f.fd = rho * ((double)(r0v * g0) - (double)c0h * (double)dt1);
+        f.la = la;
+        f.lc = lc;
+        f.ld = (double)dh;
+        double xf, xl;
+        shift_pcr(XC, S, s, p, P, P_log2, f, xf, xl, bad);
+        // Stage C (FP32) on the correction, added to x in FP64
+        const float xff = (float)xf;
+        float ee = xff;
+#pragma unroll
+        for (int j = 1; j <= M - 2; ++j) {
+            if ((j & 3) == 1) rows_group();
+            ee = (e[j] - R4[j].x * ee) * gget(j);
+            e[j] = ee;
+            if ((j & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+        }
+        e[M - 1] = (float)xl;
+#pragma unroll
+        for (int j = M - 2; j >= 1; --j) {
+            if (j == M - 2 || (j & 3) == 0) rows_group();
+            e[j] = e[j] - (R4[j].z * gget(j)) * e[j + 1];
+            if ((j & 3) == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        e[0] = xff;
+        eprev = ecur;
+        ecur = 0.0f;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            xv[j] += (double)e[j];
+            ecur = fmaxf(ecur, fabsf(e[j]));
+        }
+    }
+    // convergence per system: the maxima over its P partitions (adjacent
+    // lanes after the exchange, butterfly shuffles); the lane of partition 0
+    // judges, misses go to the fallback list
+    double xmax = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) xmax = fmax(xmax, fabs(xv[j]));
+    if (bad) ecur = __builtin_huge_valf();
+    __syncthreads();
+    XC[s * pitch + 2 * p] = pack_e(ecur, eprev);
+    XC[s * pitch + 2 * p + 1] = xmax;
+    if (p == 0) XC[s * pitch + 2 * P] = __longlong_as_double(valid ? (long long)sys_id : -1ll);
+    __syncthreads();
+    double rel = 0.0;
+    {
+        const int s2 = tid >> P_log2, p2 = tid & (P - 1);
+        float em, ep;
+        unpack_e(XC[s2 * pitch + 2 * p2], em, ep);
+        double xm = XC[s2 * pitch + 2 * p2 + 1];
+        for (int off = P >> 1; off >= 1; off >>= 1) {
+            em = fmaxf(em, __shfl_xor(em, off));
+            ep = fmaxf(ep, __shfl_xor(ep, off));
+            xm = fmax(xm, __shfl_xor(xm, off));
+        }
+        const long long id = __double_as_longlong(XC[s2 * pitch + 2 * P]);
+        const bool judge = p2 == 0 && id >= 0;
+        bool miss = false;
+        if (judge) {
+            rel = refine_ratio(state->criterion, iters, (double)em, (double)ep, xm);
+            miss = !(rel <= tol);
+        }
+        const unsigned long long ball = __ballot(miss);
+        if (ball) {
+            unsigned long long first = 0;
+            if ((tid & 63) == 0) first = atomicAdd(&state->not_converged, (unsigned long long)__popcll(ball));
+            first = __shfl(first, 0);
+            if (miss) {
+                const unsigned long long slot = first + __popcll(ball & __lanemask_lt());
+                if (state->fallback_list && slot < (unsigned long long)state->list_capacity)
+                    state->fallback_list[slot] = (int32_t)id;
+            }
+        }
+    }
+    return rel;
+}
+
+// Resident workgroups walk the tiles as k_shift_stream does; per tile the
+// refinement on chip, then each row of x is stored and its register
+// refilled with the next tile's row of d.  Every lane folds its largest
+// ratio into the state once, at the end (one atomic per wavefront at most).
+template <int M, bool FULL>
+__global__ void __launch_bounds__((shift_max_threads<double, M>()))
+k_shift_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, int P_log2,
+               int32_t ntiles, int iters, double tol, RefineState *state) {
+    extern __shared__ double lds[];
+    char *base = reinterpret_cast<char *>(lds);
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2, P = 1 << P_log2;
+    const int s = tid & (S - 1);
+    const int p = tid >> S_log2;
+    const int r0 = p * M;
+    const int64_t n = map.n, rs = map.row_stride;
+    const int32_t nsys0 = (int32_t)map.nsys0;
+    const int32_t nsys = (int32_t)map.nsys;
+    const ShiftLds L = shift_layout(sizeof(double), M, P, S);
+    size_t f32_off = 0, g_off = 0;
+    (void)shift_refine_lds(M, P, S, &f32_off, &g_off);
+    float4 *R32 = reinterpret_cast<float4 *>(base + f32_off);
+    float *G = reinterpret_cast<float *>(base + g_off);
+    const double *SH = (const double *)coef.shift;
+    const int32_t step = (int32_t)gridDim.x << S_log2;
+    int32_t t = blockIdx.x;
+    Walk w;
+    w.init(nsys0, (t << S_log2) + s, step);
+    auto sbase = [&](const Walk &ww) {
+        return (int64_t)ww.s0 * map.sys_stride0 + (int64_t)ww.s1 * map.sys_stride1;
+    };
+    build_rows<double>(coef, n, M, P, base, L);
+    {
+        // FP32 copies of the operator rows for the sweeps
+        const double2 *AB = reinterpret_cast<const double2 *>(base + L.ab);
+        const double2 *CM = reinterpret_cast<const double2 *>(base + L.cm);
+        for (int q = tid; q < P * (M + 1); q += blockDim.x)
+            R32[q] = float4{(float)AB[q].x, (float)AB[q].y, (float)CM[q].x, (float)CM[q].y};
+        __syncthreads();
+    }
+    const int nrow = (int)(n - r0 < 0 ? 0 : (n - r0 > M ? M : n - r0));
+    double dv[M], xv[M];
+    int64_t b = sbase(w);
+    bool ok = w.k < nsys;
+    int32_t id = w.k;
+    double sh = SH[ok ? w.k : 0];
+    if constexpr (FULL) {
+        int64_t q = (ok ? b : 0) + (int64_t)r0 * rs;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            dv[j] = __builtin_nontemporal_load(d + q);
+            q = opaque(q + rs);
+        }
+    } else {
+        load_lane<double, M>(d, b, ok, rs, r0, n, dv);
+    }
+    double rel = 0.0;
+    for (;;) {
+        rel = fmax(rel, shift_refine_tile<M>(base, L, R32, G, S, s, p, P, P_log2, sh, dv, xv, iters, tol,
+                                             ok, id, state));
+        t += gridDim.x;
+        const bool more = t < ntiles;
+        w.advance(nsys0, step);
+        const int64_t nb = sbase(w);
+        const bool nok = more && w.k < nsys;
+        const double nsh = SH[nok ? w.k : 0];
+        // store x row by row, each freed register taking the next tile's row
+        // of d (FULL: every row inside the system; otherwise the rows are
+        // clamped to the system's last row and those past it zeroed)
+        int64_t xq = b + (int64_t)r0 * rs;
+        if constexpr (FULL) {
+            int64_t nq = (nok ? nb : 0) + (int64_t)r0 * rs;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if (ok) __builtin_nontemporal_store(xv[j], x + xq);
+                xq = opaque(xq + rs);
+                dv[j] = __builtin_nontemporal_load(d + nq);
+                nq = opaque(nq + rs);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if (ok && j < nrow) __builtin_nontemporal_store(xv[j], x + xq);
+                xq = opaque(xq + rs);
+            }
+            load_lane<double, M>(d, nb, nok, rs, r0, n, dv);
+        }
+        if (!more) break;
+        b = nb;
+        ok = nok;
+        id = w.k;
+        sh = nsh;
+    }
+    if (tid == 0 || (tid & 63) == 0) fold_max_rel(state, rel);
 }
 
 template <typename K>
@@ -481,6 +814,23 @@ hipError_t launch_m(const SysMap &map, const Coef &coef, const TileShape &sh, co
                 : launch_t<T, M, false>(map, coef, sh, d, x, err, st);
 }
 
+template <int M, bool FULL>
+hipError_t launch_refine_m(const SysMap &map, const Coef &coef, const TileShape &sh, const double *d,
+                           double *x, int iters, double tol, RefineState *state, hipStream_t st) {
+    const int S = 1 << sh.S_log2;
+    const int P_log2 = __builtin_ctz((unsigned)sh.P);
+    size_t f32_off = 0;
+    const size_t lds = shift_refine_lds(M, sh.P, S, &f32_off);
+    const int64_t ntiles = (map.nsys + S - 1) / S;
+    if (ntiles == 0) return hipSuccess;
+    const int64_t resident = resident_of(k_shift_refine<M, FULL>, sh.threads(), lds);
+    if (resident < 1) return hipErrorInvalidConfiguration;
+    const int64_t grid = ntiles < resident ? ntiles : resident;
+    hipLaunchKernelGGL((k_shift_refine<M, FULL>), dim3((unsigned)grid), dim3(sh.threads()), lds, st, map,
+                       coef, d, x, sh.S_log2, P_log2, (int32_t)ntiles, iters, tol, state);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 size_t shift_lds_bytes(int dtype, const TileShape &sh) {
@@ -506,6 +856,32 @@ bool shift_layout_ok(const SysMap &m, const TileShape &sh) {
     const int64_t S = (int64_t)1 << sh.S_log2;
     const int64_t ntiles = (m.nsys + S - 1) / S;
     return 3 * (ntiles + 1) * S < ((int64_t)1 << 31);
+}
+
+// Precision form: M = 16 or 32 rows per lane, P a power of two <= 64,
+// 1024 lanes (512 at M = 32), uniform strided layouts as the FP64 walk.
+bool shift_refine_supported(const SysMap &m, const TileShape &sh) {
+    if (sh.M != 16 && sh.M != 32) return false;
+    if (sh.P < 1 || sh.P > 64 || (sh.P & (sh.P - 1)) != 0) return false;
+    if (sh.S_log2 < 0 || sh.threads() > (sh.M == 32 ? 512 : 1024)) return false;
+    size_t off = 0;
+    if (shift_refine_lds(sh.M, sh.P, 1 << sh.S_log2, &off) > 160 * 1024) return false;
+    TileShape k = sh;
+    k.kernel = 3;
+    return shift_layout_ok(m, k);
+}
+
+hipError_t launch_shift_refine(const SysMap &map, const Coef &coef, const TileShape &sh,
+                               const double *d, double *x, int iters, double tol,
+                               RefineState *state, hipStream_t st) {
+    if (!shift_refine_supported(map, sh) || coef.mode != TDMA_COEF_SHARED || coef.shift == nullptr)
+        return hipErrorInvalidValue;
+    const bool full = (int64_t)sh.P * sh.M == map.n;
+    if (sh.M == 32)
+        return full ? launch_refine_m<32, true>(map, coef, sh, d, x, iters, tol, state, st)
+                    : launch_refine_m<32, false>(map, coef, sh, d, x, iters, tol, state, st);
+    return full ? launch_refine_m<16, true>(map, coef, sh, d, x, iters, tol, state, st)
+                : launch_refine_m<16, false>(map, coef, sh, d, x, iters, tol, state, st);
 }
 
 hipError_t launch_shift(int dtype, const SysMap &map, const Coef &coef, const TileShape &sh,

@@ -167,14 +167,15 @@ def test_poisson_1024_cubed_fp64_and_refined():
     print("refine report", rep)
     _check_sampled(p, x, samp[samp != 0], parity.TOL_REFINED, ld_ok=True)
     _check_sampled(pin, x, [0], parity.TOL_REFINED, ld_ok=True)
-    # the benchmark's setting: two steps at tol 1e-12, judged by the
-    # contraction between the two corrections
+    # the benchmark's setting: two steps judged by the contraction between
+    # the two corrections, at tol 1e-13 (the predicted error is an estimate:
+    # at tol 1e-12 a mode was accepted at 1.2e-12)
     x.fill_(float("nan"))
-    rep = tdma.solve_refined(p.layout, co, d, x, max_iters=2, tol=1e-12, criterion=1)
-    tdma.solve_refined(pin.layout, pin_co, d, x, max_iters=2, tol=1e-12, criterion=1)
+    rep = tdma.solve_refined(p.layout, co, d, x, max_iters=2, tol=1e-13, criterion=1)
+    tdma.solve_refined(pin.layout, pin_co, d, x, max_iters=2, tol=1e-13, criterion=1)
     tdma.check()
     assert torch.isfinite(x).all()
-    print("refine report (2 steps, tol 1e-12, criterion 1)", rep)
+    print("refine report (2 steps, tol 1e-13, criterion 1)", rep)
     _check_sampled(p, x, samp[samp != 0], parity.TOL_REFINED, ld_ok=True)
     _check_sampled(pin, x, [0], parity.TOL_REFINED, ld_ok=True)
     _poisson_bulk_check(p, x, parity.TOL_REFINED, "poisson refined (2 steps, criterion 1)")
