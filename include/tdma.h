@@ -1,9 +1,9 @@
 /*
  * tdma.h -- C ABI of the MI355X batched divide-and-conquer tridiagonal solver.
  *
- * Problem (paper, Algorithms 1 and 2): "A x = d, N times; input a, b, c, d;
- * output x", where a, b, c are the sub-, main and super-diagonals of a
- * tridiagonal matrix A (Sec. 3.2.1).  Each system is split into P partitions;
+ * Problem (paper, Algorithms 1 and 2, Sec. 3.2.1): the same tridiagonal solve
+ * A x = d repeated for N independent systems, from the three diagonals a
+ * (sub), b (main), c (super) and the right-hand side d to the solution x.  Each system is split into P partitions;
  * every partition is reduced by a modified Thomas sweep to two interface
  * equations (Stage A, Sec. 2.1 step 1), the 2P-row interface system is
  * solved (Stage B, step 3), and the interior unknowns are recovered from the
@@ -14,7 +14,8 @@
  *    caller; the library never frees or retains them past the call.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
  *    are stream-ordered and asynchronous unless stated otherwise.
- *  - x may alias d (in-place solve).  x must not alias a, b, c or b_shift.
+ *  - x may alias d (in-place solve; tdma_solve_refined only without its
+ *    FP64 fallback).  x must not alias a, b, c or b_shift.
  *  - a[0] and c[n-1] of every system are never read (no x_{-1}, no x_n).
  *  - No pivoting: results are defined for diagonally dominant systems and
  *    M-matrices (the paper's ADI and Poisson operators, Sec. 5).
@@ -103,6 +104,9 @@ typedef struct tdma_coeffs {
  * dtype: TDMA_F64 (FP64 storage and sweeps) or TDMA_F32 (FP32 storage and
  * sweeps, FP64 interface solve).  The partition count and tile shape come
  * from the autotune cache if it holds this shape, else a built-in rule.
+ * A ragged layout on a stream that the caller is capturing into a graph is
+ * refused with TDMA_EUNSUPPORTED (its plan tables are allocated and cached
+ * by the library); tdma_graph_create records ragged solves instead.
  */
 int tdma_solve_batched(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtype,
                        const void *d, void *x, void *stream);
@@ -302,6 +306,8 @@ typedef struct tdma_refine_report {
  * Coefficients, d and x are FP64.  With report != NULL the call
  * synchronises the stream and fills the report; with report == NULL it is
  * asynchronous and non-converged systems are handled per `fallback`.
+ * x may alias d only with fallback = 0 (the FP64 fallback re-reads d after
+ * x is written): with the fallback on, an aliased call is refused (EINVAL).
  */
 int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *coeffs, const double *d,
                        double *x, const tdma_refine_opts *opts, tdma_refine_report *report,

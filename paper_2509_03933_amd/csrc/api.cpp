@@ -530,17 +530,21 @@ int launch_uniform(const TileShape &sh, const tdma_layout *L, const tdma_coeffs 
 int run_fused(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dtype, const void *d,
               void *x, hipStream_t st, const TileShape *force) {
     if (L->offsets) {
-        const RaggedPlan *rp = nullptr;
-        int rc = plan_ragged(ctx, L, dtype, &rp);
-        if (rc != TDMA_OK) return rc;
-        // buckets on the caller's stream and kRaggedAux library streams at
-        // once -- except while the caller's stream is being captured into a
-        // graph, where they stay on that stream
+        // A ragged call builds (or finds in the library's cache) a plan whose
+        // device tables it allocates and uploads synchronously, and a cache
+        // entry can later be freed: neither may happen inside, or be recorded
+        // by, a capture the caller started.  Graphs of ragged solves are made
+        // by tdma_graph_create, which gives them tables of their own.
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         const hipError_t ce = hipStreamIsCapturing(st, &cs);
         if (ce != hipSuccess) return hip_fail(ce, "hipStreamIsCapturing");
         if (cs != hipStreamCaptureStatusNone)
-            return launch_ragged(*rp, L, C, dtype, d, x, ctx->d_err, st, nullptr, 0, nullptr);
+            return fail(TDMA_EUNSUPPORTED, "a ragged layout cannot be solved on a stream that is being "
+                        "captured (use tdma_graph_create)");
+        const RaggedPlan *rp = nullptr;
+        int rc = plan_ragged(ctx, L, dtype, &rp);
+        if (rc != TDMA_OK) return rc;
+        // buckets on the caller's stream and kRaggedAux library streams at once
         hipStream_t *aux = nullptr;
         hipEvent_t *ev = nullptr;
         rc = ctx->get_streams(kRaggedAux, &aux);

@@ -96,21 +96,47 @@ static bool default_shift_refine_shape(const SysMap &map, TileShape *out) {
 
 using namespace tdma;
 
-extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *coeffs,
-                                  const double *d, double *x, const tdma_refine_opts *opts,
-                                  tdma_refine_report *report, void *stream) {
-    clear_error();
+namespace tdma {
+
+// The options of a refined call, validated.
+struct RefineCall {
+    int iters = 3;
+    double tol = 1e-15;
+    int fallback = 1;
+    int criterion = 0;
+};
+
+static int refine_args(const tdma_layout *layout, const tdma_coeffs *coeffs, const double *d,
+                       double *x, const tdma_refine_opts *opts, RefineCall *out) {
     int rc = validate(layout, coeffs, TDMA_F64, d, x);
     if (rc != TDMA_OK) return rc;
     if (layout->offsets) return fail(TDMA_EUNSUPPORTED, "the refined path takes uniform layouts");
-    const int iters = opts ? opts->max_iters : 3;
-    const double tol = opts && opts->tol > 0.0 ? opts->tol : 1e-15;
-    const int fallback = opts ? opts->fallback : 1;
-    const int criterion = opts ? opts->criterion : 0;
-    if (iters < 0 || iters > 3) return fail(TDMA_EINVAL, "max_iters = %d (0..3)", iters);
-    if (fallback != 0 && fallback != 1) return fail(TDMA_EINVAL, "fallback = %d (0 or 1)", fallback);
-    if (criterion != 0 && criterion != 1)
-        return fail(TDMA_EINVAL, "criterion = %d (0 or 1)", criterion);
+    RefineCall c;
+    c.iters = opts ? opts->max_iters : 3;
+    c.tol = opts && opts->tol > 0.0 ? opts->tol : 1e-15;
+    c.fallback = opts ? opts->fallback : 1;
+    c.criterion = opts ? opts->criterion : 0;
+    if (c.iters < 0 || c.iters > 3) return fail(TDMA_EINVAL, "max_iters = %d (0..3)", c.iters);
+    if (c.fallback != 0 && c.fallback != 1)
+        return fail(TDMA_EINVAL, "fallback = %d (0 or 1)", c.fallback);
+    if (c.criterion != 0 && c.criterion != 1)
+        return fail(TDMA_EINVAL, "criterion = %d (0 or 1)", c.criterion);
+    // the FP64 fallback re-reads d after the refinement kernel has written x
+    if (c.fallback && (const void *)x == (const void *)d)
+        return fail(TDMA_EINVAL, "x aliases d: the FP64 fallback re-reads d after x is written "
+                    "(solve out of place, or with fallback = 0)");
+    *out = c;
+    return TDMA_OK;
+}
+
+// The refinement, its fallback and its report on device state the caller
+// provides: `state` (the RefineState), `list` (capacity system ids), `err`
+// (the numerical error flag the fallback kernels set; cleared first when
+// clear_err).  The solve's launches are those of tdma_solve_refined.
+static int refined_run(const tdma_layout *layout, const tdma_coeffs *coeffs, const double *d,
+                       double *x, const RefineCall &c, RefineState *state, int32_t *list,
+                       int64_t capacity, int *err, bool clear_err, tdma_refine_report *report,
+                       hipStream_t st) {
     const int64_t nsys = layout->nsys0 * layout->nsys1;
     if (report) std::memset(report, 0, sizeof *report);
     if (nsys == 0) return TDMA_OK;
@@ -119,32 +145,21 @@ extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *
                               coeffs->mode == TDMA_COEF_LIKE_D, &sh))
         return fail(TDMA_EUNSUPPORTED, "n = %lld is too long for the refined path",
                     (long long)layout->n);
-    DeviceCtx *ctx = nullptr;
-    rc = get_ctx(&ctx);
-    if (rc != TDMA_OK) return rc;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    hipStream_t st = (hipStream_t)stream;
-    const int64_t capacity = std::min<int64_t>(nsys, (int64_t)1 << 16);
-    void *ws = nullptr;
-    rc = ctx->workspace(3, 256 + (size_t)capacity * sizeof(int32_t), &ws);
-    if (rc != TDMA_OK) return rc;
-    RefineState *state = (RefineState *)ws;
-    int32_t *list = (int32_t *)((char *)ws + 256);
-    hipError_t e = launch_refine_init(state, list, capacity, criterion, st);
+    hipError_t e = launch_refine_init(state, list, capacity, c.criterion, clear_err ? err : nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "refine init");
     const SysMap map = make_map(layout);
     const Coef coef = make_coef(coeffs);
     TileShape ssh;
     if (coeffs->mode == TDMA_COEF_SHARED && coeffs->b_shift == nullptr &&
         default_shared_refine_shape(layout->n, nsys, layout->row_stride == 1, &ssh))
-        e = launch_shared_refine(map, coef, ssh, d, x, iters, tol, state, st);
+        e = launch_shared_refine(map, coef, ssh, d, x, c.iters, c.tol, state, st);
     else if (coeffs->mode == TDMA_COEF_SHARED && coeffs->b_shift != nullptr &&
              layout->row_stride != 1 && default_shift_refine_shape(map, &ssh))
-        e = launch_shift_refine(map, coef, ssh, d, x, iters, tol, state, st);
+        e = launch_shift_refine(map, coef, ssh, d, x, c.iters, c.tol, state, st);
     else
-        e = launch_refine(map, coef, sh, d, x, iters, tol, state, st);
+        e = launch_refine(map, coef, sh, d, x, c.iters, c.tol, state, st);
     if (e != hipSuccess) return hip_fail(e, "refine launch");
-    if (fallback) {
+    if (c.fallback) {
         TileShape fsh;
         if (!default_shape(TDMA_F64, layout->n, capacity, layout->row_stride == 1, &fsh))
             return fail(TDMA_EUNSUPPORTED, "no FP64 fallback tile for n = %lld", (long long)layout->n);
@@ -152,7 +167,7 @@ extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *
         fm.nsys = capacity;
         fm.sys_list = list;
         fm.count = &state->not_converged;
-        e = launch_fused(TDMA_F64, fm, coef, fsh, d, x, ctx->d_err, st);
+        e = launch_fused(TDMA_F64, fm, coef, fsh, d, x, err, st);
         if (e != hipSuccess) return hip_fail(e, "fallback launch");
         // the systems that needed the fallback are the ill-conditioned ones:
         // two rounds of double-double residual + FP64 correction
@@ -168,15 +183,41 @@ extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *
     if (e != hipSuccess) return hip_fail(e, "refine report");
     double rel;
     std::memcpy(&rel, &hs.max_rel_bits, sizeof rel);
-    report->iterations = iters;
+    report->iterations = c.iters;
     report->not_converged = (int64_t)hs.not_converged;
-    report->fallback_systems = fallback ? std::min<int64_t>((int64_t)hs.not_converged, capacity) : 0;
+    report->fallback_systems = c.fallback ? std::min<int64_t>((int64_t)hs.not_converged, capacity) : 0;
     report->max_rel_correction = rel;
-    if (!fallback && hs.not_converged > 0)
+    if (!c.fallback && hs.not_converged > 0)
         return fail(TDMA_ENOCONV, "%llu systems missed tol = %g after %d steps",
-                    (unsigned long long)hs.not_converged, tol, iters);
+                    (unsigned long long)hs.not_converged, c.tol, c.iters);
     if ((int64_t)hs.not_converged > capacity)
         return fail(TDMA_ENOCONV, "%llu systems missed tol; only %lld were re-solved in FP64",
                     (unsigned long long)hs.not_converged, (long long)capacity);
     return TDMA_OK;
+}
+
+}  // namespace tdma
+
+extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *coeffs,
+                                  const double *d, double *x, const tdma_refine_opts *opts,
+                                  tdma_refine_report *report, void *stream) {
+    clear_error();
+    RefineCall c;
+    int rc = refine_args(layout, coeffs, d, x, opts, &c);
+    if (rc != TDMA_OK) return rc;
+    const int64_t nsys = layout->nsys0 * layout->nsys1;
+    if (nsys == 0) {
+        if (report) std::memset(report, 0, sizeof *report);
+        return TDMA_OK;
+    }
+    DeviceCtx *ctx = nullptr;
+    rc = get_ctx(&ctx);
+    if (rc != TDMA_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const int64_t capacity = std::min<int64_t>(nsys, (int64_t)1 << 16);
+    void *ws = nullptr;
+    rc = ctx->workspace(3, 256 + (size_t)capacity * sizeof(int32_t), &ws);
+    if (rc != TDMA_OK) return rc;
+    return refined_run(layout, coeffs, d, x, c, (RefineState *)ws, (int32_t *)((char *)ws + 256),
+                       capacity, ctx->d_err, false, report, (hipStream_t)stream);
 }

@@ -61,8 +61,10 @@ int refine_max_threads(int M);
 bool refine_supported(const TileShape &sh, bool like_d);
 hipError_t launch_refine(const SysMap &map, const Coef &coef, const TileShape &sh, const double *d,
                          double *x, int iters, double tol, RefineState *state, hipStream_t st);
+// Resets the state (and zeroes *clear_err unless it is null) with a kernel,
+// not a memset, so the call may be recorded into a graph.
 hipError_t launch_refine_init(RefineState *state, int32_t *list, int64_t capacity, int criterion,
-                              hipStream_t st);
+                              int *clear_err, hipStream_t st);
 
 // FP64 polishing of listed systems with double-double residuals (refine.hip)
 int polish_partitions(int64_t n);

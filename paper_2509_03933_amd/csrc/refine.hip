@@ -399,7 +399,9 @@ k_polish(SysMap map, Coef coef, const double *d, double *x, const int32_t *list,
     }
 }
 
-__global__ void k_refine_init(RefineState *state, int32_t *list, int64_t capacity, int criterion) {
+__global__ void k_refine_init(RefineState *state, int32_t *list, int64_t capacity, int criterion,
+                              int *err) {
+    if (err) *err = 0;
     state->not_converged = 0ull;
     state->max_rel_bits = 0ull;
     state->fallback_list = list;
@@ -455,8 +457,9 @@ bool refine_supported(const TileShape &sh, bool like_d) {
 }
 
 hipError_t launch_refine_init(RefineState *state, int32_t *list, int64_t capacity, int criterion,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(k_refine_init, dim3(1), dim3(1), 0, st, state, list, capacity, criterion);
+                              int *clear_err, hipStream_t st) {
+    hipLaunchKernelGGL(k_refine_init, dim3(1), dim3(1), 0, st, state, list, capacity, criterion,
+                       clear_err);
     return hipGetLastError();
 }
 

@@ -109,3 +109,33 @@ def test_graph_rejects_bad_dependencies():
     with pytest.raises(tdma.TdmaError):
         tdma.graph_create([dict(layout=p.layout, coeffs=co, d=td, x=tx),
                            dict(layout=p.layout, coeffs=co, d=tx, x=td, after=5)])
+
+
+def test_ragged_solve_refused_under_caller_capture():
+    """A ragged solve on a stream the caller is capturing is refused (its plan
+    tables are allocated and cached by the library; tdma_graph_create records
+    ragged solves), and nothing is left half-recorded."""
+    import numpy as np
+    import paper_2509_03933_amd as tdma
+    from workloads import configs
+    r = configs.ragged(nsys=50, nmin=2, nmax=300)
+    a, b, c, d = configs.full_arrays(r)
+    dev = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    co = dict(mode=0, a=dev(a), b=dev(b), c=dev(c))
+    td = dev(d)
+    tx = torch.empty_like(td)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    err = None
+    with torch.cuda.stream(s):
+        try:
+            with torch.cuda.graph(g, stream=s):
+                tx.fill_(0.0)   # a fill kernel, so the captured graph is not empty
+                tdma.solve_batched(r.layout, co, td, tx, stream=s)
+        except tdma.TdmaError as e:
+            err = e
+    torch.cuda.synchronize()
+    assert err is not None and err.status == tdma.EUNSUPPORTED, err
+    # the same solve outside capture works
+    tdma.solve_batched(r.layout, co, td, tx)
+    tdma.check()

@@ -198,3 +198,23 @@ def test_contraction_criterion_needs_two_steps():
     assert rep["not_converged"] == p.layout.nsys == rep["fallback_systems"]
     ref = parity.oracle_solution(p, a, b, c, d)
     assert parity.per_system_error(p.layout, x, ref).max() <= parity.TOL_F64
+
+
+def test_in_place_needs_fallback_off():
+    """x aliasing d: refused with the FP64 fallback on (it re-reads d after x
+    is written); with the fallback off the in-place result matches the
+    out-of-place one."""
+    import paper_2509_03933_amd as tdma
+    p = configs.adi(32, 16, 256)
+    a, b, c, d = parity.host_problem(p)
+    coeffs = parity.device_coeffs(p, a, b, c, torch.float64)
+    (td,) = parity.to_device([d], torch.float64)
+    with pytest.raises(tdma.TdmaError) as ei:
+        tdma.solve_refined(p.layout, coeffs, td, td, max_iters=2, tol=1e-13)
+    assert ei.value.status == tdma.EINVAL
+    tx = torch.empty_like(td)
+    tdma.solve_refined(p.layout, coeffs, td, tx, max_iters=2, tol=1e-13, fallback=0)
+    tdma.solve_refined(p.layout, coeffs, td, td, max_iters=2, tol=1e-13, fallback=0)
+    assert torch.equal(td, tx)
+    ref = parity.oracle_solution(p, a, b, c, d)
+    assert parity.per_system_error(p.layout, td.cpu().numpy(), ref).max() <= parity.TOL_REFINED
