@@ -314,6 +314,27 @@ int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *coeffs, con
                        void *stream);
 
 /*
+ * tdma_solve_refined_noalloc: tdma_solve_refined for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results;
+ * it calls no allocating routine.  Its device state (the refinement state,
+ * the fallback's error flag and the fallback list) lives in a fixed
+ * 262,400-byte array that every device the library runs on holds until the
+ * process ends; its address is looked up once per device, on the device's
+ * first call (devices 0..63).  Limit: at most 65,536 systems of a call can
+ * be listed for the FP64 fallback (as in tdma_solve_refined); when more miss
+ * tol the call returns TDMA_ENOCONV with the count.  Calls on one device
+ * share the array and the last call's contents stay in it: calls that
+ * overlap in time on one device (different streams, or host threads without
+ * ordering) race and must be ordered by the caller.  Numerical errors of the
+ * fallback (a zero or non-finite pivot) are returned as TDMA_ESINGULAR when
+ * report != NULL; tdma_check does not see them.
+ */
+int tdma_solve_refined_noalloc(const tdma_layout *layout, const tdma_coeffs *coeffs,
+                               const double *d, double *x, const tdma_refine_opts *opts,
+                               tdma_refine_report *report, void *stream);
+
+/*
  * Batching form: a list of solves recorded once into a hipGraph, replayed as
  * one submission by tdma_graph_launch.  Each item is planned and launched
  * exactly as tdma_solve_batched would (same kernels, tile shapes and

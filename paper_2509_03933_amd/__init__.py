@@ -93,6 +93,7 @@ def lib():
                                                  vp, ctypes.POINTER(_PartOpts), vp]
             L.tdma_solve_refined.argtypes = [ctypes.POINTER(_Layout), ctypes.POINTER(_Coeffs), vp, vp,
                                              ctypes.POINTER(_RefineOpts), ctypes.POINTER(RefineReport), vp]
+            L.tdma_solve_refined_noalloc.argtypes = L.tdma_solve_refined.argtypes
             L.tdma_graph_create.argtypes = [ctypes.POINTER(_WorkItem), i, i, ctypes.POINTER(vp)]
             L.tdma_graph_launch.argtypes = [vp, vp]
             L.tdma_graph_destroy.argtypes = [vp]
@@ -116,7 +117,7 @@ def lib():
             L.tdma_last_error.restype = ctypes.c_char_p
             L.tdma_shutdown.restype = None
             for f in ("tdma_solve_batched", "tdma_solve_batched_tiled", "tdma_solve_partitioned", "tdma_solve_refined",
-                      "tdma_solve_multi", "tdma_solve_pdd", "tdma_copy_streamed",
+                      "tdma_solve_refined_noalloc", "tdma_solve_multi", "tdma_solve_pdd", "tdma_copy_streamed",
                       "tdma_poisson_create", "tdma_poisson_solve",
                       "tdma_graph_create", "tdma_graph_launch", "tdma_autotune", "tdma_check"):
                 getattr(L, f).restype = ctypes.c_int
@@ -125,6 +126,7 @@ def lib():
 
 
 EXPORTED_SYMBOLS = ("tdma_solve_batched", "tdma_solve_batched_tiled", "tdma_solve_partitioned", "tdma_solve_refined",
+                    "tdma_solve_refined_noalloc",
                     "tdma_copy_streamed", "tdma_solve_multi", "tdma_solve_pdd",
                     "tdma_poisson_create", "tdma_poisson_solve", "tdma_poisson_destroy",
                     "tdma_graph_create", "tdma_graph_launch", "tdma_graph_destroy",
@@ -380,20 +382,22 @@ def solve_partitioned(layout, coeffs, d, x, partitions=0, batch=0, nstreams=0, s
 
 
 def solve_refined(layout, coeffs, d, x, max_iters=3, tol=1e-15, fallback=1, report=True,
-                  stream=None, criterion=0):
-    """FP32 sweeps with FP64 refinement (tdma_solve_refined).  Returns the
-    report as a dict when report=True (the call then synchronises).
-    criterion 0 tests the last correction against tol, 1 the remaining error
-    estimated from the observed contraction."""
+                  stream=None, criterion=0, noalloc=False):
+    """FP32 sweeps with FP64 refinement (tdma_solve_refined, or with
+    noalloc=True tdma_solve_refined_noalloc, which allocates no device
+    memory).  Returns the report as a dict when report=True (the call then
+    synchronises).  criterion 0 tests the last correction against tol, 1 the
+    remaining error estimated from the observed contraction."""
     import torch
     if d.dtype != torch.float64:
         raise TypeError("tdma_solve_refined takes FP64 d and x")
     L, C, keep = _prepare(layout, coeffs, d, x)
     o = _RefineOpts(int(max_iters), float(tol), int(fallback), int(criterion))
     rep = RefineReport()
-    _raise(lib().tdma_solve_refined(ctypes.byref(L), ctypes.byref(C), ctypes.c_void_p(d.data_ptr()),
-                                    ctypes.c_void_p(x.data_ptr()), ctypes.byref(o),
-                                    ctypes.byref(rep) if report else None, _stream_handle(stream)))
+    fn = lib().tdma_solve_refined_noalloc if noalloc else lib().tdma_solve_refined
+    _raise(fn(ctypes.byref(L), ctypes.byref(C), ctypes.c_void_p(d.data_ptr()),
+              ctypes.c_void_p(x.data_ptr()), ctypes.byref(o),
+              ctypes.byref(rep) if report else None, _stream_handle(stream)))
     return rep.as_dict() if report else None
 
 

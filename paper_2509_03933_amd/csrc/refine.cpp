@@ -198,6 +198,83 @@ static int refined_run(const tdma_layout *layout, const tdma_coeffs *coeffs, con
 
 }  // namespace tdma
 
+// ---------------------------------------------------------------------------
+// tdma_solve_refined_noalloc: the same solve for callers that cannot allocate
+// device memory.  Its device state lives in `scratch`, a file-scope array every
+// device holds until the process ends: bytes [0, 128) the RefineState, [128,
+// 132) the numerical error flag of its fallback, [256, ...) the fallback list
+// of kNoAllocList system ids.  The array's name is a host-side stand-in: its
+// device address is taken once per device, with that device current, by
+// hipGetSymbolAddress, and only that address is used afterwards.
+
+namespace tdma {
+constexpr int64_t kNoAllocList = (int64_t)1 << 16;
+constexpr size_t kNoAllocBytes = 256 + (size_t)kNoAllocList * sizeof(int32_t);
+constexpr size_t kNoAllocErr = 128;
+static_assert(sizeof(RefineState) <= kNoAllocErr, "RefineState must fit before the error flag");
+}  // namespace tdma
+
+static __device__ __align__(256) unsigned char scratch[tdma::kNoAllocBytes];
+
+namespace tdma {
+
+constexpr int kNoAllocDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch[kNoAllocDevices];
+
+// Device address of `scratch` on the current device (looked up on the
+// device's first call; no allocation).
+static int noalloc_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kNoAllocDevices)
+        return fail(TDMA_EUNSUPPORTED, "device %d (the no-allocation path serves devices 0..%d)", dev,
+                    kNoAllocDevices - 1);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(TDMA_EHIP, "hipGetSymbolAddress(scratch) gave a null address");
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return TDMA_OK;
+}
+
+}  // namespace tdma
+
+extern "C" int tdma_solve_refined_noalloc(const tdma_layout *layout, const tdma_coeffs *coeffs,
+                                          const double *d, double *x, const tdma_refine_opts *opts,
+                                          tdma_refine_report *report, void *stream) {
+    clear_error();
+    RefineCall c;
+    int rc = refine_args(layout, coeffs, d, x, opts, &c);
+    if (rc != TDMA_OK) return rc;
+    const int64_t nsys = layout->nsys0 * layout->nsys1;
+    if (nsys == 0) {
+        if (report) std::memset(report, 0, sizeof *report);
+        return TDMA_OK;
+    }
+    void *ptr = nullptr;
+    rc = noalloc_scratch(&ptr);
+    if (rc != TDMA_OK) return rc;
+    char *base = (char *)ptr;
+    const int64_t capacity = std::min<int64_t>(nsys, kNoAllocList);
+    int *err = (int *)(base + kNoAllocErr);
+    hipStream_t st = (hipStream_t)stream;
+    rc = refined_run(layout, coeffs, d, x, c, (RefineState *)base, (int32_t *)(base + 256), capacity,
+                     err, true, report, st);
+    if (rc != TDMA_OK || !report) return rc;
+    int flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, err, sizeof flag, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "error flag");
+    if (flag) return fail(TDMA_ESINGULAR, "the FP64 fallback met a zero or non-finite pivot");
+    return TDMA_OK;
+}
+
 extern "C" int tdma_solve_refined(const tdma_layout *layout, const tdma_coeffs *coeffs,
                                   const double *d, double *x, const tdma_refine_opts *opts,
                                   tdma_refine_report *report, void *stream) {
