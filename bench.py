@@ -76,6 +76,7 @@ KERNEL_SOURCES = {
     "k_shared_refine_walk": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
     "k_fused": [CSRC + "fused.hip", CSRC + "fused_tile.hip.h", CSRC + "tile.hip.h"],
     "k_shift_stream": [CSRC + "shifted.hip", CSRC + "tile.hip.h"],
+    "k_shift_refine": [CSRC + "shifted.hip", CSRC + "tile.hip.h", CSRC + "refine.h"],
     "k_refine": [CSRC + "refine.hip", CSRC + "tile.hip.h"],
     "k_multi": [CSRC + "multi.hip", CSRC + "tile.hip.h"],
     "k_stage_a": [CSRC + "partitioned.hip", CSRC + "tile.hip.h"],
@@ -416,8 +417,8 @@ def bench_poisson(args):
                                "entry_point": f"tdma_solve_refined ({REFINE_ITERS} steps, tol {REFINE_TOL:g}, "
                                               f"criterion {REFINE_CRITERION}, FP64 fallback + polish), "
                                               f"bulk + pinned mode",
-                               "roofline": roofline(bytes_bulk, msr_bulk, "k_refine",
-                                                    f"k_refine_poisson{nx}x{ny}x{nz}_f64",
+                               "roofline": roofline(bytes_bulk, msr_bulk, "k_shift_refine",
+                                                    f"k_shift_refine_poisson{nx}x{ny}x{nz}_f64",
                                                     note="bulk call (refinement kernel + fallback), "
                                                          "timed alone"),
                                "faster_than_fp64": msr < ms},
