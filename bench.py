@@ -306,9 +306,9 @@ def bench_partitioned(args):
 
 def bench_autotune(args):
     """The autotuner on the staged path's configuration: per-stage times of
-    each batch size 2^12..2^18, the pipeline model's choice, and the measured
-    pipeline time of every batch size (brute force); then the solve with the
-    tuned batch, timed."""
+    each partition count 2..32 and batch size 2^12..2^18, the pipeline
+    model's choice, and the measured pipeline time of every candidate (brute
+    force); then the solve with the tuned partition count and batch, timed."""
     import torch
     import paper_2509_03933_amd as tdma
     from workloads import configs, device
@@ -319,8 +319,8 @@ def bench_autotune(args):
     lay = p.layout
     st = torch.cuda.current_stream()
     rec = tdma.autotune(lay, coeffs, d, x, what=2, stream=st)
-    by_batch = {c["batch"]: c for c in rec["candidates"]}
-    chosen = by_batch[rec["model_choice"]]["measured_ms"]
+    by_choice = {(c["P"], c["batch"]): c for c in rec["candidates"]}
+    chosen = by_choice[(rec["P"], rec["model_choice"])]["measured_ms"]
     ms = timed(lambda i: tdma.solve_partitioned(lay, coeffs, d, x, stream=st), args.steps,
                args.warmup, st)
     unknowns = lay.unknowns()
@@ -331,10 +331,12 @@ def bench_autotune(args):
                "config": {"workload": f"partitioned_zlines_{nx}x{ny}x{nz}_autotuned", "systems": lay.nsys,
                           "n": lay.n, "partitions": rec["P"],
                           "entry_point": "tdma_autotune (what = 2), then tdma_solve_partitioned"},
-               "autotune": {"model_choice": rec["model_choice"], "model_choice_measured_ms": chosen,
-                            "brute_choice": rec["brute_choice"], "brute_ms": rec["brute_ms"],
+               "autotune": {"model_choice_P": rec["P"], "model_choice": rec["model_choice"],
+                            "model_choice_measured_ms": chosen,
+                            "brute_choice_P": rec["brute_choice_P"], "brute_choice": rec["brute_choice"],
+                            "brute_ms": rec["brute_ms"],
                             "model_over_brute": round(chosen / rec["brute_ms"], 4),
-                            "candidates": [{k: c[k] for k in ("batch", "t_a_ms", "t_b_ms", "t_c_ms",
+                            "candidates": [{k: c[k] for k in ("P", "batch", "t_a_ms", "t_b_ms", "t_c_ms",
                                                               "model_ms", "measured_ms")}
                                            for c in rec["candidates"]]},
                "max_rel_err_vs_oracle": None,
@@ -546,9 +548,8 @@ def bench_sweeps(args):
     import torch
     import paper_2509_03933_amd as tdma
     from workloads import configs, device
-    # default: half the 768x512x1536 grid along each axis (the full-size
-    # graph is not run by this benchmark; --grid selects any other)
-    nx, ny, nz = (int(v) for v in (args.grid or "384,256,768").split(","))
+    # default: the full 768x512x1536 grid (--grid selects any other)
+    nx, ny, nz = (int(v) for v in (args.grid or "768,512,1536").split(","))
     px, py, pz = configs.sweeps(nx, ny, nz)
     rg = configs.ragged()
     R, _ = device.device_inputs(px)
@@ -678,7 +679,10 @@ def oracle_errors(checks):
         elif c["kind"] == "chain":
             ref = c["R"]
             for p, systems, rows in zip(c["problems"], c["systems"], c["rows"]):
+                t0 = time.perf_counter()
                 ref = oracle.solve_batch(p.layout, 1, p.a, p.b, p.c, ref)
+                print(f"oracle chain: {p.name} ({p.layout.unknowns()} unknowns) in "
+                      f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
                 for s, got in zip(systems, rows):
                     worst = max(worst, rel(got, ref[p.layout.sys_rows(int(s))]))
         errs[c["path"]] = worst

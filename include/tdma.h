@@ -232,7 +232,7 @@ int tdma_copy_streamed(const tdma_layout *layout, int dtype, const void *src, vo
 
 /*
  * Options of the split, pipelined solve.  Zero fields take defaults.
- *  partitions  P per system (>= 1, n/P >= 2); 0 = 8.
+ *  partitions  P per system (>= 1, n/P >= 2); 0 = autotuned (cached) or 8.
  *  batch       systems per pipeline batch (the paper's batch_z, Sec. 4.2.1);
  *              0 = autotuned (cached) or 32768.
  *  nstreams    HIP streams the pipeline uses (1..8); 0 = autotuned or 4.
@@ -366,10 +366,13 @@ int tdma_graph_launch(tdma_graph *graph, void *stream);
 void tdma_graph_destroy(tdma_graph *graph);
 
 /*
- * tdma_autotune: time candidate tile shapes (fused path) or batch sizes and
- * schedules (partitioned path, using the pipeline model of Sec. 4.2.3) for
- * this shape on the calling device, store the winner in the in-process
- * cache (and in the JSON file named by TDMA_CACHE, if set).  Synchronous.
+ * tdma_autotune: time candidate tile shapes (fused path) or partition counts
+ * and batch sizes (partitioned path: P = 2..32 with n/P >= 2, batches of
+ * 2^12..2^18 systems, chosen by the pipeline model of Sec. 4.2.3) for this
+ * shape on the calling device, store the winner in the in-process cache (and
+ * in the file named by TDMA_CACHE, if set).  The partitioned path caches the
+ * model's best batch for every P (used when the caller fixes P) and its best
+ * (P, batch) overall (used when the caller leaves P at 0).  Synchronous.
  * The buffers must be valid inputs of that shape; x is overwritten and must
  * not alias d.
  * what: 0 = fused path, 1 = partitioned path (model), 2 = partitioned path

@@ -236,12 +236,16 @@ def _stream_handle(stream):
 
 
 def _prepare(layout, coeffs, d, x):
+    """Marshalled layout and coefficients, and the Python objects their
+    pointers refer to (offsets array, coefficient tensors): whoever keeps the
+    pointers past the call (a recorded graph) must keep these alive."""
     keep = []
     need = _extent(layout)
     _check_tensor("d", d, need)
     _check_tensor("x", x, need, d.dtype)
     L = _make_layout(layout, keep)
     C = _make_coeffs(layout, coeffs, d, need)
+    keep.extend(t for t in (coeffs.get(k) for k in ("a", "b", "c", "shift")) if t is not None)
     return L, C, keep
 
 
@@ -402,7 +406,9 @@ def solve_refined(layout, coeffs, d, x, max_iters=3, tol=1e-15, fallback=1, repo
 
 
 class Graph:
-    """A recorded batching-form launch (tdma_graph_*)."""
+    """A recorded batching-form launch (tdma_graph_*).  The graph's kernels
+    hold raw pointers to every item's d, x and coefficient tensors, so the
+    Graph keeps references to them for as long as it exists."""
 
     def __init__(self, handle, keep):
         self._h = handle

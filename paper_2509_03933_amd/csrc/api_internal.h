@@ -78,7 +78,9 @@ int run_fused(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dt
 
 // autotune cache (autotune.cpp)
 bool lookup_tuned(int dev, const tdma_layout *L, const tdma_coeffs *C, int dtype, TileShape *out);
-bool lookup_tuned_batch(int dev, const tdma_layout *L, const tdma_coeffs *C, int dtype, int P,
+// Tuned staged-path settings for partition count *P; *P = 0 asks for the
+// tuner's own choice of P, which is written back.
+bool lookup_tuned_batch(int dev, const tdma_layout *L, const tdma_coeffs *C, int dtype, int *P,
                         int64_t *batch, int *nstreams, int *schedule);
 int pipeline_solve(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int dtype,
                    const void *d, void *x, int P, int64_t batch, int nstreams, int schedule,

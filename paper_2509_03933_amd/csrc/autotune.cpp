@@ -5,8 +5,9 @@
 // buffers; the fastest is cached for this shape.
 //
 // Staged path (the paper's batch-size optimisation, Sec. 4.2.3): for each
-// candidate batch size s (powers of two from 2^12 to 2^18, clipped to the
-// number of systems) the mean time of Stage A, B and C on one batch is
+// partition count P (2..32, n/P >= 2) and each candidate batch size s
+// (powers of two from 2^12 to 2^18, clipped to the number of systems) the
+// mean time of Stage A, B and C on one batch is
 // measured with each stage run alone, and the total is predicted from the
 // pipelined schedule of Algorithm 2 with N_b = ceil(N/s) batches:
 //     T(s) = sum_{k=1}^{N_b+2} max([k <= N_b] t_A + [k >= 3] t_C, [2 <= k <= N_b+1] t_B)
@@ -175,12 +176,13 @@ bool lookup_tuned(int dev, const tdma_layout *L, const tdma_coeffs *C, int dtype
     return true;
 }
 
-bool lookup_tuned_batch(int dev, const tdma_layout *L, const tdma_coeffs *C, int dtype, int P,
+bool lookup_tuned_batch(int dev, const tdma_layout *L, const tdma_coeffs *C, int dtype, int *P,
                         int64_t *batch, int *nstreams, int *schedule) {
     std::lock_guard<std::mutex> g(g_tune_mutex);
     load_cache_locked();
-    auto it = g_tuned.find(key_of(dev, L, C, dtype, "part", P));
-    if (it == g_tuned.end() || it->second.batch <= 0) return false;
+    auto it = g_tuned.find(key_of(dev, L, C, dtype, "part", *P));
+    if (it == g_tuned.end() || it->second.batch <= 0 || it->second.P < 1) return false;
+    *P = it->second.P;
     *batch = it->second.batch;
     *nstreams = it->second.nstreams;
     *schedule = it->second.schedule;
@@ -270,9 +272,12 @@ int tdma_autotune(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtyp
         g_last_json = js.str();
         return TDMA_OK;
     }
-    // staged path: P = 8 (the default partition count)
-    const int P = 8;
-    if (layout->n / P < 2) return fail(TDMA_EINVAL, "n too short for P = 8");
+    // staged path: every partition count P (powers of two, n/P >= 2) with
+    // every batch size
+    std::vector<int> Ps;
+    for (int P = 2; P <= 32; P <<= 1)
+        if (layout->n / P >= 2) Ps.push_back(P);
+    if (Ps.empty()) return fail(TDMA_EINVAL, "n = %lld is too short to partition", (long long)layout->n);
     std::vector<int64_t> sizes;
     for (int64_t s = 1 << 12; s <= (1 << 18); s <<= 1) sizes.push_back(std::min(s, nsys));
     sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
@@ -280,65 +285,84 @@ int tdma_autotune(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtyp
     const Coef coef = make_coef(coeffs);
     const bool shared_factors = coeffs->mode == TDMA_COEF_SHARED && coeffs->b_shift == nullptr;
     const size_t esz = dtype == TDMA_F64 ? 8 : 4;
-    js << "{\"path\":\"partitioned\",\"P\":" << P << ",\"candidates\":[";
+    js << "{\"path\":\"partitioned\",\"candidates\":[";
     double best_model = 1e300, best_brute = 1e300;
     int64_t s_model = sizes[0], s_brute = sizes[0];
+    int P_model = Ps[0], P_brute = Ps[0];
+    std::vector<int64_t> per_P_batch(Ps.size(), sizes[0]);
     bool first = true;
-    for (int64_t s : sizes) {
-        // one batch worth of workspace (slot 0 of the pipeline workspace)
-        const size_t fac = shared_factors ? (size_t)layout->n : (size_t)layout->n * s;
-        const size_t fac_bytes = (fac * esz + 255) & ~(size_t)255;
-        const size_t dh_bytes = ((size_t)layout->n * s * esz + 255) & ~(size_t)255;
-        const size_t red_bytes = ((size_t)6 * P * s * 8 + 255) & ~(size_t)255;
-        const size_t x_bytes = ((size_t)2 * P * s * 8 + 255) & ~(size_t)255;
-        void *ws = nullptr;
-        rc = ctx->workspace(4, dh_bytes + 2 * fac_bytes + red_bytes + 2 * x_bytes, &ws);
-        if (rc != TDMA_OK) return rc;
-        char *wd_ = (char *)ws;
-        char *b = wd_ + dh_bytes;
-        void *wa = b, *wc = b + fac_bytes;
-        double *red = (double *)(b + 2 * fac_bytes), *X = (double *)(b + 2 * fac_bytes + red_bytes);
-        double *scr = (double *)(b + 2 * fac_bytes + red_bytes + x_bytes);
-        float tA = 0, tB = 0, tC = 0;
-        rc = time_median(st, 3, [&]() {
-            hipError_t e = launch_stage_a(dtype, map, coef, d, wd_, wa, wc, red, 0, s, P, shared_factors, ctx->d_err, st);
-            return e == hipSuccess ? TDMA_OK : hip_fail(e, "stage A");
-        }, &tA);
-        if (rc == TDMA_OK) rc = time_median(st, 3, [&]() {
-            hipError_t e = launch_stage_b(red, X, scr, s, P, ctx->d_err, st);
-            return e == hipSuccess ? TDMA_OK : hip_fail(e, "stage B");
-        }, &tB);
-        if (rc == TDMA_OK) rc = time_median(st, 3, [&]() {
-            hipError_t e = launch_stage_c(dtype, map, x, wd_, wa, wc, X, 0, s, P, shared_factors, st);
-            return e == hipSuccess ? TDMA_OK : hip_fail(e, "stage C");
-        }, &tC);
-        if (rc != TDMA_OK) return rc;
-        const double model = pipeline_model_ms(nsys, s, tA, tB, tC, 1);
-        const double model_seq = pipeline_model_ms(nsys, s, tA, tB, tC, 0);
-        float brute = -1.f;
-        if (what == 2) {
-            rc = time_median(st, 3, [&]() {
-                return pipeline_solve(ctx, layout, coeffs, dtype, d, x, P, s, 4, 1, st);
-            }, &brute);
+    for (size_t pi = 0; pi < Ps.size(); ++pi) {
+        const int P = Ps[pi];
+        double best_model_P = 1e300;
+        for (int64_t s : sizes) {
+            // one batch worth of workspace (slot 0 of the pipeline workspace)
+            const size_t fac = shared_factors ? (size_t)layout->n : (size_t)layout->n * s;
+            const size_t fac_bytes = (fac * esz + 255) & ~(size_t)255;
+            const size_t dh_bytes = ((size_t)layout->n * s * esz + 255) & ~(size_t)255;
+            const size_t red_bytes = ((size_t)6 * P * s * 8 + 255) & ~(size_t)255;
+            const size_t x_bytes = ((size_t)2 * P * s * 8 + 255) & ~(size_t)255;
+            void *ws = nullptr;
+            rc = ctx->workspace(4, dh_bytes + 2 * fac_bytes + red_bytes + 2 * x_bytes, &ws);
             if (rc != TDMA_OK) return rc;
-            if (brute < best_brute) { best_brute = brute; s_brute = s; }
+            char *wd_ = (char *)ws;
+            char *b = wd_ + dh_bytes;
+            void *wa = b, *wc = b + fac_bytes;
+            double *red = (double *)(b + 2 * fac_bytes), *X = (double *)(b + 2 * fac_bytes + red_bytes);
+            double *scr = (double *)(b + 2 * fac_bytes + red_bytes + x_bytes);
+            float tA = 0, tB = 0, tC = 0;
+            rc = time_median(st, 3, [&]() {
+                hipError_t e = launch_stage_a(dtype, map, coef, d, wd_, wa, wc, red, 0, s, P,
+                                              shared_factors, ctx->d_err, st);
+                return e == hipSuccess ? TDMA_OK : hip_fail(e, "stage A");
+            }, &tA);
+            if (rc == TDMA_OK) rc = time_median(st, 3, [&]() {
+                hipError_t e = launch_stage_b(red, X, scr, s, P, ctx->d_err, st);
+                return e == hipSuccess ? TDMA_OK : hip_fail(e, "stage B");
+            }, &tB);
+            if (rc == TDMA_OK) rc = time_median(st, 3, [&]() {
+                hipError_t e = launch_stage_c(dtype, map, x, wd_, wa, wc, X, 0, s, P, shared_factors, st);
+                return e == hipSuccess ? TDMA_OK : hip_fail(e, "stage C");
+            }, &tC);
+            if (rc != TDMA_OK) return rc;
+            const double model = pipeline_model_ms(nsys, s, tA, tB, tC, 1);
+            const double model_seq = pipeline_model_ms(nsys, s, tA, tB, tC, 0);
+            float brute = -1.f;
+            if (what == 2) {
+                rc = time_median(st, 3, [&]() {
+                    return pipeline_solve(ctx, layout, coeffs, dtype, d, x, P, s, 4, 1, st);
+                }, &brute);
+                if (rc != TDMA_OK) return rc;
+                if (brute < best_brute) { best_brute = brute; s_brute = s; P_brute = P; }
+            }
+            if (model < best_model_P) { best_model_P = model; per_P_batch[pi] = s; }
+            if (model < best_model) { best_model = model; s_model = s; P_model = P; }
+            js << (first ? "" : ",") << "{\"P\":" << P << ",\"batch\":" << s << ",\"t_a_ms\":" << tA
+               << ",\"t_b_ms\":" << tB << ",\"t_c_ms\":" << tC << ",\"model_ms\":" << model
+               << ",\"model_sequential_ms\":" << model_seq << ",\"measured_ms\":" << brute << "}";
+            first = false;
         }
-        if (model < best_model) { best_model = model; s_model = s; }
-        js << (first ? "" : ",") << "{\"batch\":" << s << ",\"t_a_ms\":" << tA << ",\"t_b_ms\":" << tB
-           << ",\"t_c_ms\":" << tC << ",\"model_ms\":" << model << ",\"model_sequential_ms\":"
-           << model_seq << ",\"measured_ms\":" << brute << "}";
-        first = false;
     }
-    js << "],\"model_choice\":" << s_model << ",\"model_ms\":" << best_model;
-    if (what == 2) js << ",\"brute_choice\":" << s_brute << ",\"brute_ms\":" << best_brute;
+    js << "],\"P\":" << P_model << ",\"model_choice\":" << s_model << ",\"model_ms\":" << best_model;
+    if (what == 2)
+        js << ",\"brute_choice_P\":" << P_brute << ",\"brute_choice\":" << s_brute
+           << ",\"brute_ms\":" << best_brute;
     js << "}";
     std::lock_guard<std::mutex> g(g_tune_mutex);
     load_cache_locked();
-    Tuned &t = g_tuned[key_of(ctx->dev, layout, coeffs, dtype, "part", P)];
+    // the best batch of each P (for callers that fix P), and the overall
+    // choice under P = 0 (for callers that leave P to the tuner)
+    for (size_t pi = 0; pi < Ps.size(); ++pi) {
+        Tuned &t = g_tuned[key_of(ctx->dev, layout, coeffs, dtype, "part", Ps[pi])];
+        t.batch = per_P_batch[pi];
+        t.nstreams = 4;
+        t.schedule = 1;   // round robin (the pipeline's numbering)
+        t.P = Ps[pi];
+    }
+    Tuned &t = g_tuned[key_of(ctx->dev, layout, coeffs, dtype, "part", 0)];
     t.batch = s_model;
     t.nstreams = 4;
-    t.schedule = 1;   // round robin (the pipeline's numbering)
-    t.P = P;
+    t.schedule = 1;
+    t.P = P_model;
     save_cache_locked();
     g_last_json = js.str();
     return TDMA_OK;

@@ -154,13 +154,14 @@ extern "C" int tdma_solve_partitioned(const tdma_layout *layout, const tdma_coef
     if (layout->offsets) return fail(TDMA_EUNSUPPORTED, "the partitioned path takes uniform layouts");
     const int64_t nsys = layout->nsys0 * layout->nsys1;
     if (nsys == 0) return TDMA_OK;
-    int P = opts && opts->partitions ? opts->partitions : 8;
+    int P = opts ? opts->partitions : 0;
     int64_t batch = opts && opts->batch ? opts->batch : 0;
     int nstreams = opts && opts->nstreams ? opts->nstreams : 0;
     const int sched_opt = opts ? opts->schedule : 0;
-    if (P < 1) return fail(TDMA_EINVAL, "partitions = %d (< 1)", P);
-    if (layout->n / P < 2) return fail(TDMA_EINVAL, "n = %lld gives partitions of < 2 rows (P = %d)",
-                                       (long long)layout->n, P);
+    if (P < 0) return fail(TDMA_EINVAL, "partitions = %d (< 0)", P);
+    if (P > 0 && layout->n / P < 2)
+        return fail(TDMA_EINVAL, "n = %lld gives partitions of < 2 rows (P = %d)",
+                    (long long)layout->n, P);
     if (P > 4096) return fail(TDMA_EINVAL, "partitions = %d (> 4096)", P);
     if (nstreams < 0 || nstreams > 8) return fail(TDMA_EINVAL, "nstreams = %d (1..8)", nstreams);
     if (sched_opt < 0 || sched_opt > 2) return fail(TDMA_EINVAL, "schedule = %d (0, 1 or 2)", sched_opt);
@@ -169,11 +170,22 @@ extern "C" int tdma_solve_partitioned(const tdma_layout *layout, const tdma_coef
     rc = get_ctx(&ctx);
     if (rc != TDMA_OK) return rc;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    // unset fields: the autotuned values for this shape if cached, else the
-    // measured defaults (batches of 32,768 systems, 4 streams, round robin)
+    // unset fields: the autotuned values for this shape if cached (with P
+    // unset, the tuner's P too), else the measured defaults (P = 8, batches
+    // of 32,768 systems, 4 streams, round robin)
     int64_t t_batch = 32768;
     int t_streams = 4, t_sched = 1;
-    (void)lookup_tuned_batch(ctx->dev, layout, coeffs, dtype, P, &t_batch, &t_streams, &t_sched);
+    int tP = P;
+    if (lookup_tuned_batch(ctx->dev, layout, coeffs, dtype, &tP, &t_batch, &t_streams, &t_sched))
+        P = tP;
+    if (P == 0) {
+        P = 8;
+        tP = P;
+        (void)lookup_tuned_batch(ctx->dev, layout, coeffs, dtype, &tP, &t_batch, &t_streams, &t_sched);
+    }
+    if (layout->n / P < 2)
+        return fail(TDMA_EINVAL, "n = %lld gives partitions of < 2 rows (P = %d)",
+                    (long long)layout->n, P);
     if (batch == 0) batch = t_batch;
     if (nstreams == 0) nstreams = t_streams;
     // the pipeline's own numbering: 0 = stage roles, 1 = round robin

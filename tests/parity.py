@@ -12,17 +12,21 @@ from workloads import configs
 TOL_F64 = 1e-12      # FP64 bar (relative, per system, infinity norm)
 TOL_F32 = 1e-5       # plain FP32 bar
 TOL_REFINED = 1e-12  # FP32 sweeps + FP64 refinement
-# Ill-conditioned systems (the lowest FFT-Poisson modes, kappa up to ~6e9): the
-# forward error of any FP64 solve grows like kappa * eps, and the FP64 oracle's
-# own distance from the long-double oracle measures it.  Where that distance
-# exceeds bar / ILL_FACTOR, a candidate passes within ILL_FACTOR times it of
-# the long-double oracle (a partitioned solve carries a few times the error
-# constant of one Thomas sweep).  Well-conditioned systems keep the bar.
-ILL_FACTOR = 10.0
+# Ill-conditioned systems (the pinned FFT-Poisson mode (0, 0), kappa ~1e10 at
+# n = 1024): the forward error of any FP64 solve grows like kappa * eps, and
+# the FP64 oracle's own distance from the long-double oracle measures it.  A
+# system that misses the bar against the FP64 oracle passes if its error
+# against the long-double oracle is within max(bar, ILL_FACTOR * that
+# distance).  Well-conditioned systems keep the bar.  The factor is the
+# largest ratio (error vs long double) / (FP64 oracle vs long double) measured
+# on the modes where the rule decides (the pinned mode: 2.5 for the FP64
+# kernels, 3.1 for FP32 + refinement at n = 1024), times a margin of 1.5.
+ILL_FACTOR = 5.0
 
 
 def conditioned_error(x, a, b, c, d, tol):
-    """(passes, err_vs_fp64, err_vs_long_double, fp64_oracle_err) for one system."""
+    """(passes, err_vs_fp64, err_vs_long_double, fp64_oracle_err) for one
+    system; the last two are None when the FP64 oracle alone decides."""
     ref = oracle.thomas(a, b, c, d)
     err64 = float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
     if err64 <= tol:
@@ -35,8 +39,7 @@ def _ill_conditioned(x, ref, ref_ld, tol, err64):
     scale = np.max(np.abs(ref_ld))
     err_ld = float(np.max(np.abs(x - ref_ld)) / scale)
     e_orc = float(np.max(np.abs(ref - ref_ld)) / scale)
-    bar = max(tol, ILL_FACTOR * e_orc) if ILL_FACTOR * e_orc > tol else tol
-    return err_ld <= bar, err64, err_ld, e_orc
+    return err_ld <= max(tol, ILL_FACTOR * e_orc), err64, err_ld, e_orc
 
 
 def conditioned_error_complex(x, a, b, c, d, tol):
@@ -47,6 +50,62 @@ def conditioned_error_complex(x, a, b, c, d, tol):
         return True, err64, None, None
     ref_ld = oracle.thomas_complex(a, b, c, d, oracle.LONG_DOUBLE)
     return _ill_conditioned(x, ref, ref_ld, tol, err64)
+
+
+def low_modes(nx, ny, reach=3):
+    """[((kx, ky), system)] for every mode with |kx|, |ky| <= reach, (0, 0)
+    first, then by |kx| + |ky|."""
+    modes = [(kx, ky) for ky in range(-reach, reach + 1) for kx in range(-reach, reach + 1)]
+    modes.sort(key=lambda m: (m != (0, 0), abs(m[0]) + abs(m[1]), m))
+    return [(m, (m[0] % nx) + nx * (m[1] % ny)) for m in modes]
+
+
+def mode_table(label, rows, tol):
+    """Check and print one path's low modes.  rows: [((kx, ky), x, (a, b, c,
+    d), is_complex)].  Every mode gets its error against the FP64 oracle and
+    against the long-double oracle, the FP64 oracle's own distance from the
+    long-double one, and their ratio; a mode passes within the bar against
+    the FP64 oracle or under the conditioned rule.  Returns the table."""
+    table = []
+    print(f"{label}: mode, err vs FP64 oracle, err vs long double, FP64 oracle vs long double, "
+          f"ratio, rule", flush=True)
+    for m, x, (a, b, c, d), cplx in rows:
+        th = oracle.thomas_complex if cplx else oracle.thomas
+        ref = th(a, b, c, d)
+        ref_ld = th(a, b, c, d, oracle.LONG_DOUBLE)
+        e64 = float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
+        ok, _, eld, eorc = _ill_conditioned(x, ref, ref_ld, tol, e64)
+        ok = e64 <= tol or ok
+        rule = "bar" if e64 <= tol else "conditioned"
+        ratio = eld / eorc if eorc > 0 else float("inf")
+        print(f"  {m}: {e64:.3g} {eld:.3g} {eorc:.3g} {ratio:.3g} {rule}{'' if ok else ' FAIL'}")
+        table.append(dict(mode=m, vs_oracle=e64, vs_long_double=eld, oracle_vs_long_double=eorc,
+                          ratio=ratio, rule=rule, ok=ok))
+    bad = [r for r in table if not r["ok"]]
+    assert not bad, (label, bad)
+    return table
+
+
+def poisson_mode_rows(p, get, pin=None, reach=3):
+    """mode_table rows for the low modes of an FFT-Poisson problem (real or
+    two interleaved right-hand sides): get(problem, system) returns that
+    system's solution on the host (complex for the complex problems).  Mode
+    (0, 0) is taken from the pinned problem, or left out without one."""
+    nx, ny, _ = p.grid
+    cplx = p.nrhs == 2
+    rows = []
+    for m, s in low_modes(nx, ny, reach):
+        q, sys = (pin, 0) if s == 0 else (p, s)
+        if q is None:
+            continue
+        if cplx:
+            re, im = configs.system_rhs(q, sys)
+            b = q.b + (q.shift[sys] if q.shift is not None else 0.0)
+            inputs = (q.a, b, q.c, re + 1j * im)
+        else:
+            inputs = configs.system_inputs(q, sys)
+        rows.append((m, get(q, sys), inputs, cplx))
+    return rows
 
 
 def gather_rows(layout, arr):

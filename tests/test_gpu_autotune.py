@@ -1,6 +1,7 @@
 """Autotuner on the GPU: cached shapes keep parity, and the pipeline model's
-batch choice is close to the measured best (the paper reports <= 1.6% for its
-estimator; small problems here are noisier, so the bar is looser)."""
+choice of partition count and batch size is within 5% of the measured best
+(the paper reports <= 1.6% for its estimator at full size; this problem is a
+quarter of that and its timings are noisier)."""
 import numpy as np
 import pytest
 
@@ -40,10 +41,11 @@ def test_partitioned_autotune_model_vs_brute():
     rec = tdma.autotune(p.layout, coeffs, td, tx, what=2)
     cands = rec["candidates"]
     assert rec["path"] == "partitioned" and len(cands) >= 2
-    by_batch = {c["batch"]: c for c in cands}
-    chosen = by_batch[rec["model_choice"]]["measured_ms"]
+    assert sorted({c["P"] for c in cands}) == [2, 4, 8, 16, 32]
+    by_choice = {(c["P"], c["batch"]): c for c in cands}
+    chosen = by_choice[(rec["P"], rec["model_choice"])]["measured_ms"]
     print("autotune", rec)
-    assert chosen <= 1.25 * rec["brute_ms"], (chosen, rec["brute_ms"])
+    assert chosen <= 1.05 * rec["brute_ms"], (chosen, rec["brute_ms"])
     # the cached batch is used and keeps parity on sampled systems
     tx.fill_(float("nan"))
     tdma.solve_partitioned(p.layout, coeffs, td, tx)

@@ -21,11 +21,14 @@ def _sample(nsys, k=96, seed=3):
 
 
 def _check_sampled(p, x_dev, systems, tol, ld_ok=False):
-    """Oracle parity of sampled systems.  With ld_ok, an ill-conditioned
-    system whose FP64 oracle misses the bar against the long-double oracle
-    passes within parity.ILL_FACTOR times that oracle's own error."""
+    """Oracle parity of sampled systems.  With ld_ok, a system that misses the
+    bar against the FP64 oracle passes under the conditioned rule of
+    tests/parity.py (within max(bar, ILL_FACTOR x the FP64 oracle's own
+    error) of the long-double oracle).  Returns the largest error against the
+    FP64 oracle and, when the rule was used, the largest against the
+    long-double oracle."""
     x = x_dev.double()
-    worst = 0.0
+    worst64, worst_ld = 0.0, None
     for s in systems:
         a, b, c, d = configs.system_inputs(p, int(s))
         rows = torch.from_numpy(p.layout.sys_rows(int(s))).cuda()
@@ -35,14 +38,28 @@ def _check_sampled(p, x_dev, systems, tol, ld_ok=False):
             if eld is not None:
                 print(f"system {int(s)}: err vs FP64 oracle {e64:.2e}, vs long double {eld:.2e}, "
                       f"FP64 oracle vs long double {eorc:.2e}")
+                worst_ld = max(worst_ld or 0.0, eld)
             assert ok, (int(s), e64, eld, eorc)
-            worst = max(worst, e64 if eld is None else min(e64, eld))
+            worst64 = max(worst64, e64)
         else:
             ref = oracle.thomas(a, b, c, d)
-            worst = max(worst, np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+            worst64 = max(worst64, np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
     if not ld_ok:
-        assert worst <= tol, worst
-    return worst
+        assert worst64 <= tol, worst64
+    return worst64, worst_ld
+
+
+def _mode_table(label, p, pin, x_dev):
+    """The low modes (|kx|, |ky| <= 3 and the pinned one) of a full-size
+    Poisson result: both errors per mode, printed and checked."""
+    x = x_dev.double()
+
+    def get(q, s):
+        rows = torch.from_numpy(q.layout.sys_rows(int(s))).cuda()
+        if q.nrhs == 2:
+            return x[rows].cpu().numpy() + 1j * x[rows + 1].cpu().numpy()
+        return x[rows].cpu().numpy()
+    return parity.mode_table(label, parity.poisson_mode_rows(p, get, pin), parity.TOL_F64)
 
 
 def _sample_many(nsys, k=65536, seed=11, exclude=()):
@@ -158,6 +175,7 @@ def test_poisson_1024_cubed_fp64_and_refined():
     samp = _poisson_sample(p)
     _check_sampled(p, x, samp[samp != 0], parity.TOL_F64, ld_ok=True)
     _check_sampled(pin, x, [0], parity.TOL_F64, ld_ok=True)
+    _mode_table("1024^3 FP64", p, pin, x)
     _poisson_bulk_check(p, x, parity.TOL_F64, "poisson FP64")
     x.fill_(float("nan"))
     rep = tdma.solve_refined(p.layout, co, d, x)
@@ -167,6 +185,7 @@ def test_poisson_1024_cubed_fp64_and_refined():
     print("refine report", rep)
     _check_sampled(p, x, samp[samp != 0], parity.TOL_REFINED, ld_ok=True)
     _check_sampled(pin, x, [0], parity.TOL_REFINED, ld_ok=True)
+    _mode_table("1024^3 FP32 + refinement (defaults)", p, pin, x)
     # the benchmark's setting: two steps judged by the contraction between
     # the two corrections, at tol 1e-13 (the predicted error is an estimate:
     # at tol 1e-12 a mode was accepted at 1.2e-12)
@@ -178,6 +197,7 @@ def test_poisson_1024_cubed_fp64_and_refined():
     print("refine report (2 steps, tol 1e-13, criterion 1)", rep)
     _check_sampled(p, x, samp[samp != 0], parity.TOL_REFINED, ld_ok=True)
     _check_sampled(pin, x, [0], parity.TOL_REFINED, ld_ok=True)
+    _mode_table("1024^3 FP32 + refinement (2 steps, tol 1e-13, criterion 1)", p, pin, x)
     _poisson_bulk_check(p, x, parity.TOL_REFINED, "poisson refined (2 steps, criterion 1)")
     del d, co, x
     torch.cuda.empty_cache()
@@ -221,9 +241,6 @@ def test_sweeps_full_size_one_by_one():
     assert err.max() <= parity.TOL_F64, err.max()
 
 
-@pytest.mark.skip(reason="the first run of this full-size case (with an earlier batching-form "
-                  "design that waited on the device between workgroups) went silent for 180 s "
-                  "and was stopped; no cause was shown, so the case stays off the GPU for now")
 def test_sweeps_and_ragged_graph_full_size():
     """768x512x1536 x->y->z sweeps chained in one graph beside the
     10,000-system ragged batch; sampled lines of each sweep are checked
@@ -243,11 +260,21 @@ def test_sweeps_and_ragged_graph_full_size():
                            dict(layout=pz.layout, coeffs=sh(pz), d=u2, x=u3, after=1),
                            dict(layout=rg.layout, coeffs=dict(mode=0, a=dev(ra), b=dev(rb), c=dev(rc)),
                                 d=td, x=tx)])
+    print("graph created; first launch", flush=True)
+    g.launch()
+    tdma.check()
+    for t in (u1, u2, u3, tx):
+        assert torch.isfinite(t).all()
+    # a replay on unchanged inputs gives the same bits
+    first = [t.clone() for t in (u3, tx)]
+    print("second launch", flush=True)
     g.launch()
     tdma.check()
     g.destroy()
-    for t in (u1, u2, u3, tx):
-        assert torch.isfinite(t).all()
+    for t, f in zip((u3, tx), first):
+        assert torch.equal(t, f)
+    del first
+    print("oracle checks", flush=True)
     for p, din, xout in ((px, R, u1), (py, u1, u2), (pz, u2, u3)):
         dh = din
         worst = 0.0
@@ -294,7 +321,7 @@ def test_poisson_complex_1024_cubed():
     # the lowest modes and the pinned mode, one by one
     low = _poisson_low(p)
     _, rows = got_rows(low)
-    worst = 0.0
+    worst64, worst_ld = 0.0, 0.0
     for s, got in zip(low, rows):
         re, im = configs.system_rhs(p, int(s))
         if s == 0:
@@ -306,9 +333,12 @@ def test_poisson_complex_1024_cubed():
         if eld is not None:
             print(f"mode {int(s)}: {e64:.2e} vs FP64 oracle, {eld:.2e} vs long double, "
                   f"oracle {eorc:.2e}")
+            worst_ld = max(worst_ld, eld)
         assert ok, (int(s), e64, eld, eorc)
-        worst = max(worst, e64 if eld is None else min(e64, eld))
-    print(f"complex low modes: {low.size}, worst {worst:.3e}", flush=True)
+        worst64 = max(worst64, e64)
+    print(f"complex low modes: {low.size}, worst vs FP64 oracle {worst64:.3e}, worst vs "
+          f"long double where the conditioned rule decided {worst_ld:.3e}", flush=True)
+    _mode_table("1024^3 FP64 complex (two right-hand sides)", p, pin, x)
     # the bulk, vectorised
     systems = _sample_many(lay.nsys, exclude=low)
     idx, got = got_rows(systems)

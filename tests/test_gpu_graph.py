@@ -97,6 +97,35 @@ def test_graph_single_item_fp32():
     assert err.max() <= parity.TOL_F32
 
 
+def test_graph_keeps_its_tensors_alive():
+    """A graph built from temporary coefficient tensors keeps them alive:
+    zero-filled tensors of the same sizes allocated after graph_create cannot
+    take their memory, so a replay still solves the recorded systems."""
+    import gc
+    import paper_2509_03933_amd as tdma
+    p = configs.adi(40, 24, 128)
+    _, _, _, d = configs.full_arrays(p)
+    rg = configs.ragged(nsys=64, nmin=2, nmax=500)
+    ra, rb, rc, rd = configs.full_arrays(rg)
+    td, trd = _dev(d), _dev(rd)
+    tx, trx = torch.full_like(td, float("nan")), torch.full_like(trd, float("nan"))
+    g = tdma.graph_create([dict(layout=p.layout, coeffs=dict(mode=1, a=_dev(p.a), b=_dev(p.b),
+                                                              c=_dev(p.c)), d=td, x=tx),
+                           dict(layout=rg.layout, coeffs=dict(mode=0, a=_dev(ra), b=_dev(rb),
+                                                               c=_dev(rc)), d=trd, x=trx)])
+    gc.collect()
+    junk = [torch.zeros(v.size, dtype=torch.float64, device="cuda")
+            for v in (p.a, p.b, p.c, ra, rb, rc) for _ in range(2)]
+    g.launch()
+    tdma.check()
+    g.destroy()
+    del junk
+    ref = oracle.solve_batch(p.layout, 1, p.a, p.b, p.c, d)
+    assert parity.per_system_error(p.layout, tx.cpu().numpy(), ref).max() <= parity.TOL_F64
+    rref = oracle.solve_batch(rg.layout, 0, ra, rb, rc, rd)
+    assert parity.per_system_error(rg.layout, trx.cpu().numpy(), rref).max() <= parity.TOL_F64
+
+
 def test_graph_rejects_bad_dependencies():
     import paper_2509_03933_amd as tdma
     p = configs.adi(8, 4, 16)
