@@ -15,7 +15,8 @@ working set is far larger than the 256 MB Infinity Cache).
 Other workloads (measurement of the remaining configurations):
   adi          ADI viscous z-sweep of a 256^3 grid (shared tanh-grid operator),
                FP64 and FP32+refine, PDD leg, same-pattern copy
-  partitioned  1024^3 per-row z-lines, tdma_solve_partitioned (P = 8, 4 streams)
+  partitioned  1024^3 per-row z-lines, tdma_solve_batched (walking per-row kernel),
+               the staged tdma_solve_partitioned (P = 8, 4 streams) beside it
   poisson_complex  the Poisson lines with complex right-hand sides (interleaved
                re/im pairs), FP64, tdma_solve_multi with two right-hand sides
                per system; unknowns are complex unknowns (32 B each)
@@ -25,6 +26,7 @@ Other workloads (measurement of the remaining configurations):
   sweeps       768x512x1536 x->y->z ADI sweeps + 10,000 ragged systems recorded
                into one hipGraph (dependent chain + independent ragged branch)
   plain        64 contiguous systems of n = 256
+  ragged       the 10,000 ragged systems alone (tdma_solve_batched)
   autotune     the autotuner on the partitioned configuration (model choice
                of the batch size against brute force), then the tuned solve
 
@@ -75,8 +77,9 @@ KERNEL_SOURCES = {
     "k_shared_refine": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
     "k_shared_refine_walk": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
     "k_fused": [CSRC + "fused.hip", CSRC + "fused_tile.hip.h", CSRC + "tile.hip.h"],
-    "k_shift_stream": [CSRC + "shifted.hip", CSRC + "tile.hip.h"],
-    "k_shift_refine": [CSRC + "shifted.hip", CSRC + "tile.hip.h", CSRC + "refine.h"],
+    "k_shift_stream": [CSRC + "shifted.hip", CSRC + "tile.hip.h", CSRC + "walk.hip.h"],
+    "k_shift_refine": [CSRC + "shifted.hip", CSRC + "tile.hip.h", CSRC + "refine.h", CSRC + "walk.hip.h"],
+    "k_perrow_stream": [CSRC + "perrow.hip", CSRC + "tile.hip.h", CSRC + "walk.hip.h"],
     "k_refine": [CSRC + "refine.hip", CSRC + "tile.hip.h"],
     "k_multi": [CSRC + "multi.hip", CSRC + "tile.hip.h"],
     "k_stage_a": [CSRC + "partitioned.hip", CSRC + "tile.hip.h"],
@@ -114,7 +117,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="poisson",
                     choices=["adi", "partitioned", "poisson", "poisson_complex", "poisson_fft", "sweeps",
-                             "plain", "autotune"])
+                             "plain", "autotune", "ragged"])
     ap.add_argument("--grid", default=None, help="override the grid, e.g. 256,256,256")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--batch", type=int, default=0, help="partitioned: systems per batch")
@@ -280,6 +283,10 @@ def bench_adi(args):
 
 
 def bench_partitioned(args):
+    """The per-row z-lines of a 1024^3 grid (2^20 systems of n = 1024, a, b,
+    c and d per row, rows 8 MB apart): the fused solve (tdma_solve_batched,
+    whose plan takes the walking per-row kernel) is the headline; the staged
+    pipeline (tdma_solve_partitioned, P = 8, 4 streams) is timed beside it."""
     import torch
     import paper_2509_03933_amd as tdma
     from workloads import configs, device
@@ -289,19 +296,25 @@ def bench_partitioned(args):
     x = torch.empty_like(d)
     lay = p.layout
     st = torch.cuda.current_stream()
-    ms = timed(lambda i: tdma.solve_partitioned(lay, coeffs, d, x, partitions=8, batch=args.batch,
-                                                nstreams=4, stream=st), args.steps, args.warmup, st)
+    ms = timed(lambda i: tdma.solve_batched(lay, coeffs, d, x, stream=st), args.steps, args.warmup, st)
     unknowns = lay.unknowns()
     samp = sample_systems(lay.nsys, 62)
     checks = [check(("max_rel_err_vs_oracle",), p, samp, grab_rows(p, x, samp))]
+    ms_s = timed(lambda i: tdma.solve_partitioned(lay, coeffs, d, x, partitions=8, batch=args.batch,
+                                                  nstreams=4, stream=st), args.steps, args.warmup, st)
+    checks.append(check(("staged", "max_rel_err_vs_oracle"), p, samp, grab_rows(p, x, samp)))
     return p, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
                "dtype": "f64",
-               "config": {"workload": f"partitioned_zlines_{nx}x{ny}x{nz}", "systems": lay.nsys,
-                          "n": lay.n, "partitions": 8, "streams": 4, "batch": args.batch or "default",
-                          "entry_point": "tdma_solve_partitioned"},
+               "config": {"workload": f"perrow_zlines_{nx}x{ny}x{nz}", "systems": lay.nsys,
+                          "n": lay.n, "entry_point": "tdma_solve_batched"},
                "max_rel_err_vs_oracle": None,
-               "roofline": roofline(40 * unknowns, ms, "k_stage_a", f"partitioned{nx}x{ny}x{nz}_f64",
-                                   note="whole staged solve: 32 batches x (Stage A, B, C)")}, checks
+               "roofline": roofline(40 * unknowns, ms, "k_perrow_stream", f"k_perrow_stream_perrow{nx}x{ny}x{nz}_f64"),
+               "staged": {"value": round(unknowns / (ms_s * 1e-3) / 1e9, 3), "ms_per_step": round(ms_s, 6),
+                          "partitions": 8, "streams": 4, "batch": args.batch or "default",
+                          "entry_point": "tdma_solve_partitioned", "max_rel_err_vs_oracle": None,
+                          "roofline": roofline(40 * unknowns, ms_s, "k_stage_a",
+                                               f"partitioned{nx}x{ny}x{nz}_f64",
+                                               note="whole staged solve: batches x (Stage A, B, C)")}}, checks
 
 
 def bench_autotune(args):
@@ -337,6 +350,7 @@ def bench_autotune(args):
                             "brute_ms": rec["brute_ms"],
                             "model_over_brute": round(chosen / rec["brute_ms"], 4),
                             "candidates": [{k: c[k] for k in ("P", "batch", "t_a_ms", "t_b_ms", "t_c_ms",
+                                                              "t_a_k_ms", "t_b_k_ms", "t_c_k_ms",
                                                               "model_ms", "measured_ms")}
                                            for c in rec["candidates"]]},
                "max_rel_err_vs_oracle": None,
@@ -585,6 +599,35 @@ def bench_sweeps(args):
                 "roofline": roofline(bytes_step, ms, "graph", f"graph_sweeps{nx}x{ny}x{nz}_f64")}, checks
 
 
+def bench_ragged(args):
+    """The 10,000 ragged systems alone (32..8192 rows, log-uniform lengths,
+    per-row coefficients, contiguous rows): tdma_solve_batched, whose plan
+    buckets the systems by length; every system checked against the oracle
+    in the oracle leg."""
+    import numpy as np
+    import torch
+    import paper_2509_03933_amd as tdma
+    from workloads import configs
+    rg = configs.ragged()
+    ra, rb, rc, rd = configs.full_arrays(rg)
+    dev = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    co = dict(mode=0, a=dev(ra), b=dev(rb), c=dev(rc))
+    td = dev(rd)
+    tx = torch.empty_like(td)
+    st = torch.cuda.current_stream()
+    ms = timed(lambda i: tdma.solve_batched(rg.layout, co, td, tx, stream=st), args.steps, args.warmup, st)
+    unknowns = rg.layout.unknowns()
+    checks = [{"path": ("max_rel_err_vs_oracle",), "kind": "ragged", "p": rg,
+               "systems": np.arange(rg.layout.nsys), "x": tx.cpu().numpy()}]
+    return rg, {"value": round(unknowns / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 6),
+                "dtype": "f64",
+                "config": {"workload": f"ragged_{rg.layout.nsys}_systems_32_to_8192_rows",
+                           "unknowns": unknowns, "entry_point": "tdma_solve_batched"},
+                "max_rel_err_vs_oracle": None,
+                "roofline": roofline(40 * unknowns, ms, "k_fused", "k_fused_ragged10000_f64",
+                                     note="one solve: a launch per length bucket")}, checks
+
+
 def bench_plain(args):
     import torch
     import paper_2509_03933_amd as tdma
@@ -816,7 +859,8 @@ def main():
         return
     fn = {"adi": bench_adi, "partitioned": bench_partitioned, "poisson": bench_poisson,
           "poisson_complex": bench_poisson_complex, "poisson_fft": bench_poisson_fft,
-          "sweeps": bench_sweeps, "plain": bench_plain, "autotune": bench_autotune}[args.workload]
+          "sweeps": bench_sweeps, "plain": bench_plain, "autotune": bench_autotune,
+          "ragged": bench_ragged}[args.workload]
     p, res, checks = fn(args)
     out = {"metric": METRIC, "value": res.pop("value"), "unit": "G unknowns/s", "n_gpus": 1,
            "steps": res.pop("steps", args.steps), "warmup": args.warmup,

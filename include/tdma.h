@@ -125,7 +125,16 @@ int tdma_solve_batched(const tdma_layout *layout, const tdma_coeffs *coeffs, int
  * current one.  With contiguous rows it streams when the systems are
  * consecutive (system k at element k*n) and otherwise runs as kernel 1, with
  * the same results; with contiguous rows its lanes are capped at 512 when M
- * rows fill 128 bytes and 256 when they fill 256.  Uniform layouts only.
+ * rows fill 128 bytes and 256 when they fill 256.  kernel 3 (shared operator
+ * with b_shift, strided rows): M = 8, 16, 32, P a power of two <= 64, at most
+ * 1024 lanes (512 at M = 32 in FP64); workgroups walk the tiles and load the
+ * next tile's right-hand sides as the current one's rows are stored (when
+ * P*M = n; otherwise as kernel 4).  kernel 4: kernel 3 loading each tile at
+ * its start.  kernel 5 (per-row coefficients, TDMA_COEF_LIKE_D without
+ * b_shift, strided rows): M = 16 or 32, P a power of two 2..64, at most 1024
+ * lanes (512 at M = 32); workgroups walk the tiles, each lane
+ * consuming its rows through a window of loads in flight.  Kernels 3-5 take
+ * fewer than 2^31 / 3 systems.  Uniform layouts only.
  * Errors: EINVAL for a shape outside these rules or with M*P < n.
  */
 typedef struct tdma_tile {

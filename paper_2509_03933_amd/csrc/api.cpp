@@ -299,15 +299,54 @@ static bool default_shift_shape(int dtype, int64_t n, int64_t nsys, TileShape *o
     return false;
 }
 
+// Per-row coefficients on strided layouts: the walking kernel with 128-byte
+// tile rows (16 FP64 systems; 16 FP32 systems, 64 bytes).  32 rows per lane
+// (512 lanes) where n is at least 512, else 16; shapes whose partitions cover
+// n exactly (no padding rows) first.  On the 1024^3 per-row z-lines (FP64):
+// 32 rows per lane 10.2 ms, 16 rows 12.6 ms, 16 rows with 64-byte tile rows
+// 20.4 ms.
+static bool default_perrow_shape(int dtype, int64_t n, int64_t nsys, TileShape *out) {
+    const int Ms[] = {32, 16};
+    TileShape best;
+    bool found = false, best_full = false;
+    for (int M : Ms) {
+        if (M == 32 && n < 512) continue;
+        int64_t P = 2;
+        while (P * M < n) P <<= 1;
+        if (P > 64) continue;
+        TileShape sh;
+        sh.kernel = 5;
+        sh.M = M;
+        sh.P = (int)P;
+        sh.contig = false;
+        const int64_t maxt = M == 32 ? 512 : 1024;
+        int S_log2 = 4;
+        while (S_log2 > 0 && ((int64_t)1 << S_log2) * P > maxt) --S_log2;
+        while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= nsys) --S_log2;
+        sh.S_log2 = S_log2;
+        if (!perrow_supported(dtype, sh)) continue;
+        const bool full = P * M == n;
+        if (!found || (full && !best_full)) {
+            best = sh;
+            best_full = full;
+            found = true;
+        }
+    }
+    if (found) *out = best;
+    return found;
+}
+
 // Ragged layout: systems are bucketed by the power-of-two partition count
 // they need; one launch per non-empty bucket (contiguous rows, LDS-staged).
 // build_ragged_plan allocates the plan's device tables and uploads them
 // synchronously; the caller owns them (free_ragged_plan).
-// Bucket of a ragged system of len rows: M rows per lane (16 in FP64 up to
-// 3,072 rows and 8 beyond, where more lanes per system measured faster; 32
-// and 16 in FP32 at 6,144 rows), P the power of two that covers len / M.
+// Bucket of a ragged system of len rows: M rows per lane (16 in FP64, up to
+// 8,192 rows; 32 and 16 in FP32 at 6,144 rows), P the power of two that
+// covers len / M.  With the four per-row arrays loaded at once and staged
+// without bank conflicts, 16 rows per lane measured faster than 8 on the
+// longest systems (6,144 rows: 118 against 143 us for 1,245 systems).
 static void ragged_bucket(int dtype, int64_t len, int *M_out, int *P_out) {
-    const int M = dtype == TDMA_F64 ? (len <= 3072 ? 16 : 8) : (len <= 6144 ? 32 : 16);
+    const int M = dtype == TDMA_F64 ? 16 : (len <= 6144 ? 32 : 16);
     const int64_t P = (len + M - 1) / M;
     int64_t Pb = 1;
     while (Pb < P) Pb <<= 1;
@@ -459,13 +498,14 @@ int launch_ragged(const RaggedPlan &rp, const tdma_layout *L, const tdma_coeffs 
 
 // Whether a tile shape can run a uniform layout with these coefficients.
 static bool shape_fits(int dtype, const tdma_layout *L, bool shared_op, const TileShape &sh,
-                       bool shifted_op) {
+                       bool shifted_op, bool perrow_op) {
     if ((int64_t)sh.P * sh.M < L->n) return false;
     if (sh.kernel == 3 || sh.kernel == 4) {
         if (!shifted_op || !shift_supported(dtype, sh)) return false;
         const SysMap m = make_map(L);
         return shift_layout_ok(m, sh);
     }
+    if (sh.kernel == 5) return perrow_op && perrow_supported(dtype, sh) && perrow_layout_ok(make_map(L), sh);
     if (sh.kernel == 1 || sh.kernel == 2) return shared_op && shared_supported(dtype, sh);
     if (sh.kernel != 0 || !fused_supported(dtype, sh)) return false;
     return !(sh.contig && fused_lds_bytes(dtype, sh) > 160 * 1024);
@@ -482,6 +522,7 @@ int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int
     const bool contig = L->row_stride == 1;
     const bool shared_op = C->mode == TDMA_COEF_SHARED && C->b_shift == nullptr;
     const bool shifted_op = C->mode == TDMA_COEF_SHARED && C->b_shift != nullptr;
+    const bool perrow_op = C->mode == TDMA_COEF_LIKE_D && C->b_shift == nullptr;
     if (force) {
         sh = *force;
         if ((int64_t)sh.P * sh.M < L->n)
@@ -493,14 +534,20 @@ int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int
         if ((sh.kernel == 3 || sh.kernel == 4) && !shifted_op)
             return fail(TDMA_EINVAL, "the shifted-operator kernel needs shared coefficients with "
                         "a shift (M=%d P=%d S=%d)", sh.M, sh.P, 1 << sh.S_log2);
-        if (!shape_fits(dtype, L, shared_op, sh, shifted_op))
+        if (sh.kernel == 5 && !perrow_op)
+            return fail(TDMA_EINVAL, "the per-row kernel needs per-row coefficients without a "
+                        "shift (M=%d P=%d S=%d)", sh.M, sh.P, 1 << sh.S_log2);
+        if (!shape_fits(dtype, L, shared_op, sh, shifted_op, perrow_op))
             return fail(TDMA_EINVAL, "unsupported tile shape M=%d P=%d S=%d (kernel %d)", sh.M, sh.P,
                         1 << sh.S_log2, sh.kernel);
     } else if (!(lookup_tuned(ctx->dev, L, C, dtype, &sh) && sh.contig == contig &&
-                 shape_fits(dtype, L, shared_op, sh, shifted_op))) {
+                 shape_fits(dtype, L, shared_op, sh, shifted_op, perrow_op))) {
         TileShape ssh;
         if (shifted_op && !contig && default_shift_shape(dtype, L->n, nsys, &ssh) &&
             shift_layout_ok(make_map(L), ssh))
+            sh = ssh;
+        else if (perrow_op && !contig && default_perrow_shape(dtype, L->n, nsys, &ssh) &&
+                 perrow_layout_ok(make_map(L), ssh))
             sh = ssh;
         else if (!(shared_op && default_shared_shape(dtype, L->n, nsys, contig, &sh)) &&
                  !default_shape(dtype, L->n, nsys, contig, &sh))
@@ -519,6 +566,8 @@ int launch_uniform(const TileShape &sh, const tdma_layout *L, const tdma_coeffs 
     hipError_t e;
     if (sh.kernel == 3 || sh.kernel == 4)
         e = launch_shift(dtype, m, coef, sh, d, x, err, st);
+    else if (sh.kernel == 5)
+        e = launch_perrow(dtype, m, coef, sh, d, x, err, st);
     else if (sh.kernel != 0)
         e = launch_shared(dtype, m, coef, sh, d, x, err, st);
     else
@@ -608,11 +657,13 @@ int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeff
     while ((1 << sh.S_log2) < S) ++sh.S_log2;
     sh.contig = layout->row_stride == 1;
     sh.kernel = tile->kernel;
-    if (sh.kernel < 0 || sh.kernel > 4) return fail(TDMA_EINVAL, "unknown kernel %d", sh.kernel);
+    if (sh.kernel < 0 || sh.kernel > 5) return fail(TDMA_EINVAL, "unknown kernel %d", sh.kernel);
     if (sh.kernel == 0 && !fused_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported tile M=%d S=%d P=%d", sh.M, S, sh.P);
-    if (sh.kernel >= 3 && !shift_supported(dtype, sh))
+    if ((sh.kernel == 3 || sh.kernel == 4) && !shift_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported shifted-operator tile M=%d S=%d P=%d", sh.M, S, sh.P);
+    if (sh.kernel == 5 && !perrow_supported(dtype, sh))
+        return fail(TDMA_EINVAL, "unsupported per-row tile M=%d S=%d P=%d", sh.M, S, sh.P);
     if ((sh.kernel == 1 || sh.kernel == 2) && !shared_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported shared-operator tile M=%d S=%d P=%d", sh.M, S, sh.P);
     if ((int64_t)sh.M * sh.P < layout->n) return fail(TDMA_EINVAL, "tile covers %lld rows < n = %lld",

@@ -4,20 +4,22 @@
 // systems per tile S, partitions P) is timed with hipEvents on the caller's
 // buffers; the fastest is cached for this shape.
 //
-// Staged path (the paper's batch-size optimisation, Sec. 4.2.3): for each
-// partition count P (2..32, n/P >= 2) and each candidate batch size s
-// (powers of two from 2^12 to 2^18, clipped to the number of systems) the
-// mean time of Stage A, B and C on one batch is
-// measured with each stage run alone, and the total is predicted from the
-// pipelined schedule of Algorithm 2 with N_b = ceil(N/s) batches:
-//     T(s) = sum_{k=1}^{N_b+2} max([k <= N_b] t_A + [k >= 3] t_C, [2 <= k <= N_b+1] t_B)
-// i.e. Stage B overlapping A and C by concurrent kernel execution (one GPU
-// has no communication stages, so the comm-overlap-only schedule of the
-// paper's estimator would reduce to the plain sum of stage times, which is
-// recorded too; the remainder batch is costed at full size).  The argmin is
-// cached.  Mode 2
-// also runs the full pipeline for every candidate (brute force) and records
-// both, so the model's choice can be checked against the measured best.
+// Staged path (the paper's batch-size optimisation, Sec. 4.2.3: stage times
+// measured on their own, total predicted by a model of the pipelined
+// schedule): for each partition count P (2..32, n/P >= 2) and batch size s
+// (powers of two from 2^12 to 2^18, clipped to the number of systems), the
+// time of Stage A, B and C is measured for one batch alone and for K = 4
+// batches at once on the pipeline's streams, each repetition on other
+// batches (so no batch is served from the caches by the previous
+// repetition).  The model is the schedule the pipeline runs by default,
+// round robin over K streams (round_robin_model_ms): N_b = ceil(N/s)
+// batches in rounds of K.  The paper's Algorithm 2 model (pipeline_model_ms:
+// Stage B of batch k-1 beside A of batch k and C of batch k-2) is recorded
+// too; on one GPU its stage roles leave the concurrency of the streams out,
+// and with stage times of a batch alone it misranks the candidates.  The
+// argmin is cached.  Mode 2 also runs the full pipeline for every candidate
+// (brute force) and records both, so the model's choice can be checked
+// against the measured best.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,6 +47,9 @@ struct Tuned {
     int schedule = 0;
     int P = 0;
 };
+
+// streams of the staged pipeline the tuner tunes for (its default count)
+constexpr int kTuneStreams = 4;
 
 std::mutex g_tune_mutex;
 std::map<std::string, Tuned> g_tuned;
@@ -145,6 +150,28 @@ std::vector<TileShape> fused_candidates(int dtype, const tdma_layout *L, const t
             }
         }
     }
+    // the walking kernels of strided layouts: shifted shared operator
+    // (kernels 3, 4) and per-row coefficients (kernel 5)
+    const bool shifted_op = C->mode == TDMA_COEF_SHARED && C->b_shift != nullptr;
+    const bool perrow_op = C->mode == TDMA_COEF_LIKE_D && C->b_shift == nullptr;
+    if (!contig && (shifted_op || perrow_op)) {
+        const SysMap m = make_map(L);
+        for (int M : {8, 16, 32}) {
+            int P = 2;
+            while ((int64_t)P * M < n) P <<= 1;
+            if (P > 64) continue;
+            for (int S_log2 = 2; S_log2 <= 5; ++S_log2) {
+                for (int kind : {3, 4, 5}) {
+                    if ((kind == 5) != perrow_op) continue;
+                    TileShape sh;
+                    sh.kernel = kind; sh.M = M; sh.P = P; sh.S_log2 = S_log2; sh.contig = false;
+                    const bool ok = kind == 5 ? perrow_supported(dtype, sh) && perrow_layout_ok(m, sh)
+                                              : shift_supported(dtype, sh) && shift_layout_ok(m, sh);
+                    if (ok) out.push_back(sh);
+                }
+            }
+        }
+    }
     for (int M : {4, 8, 16, 32}) {
         const int64_t P0 = (n + M - 1) / M;
         int64_t P2 = 1;
@@ -211,6 +238,23 @@ double pipeline_model_ms(int64_t N, int64_t s, double tA, double tB, double tC, 
         const double b = (k >= 2 && k <= nb + 1) ? tB : 0.0;
         const double c = k >= 3 ? tC : 0.0;
         total += concurrent ? std::max(a + c, b) : a + b + c;
+    }
+    return total;
+}
+
+// Round-robin schedule (the pipeline's default): batch b runs A, B, C on
+// stream b mod K, so the K streams run K batches at a time.  t1[] are the
+// stage times of one batch alone, tK[] of K batches at once (one per
+// stream); a full round of K batches costs tK[A] + tK[B] + tK[C], and the
+// last, partial round of r batches costs max(t1, tK r / K) per stage (at
+// least one batch's time, at most a full round's).  The remainder batch is
+// costed at full size.
+double round_robin_model_ms(int64_t nb, int K, const float *t1, const float *tK) {
+    const int64_t rounds = nb / K, r = nb % K;
+    double total = 0.0;
+    for (int x = 0; x < 3; ++x) {
+        total += (double)rounds * tK[x];
+        if (r > 0) total += std::max((double)t1[x], (double)tK[x] * (double)r / K);
     }
     return total;
 }
@@ -285,7 +329,7 @@ int tdma_autotune(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtyp
     const Coef coef = make_coef(coeffs);
     const bool shared_factors = coeffs->mode == TDMA_COEF_SHARED && coeffs->b_shift == nullptr;
     const size_t esz = dtype == TDMA_F64 ? 8 : 4;
-    js << "{\"path\":\"partitioned\",\"candidates\":[";
+    js << "{\"path\":\"partitioned\",\"streams\":" << kTuneStreams << ",\"candidates\":[";
     double best_model = 1e300, best_brute = 1e300;
     int64_t s_model = sizes[0], s_brute = sizes[0];
     int P_model = Ps[0], P_brute = Ps[0];
@@ -295,50 +339,93 @@ int tdma_autotune(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtyp
         const int P = Ps[pi];
         double best_model_P = 1e300;
         for (int64_t s : sizes) {
-            // one batch worth of workspace (slot 0 of the pipeline workspace)
+            const int64_t nb = (nsys + s - 1) / s;
+            const int64_t nb_full = std::max<int64_t>(1, nsys / s);   // batches of exactly s systems
+            const int K = (int)std::min<int64_t>(kTuneStreams, nb);
+            // K batch workspaces (the layout of one pipeline slot each)
             const size_t fac = shared_factors ? (size_t)layout->n : (size_t)layout->n * s;
             const size_t fac_bytes = (fac * esz + 255) & ~(size_t)255;
             const size_t dh_bytes = ((size_t)layout->n * s * esz + 255) & ~(size_t)255;
             const size_t red_bytes = ((size_t)6 * P * s * 8 + 255) & ~(size_t)255;
             const size_t x_bytes = ((size_t)2 * P * s * 8 + 255) & ~(size_t)255;
+            const size_t slot_bytes = dh_bytes + 2 * fac_bytes + red_bytes + 2 * x_bytes;
             void *ws = nullptr;
-            rc = ctx->workspace(4, dh_bytes + 2 * fac_bytes + red_bytes + 2 * x_bytes, &ws);
+            rc = ctx->workspace(4, slot_bytes * K, &ws);
             if (rc != TDMA_OK) return rc;
-            char *wd_ = (char *)ws;
-            char *b = wd_ + dh_bytes;
-            void *wa = b, *wc = b + fac_bytes;
-            double *red = (double *)(b + 2 * fac_bytes), *X = (double *)(b + 2 * fac_bytes + red_bytes);
-            double *scr = (double *)(b + 2 * fac_bytes + red_bytes + x_bytes);
-            float tA = 0, tB = 0, tC = 0;
-            rc = time_median(st, 3, [&]() {
-                hipError_t e = launch_stage_a(dtype, map, coef, d, wd_, wa, wc, red, 0, s, P,
-                                              shared_factors, ctx->d_err, st);
-                return e == hipSuccess ? TDMA_OK : hip_fail(e, "stage A");
-            }, &tA);
-            if (rc == TDMA_OK) rc = time_median(st, 3, [&]() {
-                hipError_t e = launch_stage_b(red, X, scr, s, P, ctx->d_err, st);
-                return e == hipSuccess ? TDMA_OK : hip_fail(e, "stage B");
-            }, &tB);
-            if (rc == TDMA_OK) rc = time_median(st, 3, [&]() {
-                hipError_t e = launch_stage_c(dtype, map, x, wd_, wa, wc, X, 0, s, P, shared_factors, st);
-                return e == hipSuccess ? TDMA_OK : hip_fail(e, "stage C");
-            }, &tC);
+            struct Slot { void *wd, *wa, *wc; double *red, *X, *scr; };
+            std::vector<Slot> sl(K);
+            for (int i = 0; i < K; ++i) {
+                char *b = (char *)ws + slot_bytes * i;
+                sl[i].wd = b;
+                b += dh_bytes;
+                sl[i].wa = b;
+                sl[i].wc = b + fac_bytes;
+                sl[i].red = (double *)(b + 2 * fac_bytes);
+                sl[i].X = (double *)(b + 2 * fac_bytes + red_bytes);
+                sl[i].scr = (double *)(b + 2 * fac_bytes + red_bytes + x_bytes);
+            }
+            // every repetition takes other batches (full ones, so each stage
+            // reads what the previous stage wrote for it): a batch's data is
+            // not left in the caches by the previous repetition
+            int rep = 0;
+            auto batch_of = [&](int r, int i) { return (((int64_t)r * K + i) % nb_full) * s; };
+            auto stage = [&](int which, int i, int64_t k0, hipStream_t q) -> int {
+                hipError_t e;
+                if (which == 0)
+                    e = launch_stage_a(dtype, map, coef, d, sl[i].wd, sl[i].wa, sl[i].wc, sl[i].red, k0, s,
+                                       P, shared_factors, ctx->d_err, q);
+                else if (which == 1)
+                    e = launch_stage_b(sl[i].red, sl[i].X, sl[i].scr, s, P, ctx->d_err, q);
+                else
+                    e = launch_stage_c(dtype, map, x, sl[i].wd, sl[i].wa, sl[i].wc, sl[i].X, k0, s, P,
+                                       shared_factors, q);
+                return e == hipSuccess ? TDMA_OK : hip_fail(e, "autotune stage");
+            };
+            // one stage alone, and K instances of it at once on the pipeline's
+            // streams (what the round-robin schedule runs)
+            auto alone = [&](int which) {
+                return [&, which]() { return stage(which, 0, batch_of(rep++, 0), st); };
+            };
+            auto together = [&](int which) {
+                return [&, which]() -> int {
+                    hipStream_t *qs = nullptr;
+                    hipEvent_t *ev = nullptr;
+                    int r2 = ctx->get_streams(K, &qs);
+                    if (r2 == TDMA_OK) r2 = ctx->get_events(K + 1, &ev);
+                    if (r2 != TDMA_OK) return r2;
+                    hipError_t e = hipEventRecord(ev[0], st);
+                    for (int i = 0; i < K && e == hipSuccess; ++i) e = hipStreamWaitEvent(qs[i], ev[0], 0);
+                    if (e != hipSuccess) return hip_fail(e, "autotune fork");
+                    for (int i = 0; i < K && r2 == TDMA_OK; ++i) r2 = stage(which, i, batch_of(rep, i), qs[i]);
+                    ++rep;
+                    for (int i = 0; i < K && e == hipSuccess && r2 == TDMA_OK; ++i) {
+                        e = hipEventRecord(ev[1 + i], qs[i]);
+                        if (e == hipSuccess) e = hipStreamWaitEvent(st, ev[1 + i], 0);
+                    }
+                    if (r2 == TDMA_OK && e != hipSuccess) r2 = hip_fail(e, "autotune join");
+                    return r2;
+                };
+            };
+            float t1[3] = {0, 0, 0}, tK[3] = {0, 0, 0};
+            for (int which = 0; which < 3 && rc == TDMA_OK; ++which) rc = time_median(st, 5, alone(which), &t1[which]);
+            for (int which = 0; which < 3 && rc == TDMA_OK; ++which) rc = time_median(st, 5, together(which), &tK[which]);
             if (rc != TDMA_OK) return rc;
-            const double model = pipeline_model_ms(nsys, s, tA, tB, tC, 1);
-            const double model_seq = pipeline_model_ms(nsys, s, tA, tB, tC, 0);
+            const double model = round_robin_model_ms(nb, K, t1, tK);
+            const double model_alg2 = pipeline_model_ms(nsys, s, t1[0], t1[1], t1[2], 1);
             float brute = -1.f;
             if (what == 2) {
-                rc = time_median(st, 3, [&]() {
-                    return pipeline_solve(ctx, layout, coeffs, dtype, d, x, P, s, 4, 1, st);
+                rc = time_median(st, 5, [&]() {
+                    return pipeline_solve(ctx, layout, coeffs, dtype, d, x, P, s, kTuneStreams, 1, st);
                 }, &brute);
                 if (rc != TDMA_OK) return rc;
                 if (brute < best_brute) { best_brute = brute; s_brute = s; P_brute = P; }
             }
             if (model < best_model_P) { best_model_P = model; per_P_batch[pi] = s; }
             if (model < best_model) { best_model = model; s_model = s; P_model = P; }
-            js << (first ? "" : ",") << "{\"P\":" << P << ",\"batch\":" << s << ",\"t_a_ms\":" << tA
-               << ",\"t_b_ms\":" << tB << ",\"t_c_ms\":" << tC << ",\"model_ms\":" << model
-               << ",\"model_sequential_ms\":" << model_seq << ",\"measured_ms\":" << brute << "}";
+            js << (first ? "" : ",") << "{\"P\":" << P << ",\"batch\":" << s << ",\"t_a_ms\":" << t1[0]
+               << ",\"t_b_ms\":" << t1[1] << ",\"t_c_ms\":" << t1[2] << ",\"t_a_k_ms\":" << tK[0]
+               << ",\"t_b_k_ms\":" << tK[1] << ",\"t_c_k_ms\":" << tK[2] << ",\"model_ms\":" << model
+               << ",\"model_alg2_ms\":" << model_alg2 << ",\"measured_ms\":" << brute << "}";
             first = false;
         }
     }
@@ -354,13 +441,13 @@ int tdma_autotune(const tdma_layout *layout, const tdma_coeffs *coeffs, int dtyp
     for (size_t pi = 0; pi < Ps.size(); ++pi) {
         Tuned &t = g_tuned[key_of(ctx->dev, layout, coeffs, dtype, "part", Ps[pi])];
         t.batch = per_P_batch[pi];
-        t.nstreams = 4;
+        t.nstreams = kTuneStreams;
         t.schedule = 1;   // round robin (the pipeline's numbering)
         t.P = Ps[pi];
     }
     Tuned &t = g_tuned[key_of(ctx->dev, layout, coeffs, dtype, "part", 0)];
     t.batch = s_model;
-    t.nstreams = 4;
+    t.nstreams = kTuneStreams;
     t.schedule = 1;
     t.P = P_model;
     save_cache_locked();

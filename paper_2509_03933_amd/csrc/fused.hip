@@ -90,7 +90,7 @@ size_t fused_lds_bytes(int dtype, const TileShape &sh, bool shared_rows) {
     const size_t esz = dtype == TDMA_F64 ? 8 : 4;
     if (shared_rows)
         return fused_co_offset(esz, S, sh.P, sh.M, sh.contig) + 3 * (size_t)sh.P * sh.M * esz;
-    return fused_region0(esz, S, sh.P, sh.M, sh.contig) + (sh.contig ? (size_t)S * 16 : 0);
+    return fused_region0(esz, S, sh.P, sh.M, sh.contig, true) + (sh.contig ? (size_t)S * 16 : 0);
 }
 
 hipError_t launch_fused(int dtype, const SysMap &map, const Coef &coef, const TileShape &sh,

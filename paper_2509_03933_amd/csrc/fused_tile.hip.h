@@ -107,7 +107,7 @@ __device__ __forceinline__ void fused_tile(const SysMap &map, const Coef &coef, 
         }
     } else {
         const int R = P * M;
-        const int pitch = R + 1;
+        const int pitch = P * (M + 1) + 1;
         T *stg = reinterpret_cast<T *>(lds);
         const size_t stg_bytes = ((size_t)S * pitch * sizeof(T) + 15) & ~(size_t)15;
         const size_t pcr_bytes = dev::pcr_lds_bytes(S, P);
@@ -128,13 +128,12 @@ __device__ __forceinline__ void fused_tile(const SysMap &map, const Coef &coef, 
                 av[j] = A[r]; bv[j] = B[r]; cv[j] = C[r];
             }
         }
-        // one array at a time through the staging buffer
-        dev::stage_in<T, M>(stg, tsys, d, Ident<T>::d, S, R, pitch, invR, s, r0, dv);
         if constexpr (LIKE_D) {
-            dev::stage_in<T, M>(stg, tsys, A, Ident<T>::a, S, R, pitch, invR, s, r0, av);
-            dev::stage_in<T, M>(stg, tsys, B, Ident<T>::b, S, R, pitch, invR, s, r0, bv);
-            dev::stage_in<T, M>(stg, tsys, C, Ident<T>::c, S, R, pitch, invR, s, r0, cv);
+            // the four arrays' loads in flight together, then through the
+            // staging buffer one after the other
+            dev::stage_in4_sw<T, M>(stg, tsys, A, B, C, d, S, R, pitch, invR, s, p, av, bv, cv, dv);
         } else {
+            dev::stage_in_sw<T, M>(stg, tsys, d, Ident<T>::d, S, R, pitch, invR, s, p, dv);
 #pragma unroll
             for (int j = 0; j < M; ++j)
                 if (r0 + j >= sys.nrows) {
@@ -175,13 +174,13 @@ __device__ __forceinline__ void fused_tile(const SysMap &map, const Coef &coef, 
             if (j < rows_here) x[off0 + j * rs] = dv[j];
     } else {
         const int R = P * M;
-        const int pitch = R + 1;
+        const int pitch = P * (M + 1) + 1;
         T *stg = reinterpret_cast<T *>(lds);
         const size_t stg_bytes = ((size_t)S * pitch * sizeof(T) + 15) & ~(size_t)15;
         const size_t pcr_bytes = dev::pcr_lds_bytes(S, P);
         TileSysLds *tsys = reinterpret_cast<TileSysLds *>(
             reinterpret_cast<char *>(lds) + (stg_bytes > pcr_bytes ? stg_bytes : pcr_bytes));
-        stage_out<T, M>(stg, tsys, x, S, R, pitch, 1.0f / (float)R, s, r0, dv);
+        dev::stage_out_sw<T, M>(stg, tsys, x, S, R, pitch, 1.0f / (float)R, s, p, dv);
     }
     if (bad && sys.valid) atomicOr(err, 1);
 }
@@ -189,11 +188,15 @@ __device__ __forceinline__ void fused_tile(const SysMap &map, const Coef &coef, 
 
 // LDS layout of the fused tile: [0, region0) staging (contiguous rows) or the
 // Stage B scratch, whichever is larger; the contiguous-row system table; and,
-// for a shared operator held in LDS, its 3 x P*M coefficient rows.
-__host__ __device__ inline size_t fused_region0(size_t esz, int S, int P, int M, bool contig) {
+// for a shared operator held in LDS, its 3 x P*M coefficient rows.  The
+// generic tile stages with each lane's rows M+1 slots apart (sw, pitch
+// P*(M+1)+1), the shared-operator tile with pitch P*M+1.
+__host__ __device__ inline size_t fused_region0(size_t esz, int S, int P, int M, bool contig,
+                                                bool sw = false) {
     const size_t pcr = dev::pcr_lds_bytes(S, P);
     if (!contig) return pcr;
-    const size_t stg = ((size_t)S * ((size_t)P * M + 1) * esz + 15) & ~(size_t)15;
+    const size_t pitch = sw ? (size_t)P * (M + 1) + 1 : (size_t)P * M + 1;
+    const size_t stg = ((size_t)S * pitch * esz + 15) & ~(size_t)15;
     return stg > pcr ? stg : pcr;
 }
 

@@ -35,6 +35,7 @@
 
 #include "refine.h"
 #include "tile.hip.h"
+#include "walk.hip.h"
 
 namespace tdma {
 namespace {
@@ -67,25 +68,6 @@ __host__ __device__ inline ShiftLds shift_layout(size_t esz, int M, int P, int S
     return L;
 }
 
-// System of a lane in a uniform layout (fewer than 2^31 systems) stepped by
-// a fixed number of systems without a division per step.
-struct Walk {
-    int32_t k, s0, s1, q, r;
-    __device__ void init(int32_t nsys0, int32_t k0, int32_t step) {
-        k = k0;
-        s1 = k0 / nsys0;
-        s0 = k0 - s1 * nsys0;
-        q = step / nsys0;
-        r = step - q * nsys0;
-    }
-    __device__ void advance(int32_t nsys0, int32_t step) {
-        k += step;
-        s0 += r;
-        s1 += q;
-        if (s0 >= nsys0) { s0 -= nsys0; ++s1; }
-    }
-};
-
 // The tile's operator rows into LDS (once per workgroup), identity rows past n.
 template <typename T>
 __device__ __forceinline__ void build_rows(const Coef &coef, int64_t n, int M, int P, char *base,
@@ -103,97 +85,6 @@ __device__ __forceinline__ void build_rows(const Coef &coef, int64_t n, int M, i
         CM[q] = T2{in && r < n - 1 ? C[r] : T(0), in ? T(1) : T(0)};
     }
     __syncthreads();
-}
-
-// One PCR elimination step on a unit-diagonal row (a, c, d) with its
-// neighbours at distance h below (al, cl, dl) and above (au, cu, du);
-// renormalised to unit diagonal.  Missing neighbours are zero rows.
-__device__ __forceinline__ void pcr_step_row(double &a, double &c, double &d, double al, double cl,
-                                             double dl, double au, double cu, double du,
-                                             bool &bad) {
-    const double beta = 1.0 - a * cl - c * au;
-    bad |= dev::bad_pivot(beta);
-    const double ib = dev::recip(beta);
-    const double na = -a * al, nc = -c * cu, nd = d - a * dl - c * du;
-    a = na * ib;
-    c = nc * ib;
-    d = nd * ib;
-}
-
-// Stage B: the interface rows of the tile's S systems go through LDS to P
-// consecutive lanes per system (P a power of two <= 64), which run the PCR
-// steps with wavefront shuffles; the solution comes back through LDS.  For
-// a distance of two rows or more, row 2p meets only the neighbours' rows 2p
-// and row 2p+1 only their rows 2p+1, so the two rows are stepped one after
-// the other, which holds half the neighbour values at a time.  Every thread
-// of the block calls it; returns X_{2p} and X_{2p+1} of the caller's system.
-__device__ __forceinline__ void shift_pcr(double *XC, int S, int s, int p, int P, int P_log2,
-                                          const Iface &f, double &x_first, double &x_last,
-                                          bool &bad) {
-    const int R2 = 2 * P;
-    const int pitch = R2 + 1;
-    double *ra = XC, *rc = XC + S * pitch, *rd = XC + 2 * S * pitch;
-    __syncthreads();   // the exchange is free (previous tile done reading it)
-    {
-        const int q = s * pitch + 2 * p;
-        ra[q] = f.fa; rc[q] = f.fc; rd[q] = f.fd;
-        ra[q + 1] = f.la; rc[q + 1] = f.lc; rd[q + 1] = f.ld;
-    }
-    __syncthreads();
-    const int t = threadIdx.x;
-    const int s2 = t >> P_log2;
-    const int p2 = t & (P - 1);
-    const int q2 = s2 * pitch + 2 * p2;
-    double a0 = ra[q2], c0 = rc[q2], d0 = rd[q2];
-    double a1 = ra[q2 + 1], c1 = rc[q2 + 1], d1 = rd[q2 + 1];
-    const int lane = t & 63;
-    {
-        // distance 1: row 2p2 meets row 2p2-1 (lane-1) and its own row 2p2+1;
-        // row 2p2+1 meets its own row 2p2 and row 2p2+2 (lane+1)
-        const bool has_lo = p2 > 0, has_hi = p2 < P - 1;
-        const int lo = has_lo ? lane - 1 : lane, hi = has_hi ? lane + 1 : lane;
-        double am = __shfl(a1, lo), cm = __shfl(c1, lo), dm = __shfl(d1, lo);
-        double ap = __shfl(a0, hi), cp = __shfl(c0, hi), dp = __shfl(d0, hi);
-        if (!has_lo) { am = 0.0; cm = 0.0; dm = 0.0; }
-        if (!has_hi) { ap = 0.0; cp = 0.0; dp = 0.0; }
-        const double oa0 = a0, oc0 = c0, od0 = d0;
-        pcr_step_row(a0, c0, d0, am, cm, dm, a1, c1, d1, bad);
-        pcr_step_row(a1, c1, d1, oa0, oc0, od0, ap, cp, dp, bad);
-    }
-    for (int h = 2; h < R2; h <<= 1) {
-        const int dl = h >> 1;          // rows 2p2+e +- h live in lanes p2 +- h/2
-        const bool has_lo = p2 >= dl, has_hi = p2 + dl < P;
-        const int lo = has_lo ? lane - dl : lane, hi = has_hi ? lane + dl : lane;
-        {
-            double la = __shfl(a0, lo), lc = __shfl(c0, lo), ld = __shfl(d0, lo);
-            double ua = __shfl(a0, hi), uc = __shfl(c0, hi), ud = __shfl(d0, hi);
-            if (!has_lo) { la = lc = ld = 0.0; }
-            if (!has_hi) { ua = uc = ud = 0.0; }
-            pcr_step_row(a0, c0, d0, la, lc, ld, ua, uc, ud, bad);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        {
-            double la = __shfl(a1, lo), lc = __shfl(c1, lo), ld = __shfl(d1, lo);
-            double ua = __shfl(a1, hi), uc = __shfl(c1, hi), ud = __shfl(d1, hi);
-            if (!has_lo) { la = lc = ld = 0.0; }
-            if (!has_hi) { ua = uc = ud = 0.0; }
-            pcr_step_row(a1, c1, d1, la, lc, ld, ua, uc, ud, bad);
-        }
-    }
-    // each lane overwrites only its own two slots: no barrier needed before
-    rd[q2] = d0;
-    rd[q2 + 1] = d1;
-    __syncthreads();
-    x_first = rd[s * pitch + 2 * p];
-    x_last = rd[s * pitch + 2 * p + 1];
-}
-
-// A value the compiler cannot see through (it is then recomputed or
-// re-read where it is used instead of being kept live from an earlier point).
-template <typename V>
-__device__ __forceinline__ V opaque(V v) {
-    asm volatile("" : "+v"(v));
-    return v;
 }
 
 // Where the x rows of a lane go and, when the walk rolls on, where the next
@@ -296,7 +187,7 @@ __device__ __forceinline__ void shift_solve(const char *base, const ShiftLds &L,
 
     // Stage B
     double xfd, xld;
-    shift_pcr(XC, S, s, p, P, P_log2, f, xfd, xld, bad);
+    iface_pcr(XC, S, s, p, P, P_log2, f, xfd, xld, bad);
 
     // Stage C, forward: e_j in place of d_j
     const T xf = (T)xfd;
@@ -610,7 +501,7 @@ __device__ __forceinline__ double shift_refine_tile(const char *base, const Shif
         f.lc = lc;
         f.ld = (double)dh;
         double xf, xl;
-        shift_pcr(XC, S, s, p, P, P_log2, f, xf, xl, bad);
+        iface_pcr(XC, S, s, p, P, P_log2, f, xf, xl, bad);
         // Stage C (FP32) on the correction, added to x in FP64
         const float xff = (float)xf;
         float ee = xff;

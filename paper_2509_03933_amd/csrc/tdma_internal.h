@@ -39,7 +39,8 @@ struct TileShape {
                             // 2: its streaming form (resident blocks walk the tiles),
                             // 3: shared operator + per-system shift, streaming with the
                             // next tile's rows loaded as Stage C frees registers, 4: the
-                            // same loading each tile at its start (shifted.hip)
+                            // same loading each tile at its start (shifted.hip),
+                            // 5: per-row coefficients, streaming (perrow.hip)
     bool pdd = false;       // kernel 0 only: Stage B by the PDD approximation
     int threads() const { return (1 << S_log2) * P; }
 };
@@ -73,6 +74,14 @@ bool shift_layout_ok(const SysMap &map, const TileShape &shape);
 size_t shift_lds_bytes(int dtype, const TileShape &shape);
 hipError_t launch_shift(int dtype, const SysMap &map, const Coef &coef, const TileShape &shape,
                         const void *d, void *x, int *err_flag, hipStream_t stream);
+
+// per-row coefficients (a, b, c laid out like d), strided layouts, walking
+// workgroups with 128-byte tile rows (perrow.hip)
+bool perrow_supported(int dtype, const TileShape &shape);
+bool perrow_layout_ok(const SysMap &map, const TileShape &shape);
+size_t perrow_lds_bytes(const TileShape &shape);
+hipError_t launch_perrow(int dtype, const SysMap &map, const Coef &coef, const TileShape &shape,
+                         const void *d, void *x, int *err_flag, hipStream_t stream);
 
 // several right-hand sides over one shared operator (multi.hip): S systems x
 // P partitions (P <= 64) x M rows per lane, one tile per block

@@ -534,5 +534,108 @@ __device__ __forceinline__ void stage_out(T *stg, const TileSysLds *tsys, T *dst
     }
 }
 
+// The same copies with each lane's M rows at a stride of M+1 in LDS (row re
+// of a system at slot re + re/M, systems `pitch` = P*(M+1)+1 slots apart):
+// the lanes of a wavefront, which hold consecutive partitions of a system,
+// then read and write their rows at an odd stride of 8-byte words, without
+// the bank conflicts of a stride of M rows.
+template <int M>
+__device__ __forceinline__ int sw_slot(int re) { return re + re / M; }
+
+template <typename T, int M, int K = 4>
+__device__ __forceinline__ void stage_in_sw(T *stg, const TileSysLds *tsys, const T *src, T ident,
+                                            int S, int R, int pitch, float invR, int s, int p,
+                                            T (&dst)[M]) {
+    static_assert(M % K == 0, "K must divide M");
+    const int tot = S * R;
+    __syncthreads();
+    const int tid = opaque_tid();
+#pragma unroll
+    for (int c = 0; c < M; c += K) {
+        T v[K];
+        int se[K], re[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e0 = tid + (c + k) * (int)blockDim.x;
+            split_elem(e0 < tot ? e0 : tot - 1, R, invR, se[k], re[k]);
+            const int64_t nr = tsys[se[k]].nrows;
+            const int64_t rr = re[k] < nr ? re[k] : (nr > 0 ? nr - 1 : 0);
+            v[k] = src[(nr > 0 ? tsys[se[k]].base : 0) + rr];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e0 = tid + (c + k) * (int)blockDim.x;
+            if (e0 < tot) stg[se[k] * pitch + sw_slot<M>(re[k])] = re[k] < tsys[se[k]].nrows ? v[k] : ident;
+        }
+    }
+    __syncthreads();
+    const int q = s * pitch + p * (M + 1);
+#pragma unroll
+    for (int j = 0; j < M; ++j) dst[j] = stg[q + j];
+}
+
+// All four arrays of a per-row tile (a, b, c, d; rows contiguous) at once:
+// every thread issues its M loads of each array (elements tid + i*blockDim,
+// the same offsets for the four), so the four arrays' loads are in flight
+// together, then the arrays pass through the staging buffer one after the
+// other in place, each lane taking its own rows (identity values past a
+// system's end).  blockDim.x * M == S * R.
+template <typename T, int M>
+__device__ __forceinline__ void stage_in4_sw(T *stg, const TileSysLds *tsys, const T *A, const T *B,
+                                             const T *C, const T *D, int S, int R, int pitch,
+                                             float invR, int s, int p, T (&av)[M], T (&bv)[M],
+                                             T (&cv)[M], T (&dv)[M]) {
+    __syncthreads();
+    const int tot = S * R;
+    const int tid = opaque_tid();
+    int slot[M];
+    bool in[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        const int e0 = tid + i * (int)blockDim.x;
+        const int e = e0 < tot ? e0 : tot - 1;
+        int se, re;
+        split_elem(e, R, invR, se, re);
+        const int64_t nr = tsys[se].nrows;
+        const int64_t rr = re < nr ? re : (nr > 0 ? nr - 1 : 0);
+        const int64_t o = (nr > 0 ? tsys[se].base : 0) + rr;
+        av[i] = A[o];
+        bv[i] = B[o];
+        cv[i] = C[o];
+        dv[i] = D[o];
+        slot[i] = se * pitch + sw_slot<M>(re);
+        in[i] = re < nr;
+    }
+    const int q = s * pitch + p * (M + 1);
+    auto put = [&](T (&v)[M], T ident) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) stg[slot[i]] = in[i] ? v[i] : ident;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < M; ++j) v[j] = stg[q + j];
+        __syncthreads();
+    };
+    put(dv, Ident<T>::d);
+    put(av, Ident<T>::a);
+    put(bv, Ident<T>::b);
+    put(cv, Ident<T>::c);
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void stage_out_sw(T *stg, const TileSysLds *tsys, T *dst_g, int S, int R,
+                                             int pitch, float invR, int s, int p, const T (&src)[M]) {
+    const int nthr = blockDim.x;
+    __syncthreads();
+    const int q = s * pitch + p * (M + 1);
+#pragma unroll
+    for (int j = 0; j < M; ++j) stg[q + j] = src[j];
+    __syncthreads();
+    for (int e = threadIdx.x; e < S * R; e += nthr) {
+        int se, re;
+        split_elem(e, R, invR, se, re);
+        if (re < tsys[se].nrows) dst_g[tsys[se].base + re] = stg[se * pitch + sw_slot<M>(re)];
+    }
+}
+
 }  // namespace dev
 }  // namespace tdma

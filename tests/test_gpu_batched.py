@@ -325,8 +325,8 @@ def test_ragged_long_systems_fp32():
 
 
 def test_ragged_too_long_for_fp64():
-    """An FP64 ragged system beyond 8,192 rows (more than 1,024 partitions of
-    8 rows) is refused with EUNSUPPORTED before any launch."""
+    """An FP64 ragged system beyond 8,192 rows (more than 512 partitions of
+    16 rows) is refused with EUNSUPPORTED before any launch."""
     import paper_2509_03933_amd as tdma
     offsets = np.array([0, 100, 100 + 9000], dtype=np.int64)
     lay = configs.Layout(n=9000, nsys0=2, nsys1=1, offsets=offsets)

@@ -112,23 +112,30 @@ def test_adi_256_cubed_fp32():
 
 
 def test_partitioned_1024_cubed():
-    """1,048,576 z-systems of n = 1024, P = 8, 4 streams, default batch."""
+    """1,048,576 per-row z-systems of n = 1024: the fused solve as the
+    benchmark runs it (tdma_solve_batched: the walking per-row kernel), then
+    the staged pipeline (P = 8, 4 streams, default batch); 65,536 systems of
+    each against the oracle."""
     import paper_2509_03933_amd as tdma
     from workloads import device
     p = configs.partitioned(1024, 1024, 1024)
     d, co = device.device_inputs(p)
     x = torch.empty_like(d)
-    tdma.solve_partitioned(p.layout, co, d, x, partitions=8, nstreams=4)
-    tdma.check()
-    assert torch.isfinite(x).all()
-    # 65,536 systems against the oracle, inputs from the host generator
     lay = p.layout
     systems = _sample_many(lay.nsys)
     idx = _rows(lay, systems)
     row = np.broadcast_to(np.arange(lay.n, dtype=np.int64), idx.shape)
     a, b, c, dd = configs.element_values(p, idx.ravel(), row.ravel(), lay.n)
     ref = oracle.solve_batch(_packed(lay.n, systems.size), 0, a, b, c, dd)
-    _compare_rows(x, idx, ref, parity.TOL_F64, "partitioned 1024^3")
+    tdma.solve_batched(lay, co, d, x)
+    tdma.check()
+    assert torch.isfinite(x).all()
+    _compare_rows(x, idx, ref, parity.TOL_F64, "per-row 1024^3, fused")
+    x.fill_(float("nan"))
+    tdma.solve_partitioned(lay, co, d, x, partitions=8, nstreams=4)
+    tdma.check()
+    assert torch.isfinite(x).all()
+    _compare_rows(x, idx, ref, parity.TOL_F64, "per-row 1024^3, staged")
     del d, co, x
     torch.cuda.empty_cache()
 
