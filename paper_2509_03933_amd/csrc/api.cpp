@@ -386,13 +386,70 @@ int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out) {
         all.insert(all.end(), kv.second.begin(), kv.second.end());
         rp.buckets.push_back(b);
     }
+    // the single-launch form: per rows-per-lane class, tiles of every bucket
+    // (longest systems first) whose S*P lanes fill a block of the class's
+    // largest size
+    std::vector<RaggedTile> tiles;
+    std::vector<int> Ms;
+    for (const RaggedBucket &b : rp.buckets)
+        if (std::find(Ms.begin(), Ms.end(), b.shape.M) == Ms.end()) Ms.push_back(b.shape.M);
+    bool groups_ok = true;
+    for (int M : Ms) {
+        if (!fused_tiles_supported(dtype, M)) { groups_ok = false; break; }
+        RaggedGroup g;
+        g.M = M;
+        g.threads = fused_max_threads(dtype, M);
+        g.first_tile = (int64_t)tiles.size();
+        std::vector<const RaggedBucket *> bs;
+        for (const RaggedBucket &b : rp.buckets)
+            if (b.shape.M == M) bs.push_back(&b);
+        std::sort(bs.begin(), bs.end(),
+                  [](const RaggedBucket *x, const RaggedBucket *y) { return x->shape.P > y->shape.P; });
+        for (const RaggedBucket *b : bs) {
+            const int P = b->shape.P;
+            if (P > g.threads) { groups_ok = false; break; }
+            const int S = g.threads / P;
+            TileShape sh;
+            sh.M = M;
+            sh.P = P;
+            sh.S_log2 = ilog2_floor(S);
+            sh.contig = true;
+            g.lds = std::max(g.lds, fused_lds_bytes(dtype, sh));
+            for (int64_t k = 0; k < b->count; k += S) {
+                RaggedTile t;
+                t.first = (int32_t)(b->first + k);
+                t.count = (int32_t)std::min<int64_t>(S, b->count - k);
+                t.P_log2 = ilog2_floor(P);
+                t.S_log2 = sh.S_log2;
+                tiles.push_back(t);
+            }
+        }
+        g.ntiles = (int64_t)tiles.size() - g.first_tile;
+        if (g.lds > 160 * 1024) groups_ok = false;
+        if (!groups_ok) break;
+        rp.groups.push_back(g);
+    }
+    if (!groups_ok || tiles.size() > (size_t)INT32_MAX) {
+        rp.groups.clear();
+        tiles.clear();
+    }
     hipError_t e = hipMalloc(&rp.d_offsets, (nsys + 1) * sizeof(int64_t));
     if (e != hipSuccess) return fail(TDMA_ENOMEM, "ragged offsets");
     e = hipMalloc(&rp.d_list, std::max<size_t>(1, all.size()) * sizeof(int32_t));
     if (e != hipSuccess) { (void)hipFree(rp.d_offsets); return fail(TDMA_ENOMEM, "ragged list"); }
+    if (!tiles.empty()) {
+        e = hipMalloc(&rp.d_tiles, tiles.size() * sizeof(RaggedTile));
+        if (e != hipSuccess) {
+            rp.d_tiles = nullptr;
+            free_ragged_plan(&rp);
+            return fail(TDMA_ENOMEM, "ragged tiles");
+        }
+    }
     e = hipMemcpy(rp.d_offsets, L->offsets, (nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && !all.empty())
         e = hipMemcpy(rp.d_list, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tiles.empty())
+        e = hipMemcpy(rp.d_tiles, tiles.data(), tiles.size() * sizeof(RaggedTile), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         free_ragged_plan(&rp);
         return hip_fail(e, "upload ragged plan");
@@ -404,6 +461,8 @@ int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out) {
 void free_ragged_plan(RaggedPlan *rp) {
     if (rp->d_offsets) (void)hipFree(rp->d_offsets);
     if (rp->d_list) (void)hipFree(rp->d_list);
+    if (rp->d_tiles) (void)hipFree(rp->d_tiles);
+    rp->d_tiles = nullptr;
     rp->d_offsets = nullptr;
     rp->d_list = nullptr;
 }
@@ -464,11 +523,23 @@ Coef make_coef(const tdma_coeffs *C) {
     return c;
 }
 
-// One launch per bucket of a ragged plan.
+// Per-row coefficients without a shift: one launch per rows-per-lane class
+// of the plan's tile list.  Otherwise one launch per bucket.
 int launch_ragged(const RaggedPlan &rp, const tdma_layout *L, const tdma_coeffs *C, int dtype,
                   const void *d, void *x, int *err, hipStream_t st, const hipStream_t *aux,
                   int naux, const hipEvent_t *ev) {
     const Coef coef = make_coef(C);
+    if (C->mode == TDMA_COEF_LIKE_D && C->b_shift == nullptr && !rp.groups.empty()) {
+        for (const RaggedGroup &g : rp.groups) {
+            SysMap m = make_map(L);
+            m.offsets = rp.d_offsets;
+            m.sys_list = rp.d_list;
+            const hipError_t e = launch_fused_tiles(dtype, g.M, m, coef, d, x, rp.d_tiles + g.first_tile,
+                                                    g.ntiles, g.threads, g.lds, err, st);
+            if (e != hipSuccess) return hip_fail(e, "fused launch (ragged tiles)");
+        }
+        return TDMA_OK;
+    }
     const int nb = (int)rp.buckets.size();
     const int nuse = std::max(0, std::min(naux, nb - 1));
     hipError_t e = hipSuccess;

@@ -18,6 +18,14 @@ struct RaggedBucket {
     int64_t count = 0;
 };
 
+// Tiles of one rows-per-lane class in the single-launch form.
+struct RaggedGroup {
+    int M = 0;
+    int threads = 0;
+    size_t lds = 0;
+    int64_t first_tile = 0, ntiles = 0;
+};
+
 struct RaggedPlan {
     int64_t nsys = 0;
     int dtype = -1;
@@ -25,6 +33,10 @@ struct RaggedPlan {
     int64_t *d_offsets = nullptr;
     int32_t *d_list = nullptr;
     std::vector<RaggedBucket> buckets;
+    // per-row coefficients: every bucket of one M in one launch (tile list,
+    // longest systems first); empty when a tile would not fit
+    std::vector<RaggedGroup> groups;
+    RaggedTile *d_tiles = nullptr;
 };
 
 struct Workspace {

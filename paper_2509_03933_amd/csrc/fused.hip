@@ -21,6 +21,21 @@ k_fused(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P, int *err) {
         fused_tile<T, M, LIKE_D, SHIFT, CONTIG, PDD>(map, coef, d, x, S_log2, P, k0, err, lds);
 }
 
+// A whole ragged batch of per-row systems in one launch: block b solves tile
+// b of a list that the plan orders longest systems first; every tile's
+// S*P lanes fill the block, whatever its partition count.
+template <typename T, int M>
+__global__ void __launch_bounds__((fused_max_threads<T, M>()))
+k_fused_tiles(SysMap map, Coef coef, const T *d, T *x, const RaggedTile *tiles, int *err) {
+    extern __shared__ double lds[];
+    const RaggedTile tl = tiles[blockIdx.x];
+    SysMap m = map;
+    m.sys_list = map.sys_list + tl.first;
+    m.nsys = tl.count;
+    m.n = (int64_t)M << tl.P_log2;
+    fused_tile<T, M, true, false, true, false>(m, coef, d, x, tl.S_log2, 1 << tl.P_log2, 0, err, lds);
+}
+
 template <typename T, int M, bool LIKE_D, bool SHIFT, bool CONTIG, bool CO>
 hipError_t launch_t(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
                     void *x, int *err, size_t lds, hipStream_t st) {
@@ -83,6 +98,30 @@ bool fused_supported(int dtype, const TileShape &sh) {
     if (dtype == TDMA_F64) return sh.M == 4 || sh.M == 8 || sh.M == 16;
     if (dtype == TDMA_F32) return sh.M == 4 || sh.M == 8 || sh.M == 16 || sh.M == 32;
     return false;
+}
+
+bool fused_tiles_supported(int dtype, int M) {
+    return dtype == TDMA_F64 ? M == 16 : (dtype == TDMA_F32 && (M == 16 || M == 32));
+}
+
+hipError_t launch_fused_tiles(int dtype, int M, const SysMap &map, const Coef &coef, const void *d,
+                              void *x, const RaggedTile *tiles, int64_t ntiles, int threads,
+                              size_t lds, int *err, hipStream_t st) {
+    if (ntiles == 0) return hipSuccess;
+    if (!fused_tiles_supported(dtype, M) || threads > fused_max_threads(dtype, M) ||
+        coef.mode != TDMA_COEF_LIKE_D || coef.shift != nullptr || lds > 160 * 1024)
+        return hipErrorInvalidValue;
+    const dim3 grid((unsigned)ntiles), block((unsigned)threads);
+    if (dtype == TDMA_F64)
+        hipLaunchKernelGGL((k_fused_tiles<double, 16>), grid, block, lds, st, map, coef, (const double *)d,
+                           (double *)x, tiles, err);
+    else if (M == 16)
+        hipLaunchKernelGGL((k_fused_tiles<float, 16>), grid, block, lds, st, map, coef, (const float *)d,
+                           (float *)x, tiles, err);
+    else
+        hipLaunchKernelGGL((k_fused_tiles<float, 32>), grid, block, lds, st, map, coef, (const float *)d,
+                           (float *)x, tiles, err);
+    return hipGetLastError();
 }
 
 size_t fused_lds_bytes(int dtype, const TileShape &sh, bool shared_rows) {

@@ -75,6 +75,20 @@ size_t shift_lds_bytes(int dtype, const TileShape &shape);
 hipError_t launch_shift(int dtype, const SysMap &map, const Coef &coef, const TileShape &shape,
                         const void *d, void *x, int *err_flag, hipStream_t stream);
 
+// One tile of a ragged batch solved in a single launch (fused.hip): `count`
+// systems (at most 2^S_log2) from entry `first` of the plan's system list,
+// each of at most M << P_log2 rows; a block of 2^S_log2 << P_log2 lanes.
+struct RaggedTile {
+    int32_t first, count;
+    int32_t P_log2, S_log2;
+};
+// per-row coefficients without a shift, contiguous rows; M = 16 (FP64) or
+// 16, 32 (FP32); `threads` lanes per block for every tile of the list
+bool fused_tiles_supported(int dtype, int M);
+hipError_t launch_fused_tiles(int dtype, int M, const SysMap &map, const Coef &coef, const void *d,
+                              void *x, const RaggedTile *tiles, int64_t ntiles, int threads,
+                              size_t lds, int *err_flag, hipStream_t stream);
+
 // per-row coefficients (a, b, c laid out like d), strided layouts, walking
 // workgroups with 128-byte tile rows (perrow.hip)
 bool perrow_supported(int dtype, const TileShape &shape);
