@@ -144,6 +144,36 @@ def test_ragged_fp64():
     assert err.max() <= parity.TOL_F64, err.max()
 
 
+def _ragged_with_lengths(lens, seed=31):
+    """A ragged per-row problem with the given system lengths (the ragged
+    law of configs.ragged)."""
+    import dataclasses
+    lens = np.asarray(lens, dtype=np.int64)
+    base = configs.ragged(nsys=len(lens), seed=seed)
+    offsets = np.zeros(len(lens) + 1, dtype=np.int64)
+    np.cumsum(lens, out=offsets[1:])
+    lay = configs.Layout(n=int(lens.max()), nsys0=len(lens), nsys1=1, offsets=offsets)
+    return dataclasses.replace(base, layout=lay)
+
+
+@pytest.mark.parametrize("case", ["one_longest", "many_shortest", "bucket_edges", "one_per_bucket"])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_ragged_tile_list_edges(case, dtype):
+    """The single-launch tile list at the edges of its bucketing: one system
+    of the longest length; 5,000 systems of 2 rows (512 systems per tile);
+    lengths at every power-of-two bucket edge and one row past it (tiles of
+    one bucket cut short, last tiles partly filled); one system per bucket."""
+    top = 8192 if dtype == np.float64 else 16384
+    edges = [2 ** k for k in range(1, 14) if 2 ** k <= top]
+    lens = {"one_longest": [top],
+            "many_shortest": [2] * 5000,
+            "bucket_edges": [e + o for e in edges for o in (0, 1) if e + o <= top] * 3,
+            "one_per_bucket": [e - 1 for e in edges if e - 1 >= 2] + [top]}[case]
+    p = _ragged_with_lengths(lens)
+    err, _, _ = _run(p, dtype)
+    assert err.max() <= (parity.TOL_F64 if dtype == np.float64 else parity.TOL_F32), err.max()
+
+
 def test_ragged_fp32():
     r = configs.ragged(nsys=200, nmin=2, nmax=3000)
     err, _, _ = _run(r, np.float32)
