@@ -72,10 +72,10 @@ PDD_ROWS = 16
 HBM_PEAK_GBS = 8000.0
 CSRC = "paper_2509_03933_amd/csrc/"
 KERNEL_SOURCES = {
-    "k_shared": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
-    "k_shared_stream": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
-    "k_shared_refine": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
-    "k_shared_refine_walk": [CSRC + "shared.hip", CSRC + "tile.hip.h"],
+    "k_shared": [CSRC + "shared.hip", CSRC + "tile.hip.h", CSRC + "walk.hip.h"],
+    "k_shared_stream": [CSRC + "shared.hip", CSRC + "tile.hip.h", CSRC + "walk.hip.h"],
+    "k_shared_refine": [CSRC + "shared.hip", CSRC + "tile.hip.h", CSRC + "walk.hip.h"],
+    "k_shared_refine_walk": [CSRC + "shared.hip", CSRC + "tile.hip.h", CSRC + "walk.hip.h"],
     "k_fused": [CSRC + "fused.hip", CSRC + "fused_tile.hip.h", CSRC + "tile.hip.h"],
     "k_fused_tiles": [CSRC + "fused.hip", CSRC + "fused_tile.hip.h", CSRC + "tile.hip.h"],
     "k_shift_stream": [CSRC + "shifted.hip", CSRC + "tile.hip.h", CSRC + "walk.hip.h"],
@@ -85,7 +85,7 @@ KERNEL_SOURCES = {
     "k_multi": [CSRC + "multi.hip", CSRC + "tile.hip.h"],
     "k_stage_a": [CSRC + "partitioned.hip", CSRC + "tile.hip.h"],
     "graph": [CSRC + "graph.cpp", CSRC + "fused.hip", CSRC + "shared.hip", CSRC + "fused_tile.hip.h",
-              CSRC + "tile.hip.h"],
+              CSRC + "tile.hip.h", CSRC + "walk.hip.h"],
 }
 
 

@@ -137,7 +137,12 @@ int tdma_solve_batched(const tdma_layout *layout, const tdma_coeffs *coeffs, int
  * its start.  kernel 5 (per-row coefficients, TDMA_COEF_LIKE_D without
  * b_shift, strided rows): M = 16 or 32, P a power of two 2..64, at most 1024
  * lanes (512 at M = 32); workgroups walk the tiles, each lane
- * consuming its rows through a window of loads in flight.  Kernels 3-5 take
+ * consuming its rows through a window of loads in flight.  kernel 6 (shared
+ * operator without b_shift, strided rows): kernel 2 holding one set of
+ * right-hand sides per lane, each register refilled with the next tile's row
+ * as Stage C stores the current one (the row order alternating between
+ * tiles), so that wider tiles fit: M*P = n exactly, at most 1024 lanes (512
+ * when M rows fill 256 bytes); results equal kernel 2's.  Kernels 3-6 take
  * fewer than 2^31 / 3 systems.  Uniform layouts only.
  * Errors: EINVAL for a shape outside these rules or with M*P < n.
  */

@@ -265,7 +265,9 @@ def solve_batched_tiled(layout, coeffs, d, x, M, S, P, kernel=0, stream=None):
     kernel 0 = generic, 1 = shared-operator, 2 = its streaming form, 3 = shared
     operator + per-system shift, streaming (the next tile's rows loaded as the
     current one is stored), 4 = the same loading each tile at its start,
-    5 = per-row coefficients on strided rows, streaming."""
+    5 = per-row coefficients on strided rows, streaming, 6 = kernel 2 with one
+    register set refilled from the next tile as rows are stored (strided rows,
+    M*P = n), which fits wider tiles."""
     L, C, keep = _prepare(layout, coeffs, d, x)
     t = _Tile(int(M), int(S), int(P), int(kernel))
     _raise(lib().tdma_solve_batched_tiled(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),

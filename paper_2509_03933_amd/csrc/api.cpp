@@ -239,8 +239,10 @@ bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *o
 // FP32), contiguous rows S = 8 and at least 256 lanes (best on x-lines of
 // n = 384 and 768); both as far as the lanes and LDS allow.  A streaming
 // block holds its CU's LDS for the whole launch, so the whole 160 KB is
-// available to it.
-bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *out) {
+// available to it.  allow_roll admits the rolling form (kernel 6) below; the
+// streamed copy keeps the two-set shape, whose lane bound its kernel shares.
+bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *out,
+                          bool allow_roll) {
     const int Ms[] = {16, 32, 8, 12, 24};
     bool found = false;
     TileShape best;
@@ -264,6 +266,23 @@ bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileS
             best = sh;
             found = true;
         }
+    }
+    // Strided rows whose two-set streaming tile is narrower than a 128-byte
+    // line (its lanes are capped where M rows fill 192 bytes: the 1536-row
+    // z-lines of the large sweeps take 8 systems), with partitions that cover
+    // n exactly: the rolling form holds one register set and fits the full
+    // 128-byte width (z-lines of 1536 rows: 3.24 -> 2.44 ms).
+    const int esz = dtype == TDMA_F64 ? 8 : 4;
+    if (found && allow_roll && !contig && (int64_t)best.P * best.M == n &&
+        ((int64_t)esz << best.S_log2) < 128) {
+        TileShape r = best;
+        r.kernel = 6;
+        r.S_log2 = ilog2_floor(128 / esz);
+        const int maxt = shared_max_threads(dtype, r.M, 6, false);
+        while (r.S_log2 > 0 && ((int64_t)1 << r.S_log2) * r.P > maxt) --r.S_log2;
+        while (r.S_log2 > 0 && ((int64_t)1 << (r.S_log2 - 1)) >= nsys) --r.S_log2;
+        while (r.S_log2 > 0 && shared_lds_bytes(dtype, r) > 160 * 1024) --r.S_log2;
+        if (r.S_log2 > best.S_log2 && shared_supported(dtype, r)) best = r;
     }
     if (found) *out = best;
     return found;
@@ -578,6 +597,8 @@ static bool shape_fits(int dtype, const tdma_layout *L, bool shared_op, const Ti
     }
     if (sh.kernel == 5) return perrow_op && perrow_supported(dtype, sh) && perrow_layout_ok(make_map(L), sh);
     if (sh.kernel == 1 || sh.kernel == 2) return shared_op && shared_supported(dtype, sh);
+    if (sh.kernel == 6)
+        return shared_op && shared_supported(dtype, sh) && (int64_t)sh.P * sh.M == L->n;
     if (sh.kernel != 0 || !fused_supported(dtype, sh)) return false;
     return !(sh.contig && fused_lds_bytes(dtype, sh) > 160 * 1024);
 }
@@ -599,7 +620,7 @@ int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int
         if ((int64_t)sh.P * sh.M < L->n)
             return fail(TDMA_EINVAL, "tile shape M=%d P=%d S=%d does not cover n=%lld", sh.M, sh.P,
                         1 << sh.S_log2, (long long)L->n);
-        if ((sh.kernel == 1 || sh.kernel == 2) && !shared_op)
+        if ((sh.kernel == 1 || sh.kernel == 2 || sh.kernel == 6) && !shared_op)
             return fail(TDMA_EINVAL, "the shared-operator kernel needs shared coefficients without "
                         "a shift (M=%d P=%d S=%d)", sh.M, sh.P, 1 << sh.S_log2);
         if ((sh.kernel == 3 || sh.kernel == 4) && !shifted_op)
@@ -620,7 +641,7 @@ int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int
         else if (perrow_op && !contig && default_perrow_shape(dtype, L->n, nsys, &ssh) &&
                  perrow_layout_ok(make_map(L), ssh))
             sh = ssh;
-        else if (!(shared_op && default_shared_shape(dtype, L->n, nsys, contig, &sh)) &&
+        else if (!(shared_op && default_shared_shape(dtype, L->n, nsys, contig, &sh, true)) &&
                  !default_shape(dtype, L->n, nsys, contig, &sh))
             return fail(TDMA_EUNSUPPORTED, "n = %lld is too long for the fused path (use "
                         "tdma_solve_partitioned)", (long long)L->n);
@@ -728,15 +749,18 @@ int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeff
     while ((1 << sh.S_log2) < S) ++sh.S_log2;
     sh.contig = layout->row_stride == 1;
     sh.kernel = tile->kernel;
-    if (sh.kernel < 0 || sh.kernel > 5) return fail(TDMA_EINVAL, "unknown kernel %d", sh.kernel);
+    if (sh.kernel < 0 || sh.kernel > 6) return fail(TDMA_EINVAL, "unknown kernel %d", sh.kernel);
     if (sh.kernel == 0 && !fused_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported tile M=%d S=%d P=%d", sh.M, S, sh.P);
     if ((sh.kernel == 3 || sh.kernel == 4) && !shift_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported shifted-operator tile M=%d S=%d P=%d", sh.M, S, sh.P);
     if (sh.kernel == 5 && !perrow_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported per-row tile M=%d S=%d P=%d", sh.M, S, sh.P);
-    if ((sh.kernel == 1 || sh.kernel == 2) && !shared_supported(dtype, sh))
+    if ((sh.kernel == 1 || sh.kernel == 2 || sh.kernel == 6) && !shared_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported shared-operator tile M=%d S=%d P=%d", sh.M, S, sh.P);
+    if (sh.kernel == 6 && (int64_t)sh.M * sh.P != layout->n)
+        return fail(TDMA_EINVAL, "kernel 6 needs partitions that cover n exactly (M=%d P=%d, n = %lld)",
+                    sh.M, sh.P, (long long)layout->n);
     if ((int64_t)sh.M * sh.P < layout->n) return fail(TDMA_EINVAL, "tile covers %lld rows < n = %lld",
                                                       (long long)sh.M * sh.P, (long long)layout->n);
     if (sh.kernel == 0 && sh.contig && fused_lds_bytes(dtype, sh) > 160 * 1024)
@@ -763,7 +787,7 @@ int tdma_copy_streamed(const tdma_layout *layout, int dtype, const void *src, vo
     const int64_t nsys = layout->nsys0 * layout->nsys1;
     if (nsys == 0) return TDMA_OK;
     TileShape sh;
-    if (!default_shared_shape(dtype, layout->n, nsys, false, &sh))
+    if (!default_shared_shape(dtype, layout->n, nsys, false, &sh, false))
         return fail(TDMA_EUNSUPPORTED, "n = %lld has no streaming shape", (long long)layout->n);
     const SysMap map = make_map(layout);
     if (!copy_streamed_supported(map, sh))

@@ -20,6 +20,7 @@
 
 #include "refine.h"
 #include "tile.hip.h"
+#include "walk.hip.h"
 
 namespace tdma {
 namespace {
@@ -631,6 +632,146 @@ k_shared_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2,
     if (bad) atomicOr(err, 1);
 }
 
+// Rolling form of the streaming kernel (kernel 6), for partitions that
+// cover n exactly: one register set of right-hand sides instead of two.
+// Stage C produces the rows of x from the bottom up; each row is stored at
+// once and its register takes the next tile's row M-1-j, so the next tile's
+// rows arrive in the order its Stage A consumes them and the register order
+// of the rows alternates between tiles (FL: logical row j in register j, or
+// M-1-j).  Half the registers of two sets: 24 FP64 rows per lane fit 1024
+// lanes, i.e. 16 systems (128-byte tile rows) of 64 partitions at n = 1536.
+template <typename T, int M>
+constexpr int roll_max_threads() { return (int)sizeof(T) * M >= 256 ? 512 : 1024; }
+
+template <typename T, int M, int MODE, int FL, typename OffT>
+__device__ __forceinline__ void shared_solve_roll(const SharedLds &L, char *base, int S, int P,
+                                                  int P_log2, int s, int p, T (&v)[M],
+                                                  const char *db, char *xb, OffT xo, OffT no,
+                                                  OffT step, bool store, bool fetch) {
+    using P2 = typename PairOf<T>::type;
+    auto slot = [](int j) { return FL == 1 ? M - 1 - j : j; };
+    // The tables are the same for every tile: each group of four rows reads
+    // them through an offset the compiler cannot see through, so the reads
+    // are not hoisted out of the walk and held in registers across it.
+    const int q0 = p * (M + 1);
+    const P2 *GH0 = reinterpret_cast<const P2 *>(base + L.gh);
+    const P2 *AC0 = reinterpret_cast<const P2 *>(base + L.ac);
+    const T *PI0 = reinterpret_cast<const T *>(base + L.pi);
+    const P2 *GH = GH0 + opaque(q0), *AC = AC0 + opaque(q0);
+    const T *PI = PI0 + opaque(q0);
+    auto rows_group = [&] {
+        const int q = opaque(q0);
+        GH = GH0 + q;
+        AC = AC0 + q;
+        PI = PI0 + q;
+    };
+    const double *PT = reinterpret_cast<const double *>(base + L.part);
+    const double *QA = reinterpret_cast<const double *>(base + L.qa);
+    const double *QC = QA + L.nsteps * 2 * P, *QB = QC + L.nsteps * 2 * P;
+    double *XD = reinterpret_cast<double *>(base + L.xd);
+    // Stage A
+    const T draw0 = v[slot(0)];
+    v[slot(1)] = GH[1].x * v[slot(1)];
+#pragma unroll
+    for (int j = 2; j < M; ++j) {
+        if ((j & 3) == 0) rows_group();
+        const P2 gh = GH[j];
+        v[slot(j)] = gh.x * v[slot(j)] - gh.y * v[slot(j - 1)];
+        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    rows_group();
+    T dt1 = T(0);
+#pragma unroll
+    for (int j = 1; j <= M - 2; ++j) {
+        dt1 += PI[j] * v[slot(j)];
+        if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+    const double df = PT[p] * (double)draw0 - PT[P + p] * (double)dt1;
+    const double dl_ = (double)v[slot(M - 1)];
+    // Stage B
+    double xfd, xld;
+    shared_rhs_pcr<MODE>(XD, QA, QC, QB, S, P, P_log2, s, p, df, dl_, xfd, xld);
+    const T xf = (T)xfd;
+    // Stage C from the bottom: each row stored at once, its register refilled
+    OffT xq = xo + (OffT)(M - 1) * step;
+    OffT nq = no;
+    T xn = (T)xld;
+    if (store) __builtin_nontemporal_store(xn, reinterpret_cast<T *>(xb + xq));
+    if (fetch) v[slot(M - 1)] = __builtin_nontemporal_load(reinterpret_cast<const T *>(db + nq));
+#pragma unroll
+    for (int j = M - 2; j >= 1; --j) {
+        if (j == M - 2 || (j & 3) == 0) rows_group();
+        const P2 ac = AC[j];
+        T xj = v[slot(j)] - ac.x * xf - ac.y * xn;
+        xj = opaque(xj);
+        xq = opaque(xq - step);
+        if (store) __builtin_nontemporal_store(xj, reinterpret_cast<T *>(xb + xq));
+        nq = opaque(nq + step);
+        if (fetch) v[slot(j)] = __builtin_nontemporal_load(reinterpret_cast<const T *>(db + nq));
+        xn = xj;
+        if ((j & 3) == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (store) __builtin_nontemporal_store(xf, reinterpret_cast<T *>(xb + xo));
+    if (fetch) v[slot(0)] = __builtin_nontemporal_load(reinterpret_cast<const T *>(db + (nq + step)));
+}
+
+template <typename T, int M, typename OffT, int MODE>
+__global__ void __launch_bounds__((roll_max_threads<T, M>()))
+k_shared_roll(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int64_t ntiles,
+              int *err) {
+    extern __shared__ double lds[];
+    char *base = reinterpret_cast<char *>(lds);
+    const int tid = threadIdx.x;
+    const int S = 1 << S_log2, P = 1 << P_log2;
+    const int s = tid & (S - 1);
+    const int p = tid >> S_log2;
+    const int r0 = p * M;
+    const int64_t rs = map.row_stride;
+    const SharedLds L = shared_layout(sizeof(T), M, P, S);
+    const int32_t step_sys = (int32_t)gridDim.x << S_log2;
+    const int32_t nt = (int32_t)ntiles;
+    int32_t t = (int32_t)((S * (int)sizeof(T) < 128) ? dev::xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
+    LaneWalk w;
+    w.init(map, (t << S_log2) + s, step_sys);
+    dev::RowRegs<shared_cr<M>()> cr;
+    dev::rows_prefetch<T, shared_cr<M>()>(coef, map.n, cr);
+    __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the right-hand sides
+    T v[M];
+    LaneSys l = w.sys(map);
+    load_rows<T, M, OffT>(d, l, rs, r0, v);
+    bool bad = false;
+    shared_tables<T, T, M>(coef, map.n, L, base, tid, s, p, P, cr, bad);
+    // byte offsets of a lane's row 0 (a lane past the last system: system 0)
+    const OffT step = (OffT)(rs * (int64_t)sizeof(T));
+    auto off_of = [&](const LaneSys &q) {
+        return (OffT)((q.base + (int64_t)r0 * rs) * (int64_t)sizeof(T));
+    };
+    bool ok = l.valid;
+    OffT xo = off_of(l);
+    const char *db = reinterpret_cast<const char *>(d);
+    char *xb = reinterpret_cast<char *>(x);
+    auto one = [&](auto layout) {
+        constexpr int F = decltype(layout)::value;
+        w.advance(map, step_sys);
+        const LaneSys nl = w.sys(map);
+        const OffT no = off_of(nl);
+        const bool fetch = t + (int32_t)gridDim.x < nt;   // the block has a next tile
+        shared_solve_roll<T, M, MODE, F, OffT>(L, base, S, P, P_log2, s, p, v, db, xb, xo, no, step,
+                                               ok, fetch);
+        ok = nl.valid;
+        xo = no;
+    };
+    for (;;) {
+        one(std::integral_constant<int, 0>{});
+        t += gridDim.x;
+        if (t >= nt) break;
+        one(std::integral_constant<int, 1>{});
+        t += gridDim.x;
+        if (t >= nt) break;
+    }
+    if (bad) atomicOr(err, 1);
+}
+
 // The memory traffic of k_shared_stream alone: the same tile walk, lane rows
 // and register double-buffering, with no tables and no arithmetic (x = d on
 // every system row).  The ceiling of that access pattern, for measurement.
@@ -1070,6 +1211,17 @@ hipError_t launch_stream(const SysMap &map, const Coef &coef, const TileShape &s
     return hipGetLastError();
 }
 
+template <typename T, int M, typename OffT, int MODE>
+hipError_t launch_roll(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
+                       void *x, int *err, size_t lds, hipStream_t st, int64_t blocks, int P_log2) {
+    const int64_t resident = resident_blocks(k_shared_roll<T, M, OffT, MODE>, sh.threads(), lds);
+    if (resident < 1) return hipErrorInvalidConfiguration;
+    const int64_t grid = blocks < resident ? blocks : resident;
+    hipLaunchKernelGGL((k_shared_roll<T, M, OffT, MODE>), dim3((unsigned)grid), dim3(sh.threads()),
+                       lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, blocks, err);
+    return hipGetLastError();
+}
+
 template <typename T, int M, typename OffT>
 hipError_t launch_strided(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d,
                           void *x, int *err, size_t lds, hipStream_t st, int64_t blocks,
@@ -1081,10 +1233,17 @@ hipError_t launch_strided(const SysMap &map, const Coef &coef, const TileShape &
     const int64_t S = (int64_t)1 << sh.S_log2;
     const bool stream_ok = !map.offsets && !map.sys_list && !map.count &&
                            2 * (blocks + 1) * S < ((int64_t)1 << 31);
-    if (sh.kernel == 2 && stream_ok) {
+    if (sh.kernel == 6 && stream_ok && (int64_t)sh.P * M == map.n) {
+        if (sh.P <= 16)
+            return launch_roll<T, M, OffT, PCR_DPP>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
+        return launch_roll<T, M, OffT, PCR_SHFL>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
+    }
+    if ((sh.kernel == 2 || sh.kernel == 6) && stream_ok && sh.threads() <= shared_max_threads<T, M>()) {
         if (sh.P <= 16)
             return launch_stream<T, M, OffT, PCR_DPP>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
         return launch_stream<T, M, OffT, PCR_SHFL>(map, coef, sh, d, x, err, lds, st, blocks, P_log2);
+    } else if (sh.threads() > shared_max_threads<T, M>()) {
+        return hipErrorInvalidValue;
     } else {
         hipLaunchKernelGGL((k_shared<T, M, false, OffT>), dim3((unsigned)blocks), dim3(sh.threads()),
                            lds, st, map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, err);
@@ -1164,6 +1323,7 @@ hipError_t launch_copy_t(const SysMap &map, const TileShape &sh, const void *d, 
 int shared_max_threads(int dtype, int M, int kernel, bool contig) {
     const int esz = dtype == TDMA_F64 ? 8 : 4;
     if (kernel == 2 && contig) return esz * M >= 256 ? 256 : (esz * M >= 128 ? 512 : 1024);
+    if (kernel == 6) return esz * M >= 256 ? 512 : 1024;
     return esz * M >= 192 ? 512 : 1024;
 }
 
@@ -1177,6 +1337,7 @@ size_t shared_lds_bytes(int dtype, const TileShape &sh) {
 
 bool shared_supported(int dtype, const TileShape &sh) {
     if (sh.P < 1 || sh.P > 64 || (sh.P & (sh.P - 1)) != 0) return false;
+    if (sh.kernel == 6 && sh.contig) return false;
     if (sh.M != 8 && sh.M != 12 && sh.M != 16 && sh.M != 24 && sh.M != 32) return false;
     if (sh.threads() > shared_max_threads(dtype, sh.M, sh.kernel, sh.contig)) return false;
     return shared_lds_bytes(dtype, sh) <= 160 * 1024;

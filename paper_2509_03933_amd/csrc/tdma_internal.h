@@ -40,7 +40,9 @@ struct TileShape {
                             // 3: shared operator + per-system shift, streaming with the
                             // next tile's rows loaded as Stage C frees registers, 4: the
                             // same loading each tile at its start (shifted.hip),
-                            // 5: per-row coefficients, streaming (perrow.hip)
+                            // 5: per-row coefficients, streaming (perrow.hip),
+                            // 6: kernel 2 with one register set refilled as
+                            // Stage C stores (partitions covering n exactly)
     bool pdd = false;       // kernel 0 only: Stage B by the PDD approximation
     int threads() const { return (1 << S_log2) * P; }
 };
