@@ -142,8 +142,12 @@ int tdma_solve_batched(const tdma_layout *layout, const tdma_coeffs *coeffs, int
  * right-hand sides per lane, each register refilled with the next tile's row
  * as Stage C stores the current one (the row order alternating between
  * tiles), so that wider tiles fit: M*P = n exactly, at most 1024 lanes (512
- * when M rows fill 256 bytes); results equal kernel 2's.  Kernels 3-6 take
- * fewer than 2^31 / 3 systems.  Uniform layouts only.
+ * when M rows fill 256 bytes); results equal kernel 2's.  kernel 7 (shared
+ * operator with b_shift, strided rows, FP64): kernel 3 holding only the
+ * right-hand sides, the pivots recomputed in Stage C, so that 32-system tiles
+ * fit: M = 16 or 32, M*P = n exactly, at most 1024 lanes; results equal
+ * kernel 3's.  Kernels 3-7 take fewer than 2^31 / 3 systems.  Uniform layouts
+ * only.
  * Errors: EINVAL for a shape outside these rules or with M*P < n.
  */
 typedef struct tdma_tile {

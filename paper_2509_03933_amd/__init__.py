@@ -267,7 +267,8 @@ def solve_batched_tiled(layout, coeffs, d, x, M, S, P, kernel=0, stream=None):
     current one is stored), 4 = the same loading each tile at its start,
     5 = per-row coefficients on strided rows, streaming, 6 = kernel 2 with one
     register set refilled from the next tile as rows are stored (strided rows,
-    M*P = n), which fits wider tiles."""
+    M*P = n), which fits wider tiles, 7 = kernel 3 recomputing its pivots
+    instead of keeping them (FP64, M*P = n), which fits 32-system tiles."""
     L, C, keep = _prepare(layout, coeffs, d, x)
     t = _Tile(int(M), int(S), int(P), int(kernel))
     _raise(lib().tdma_solve_batched_tiled(ctypes.byref(L), ctypes.byref(C), _dtype_code(d),

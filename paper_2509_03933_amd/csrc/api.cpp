@@ -292,9 +292,13 @@ bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileS
 // FFT-Poisson lines): M = 32 rows per lane (else 16, 8), P a power of two
 // <= 64 with P*M >= n, and S = 16 consecutive systems per tile in FP64, 32 in
 // FP32 (128-byte tile rows), as far as the lanes allow (512 for FP64 at
-// M = 32, else 1024); the rolling walk (kernel 3).  Measured on the 1024^3
-// Poisson lines in FP64: 16 x 32 partitions x 32 rows 4.8 ms, 16 x 64 x 16
-// 6.0 ms, 8 x 32 x 32 7.3 ms.
+// M = 32, else 1024); the rolling walk (kernel 3).  In FP64 with 32 rows per
+// lane and 16 or 32 partitions covering n, the walk that recomputes its
+// pivots (kernel 7) with S = 32 (256-byte rows).  Measured on the 1024^3
+// Poisson lines in FP64: kernel 7 with 32 x 32 partitions x 32 rows 4.0 ms;
+// kernel 3 with 16 x 32 x 32 4.5 ms, 16 x 64 x 16 6.0 ms, 8 x 32 x 32 7.3 ms;
+// on 1024^2 x 512 lines kernel 7 with 32 x 16 x 32 1.90 ms, kernel 3 with
+// 16 x 16 x 32 2.54 ms.
 static bool default_shift_shape(int dtype, int64_t n, int64_t nsys, TileShape *out) {
     const int Ms[] = {32, 16, 8};
     for (int M : Ms) {
@@ -312,6 +316,15 @@ static bool default_shift_shape(int dtype, int64_t n, int64_t nsys, TileShape *o
         while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= nsys) --S_log2;
         sh.S_log2 = S_log2;
         if (!shift_supported(dtype, sh)) continue;
+        // FP64, 32 rows per lane, 16 or 32 partitions covering n: the kernel
+        // that recomputes its pivots fits 32 systems (256-byte rows)
+        if (dtype == TDMA_F64 && M == 32 && (P == 16 || P == 32) && P * M == n) {
+            TileShape w = sh;
+            w.kernel = 7;
+            w.S_log2 = 5;
+            while (w.S_log2 > 0 && ((int64_t)1 << (w.S_log2 - 1)) >= nsys) --w.S_log2;
+            if (w.S_log2 > sh.S_log2 && shift_supported(dtype, w)) sh = w;
+        }
         *out = sh;
         return true;
     }
@@ -590,15 +603,15 @@ int launch_ragged(const RaggedPlan &rp, const tdma_layout *L, const tdma_coeffs 
 static bool shape_fits(int dtype, const tdma_layout *L, bool shared_op, const TileShape &sh,
                        bool shifted_op, bool perrow_op) {
     if ((int64_t)sh.P * sh.M < L->n) return false;
-    if (sh.kernel == 3 || sh.kernel == 4) {
+    if (sh.kernel == 3 || sh.kernel == 4 || sh.kernel == 7) {
         if (!shifted_op || !shift_supported(dtype, sh)) return false;
+        if (sh.kernel == 7 && (int64_t)sh.P * sh.M != L->n) return false;
         const SysMap m = make_map(L);
         return shift_layout_ok(m, sh);
     }
     if (sh.kernel == 5) return perrow_op && perrow_supported(dtype, sh) && perrow_layout_ok(make_map(L), sh);
     if (sh.kernel == 1 || sh.kernel == 2) return shared_op && shared_supported(dtype, sh);
-    if (sh.kernel == 6)
-        return shared_op && shared_supported(dtype, sh) && (int64_t)sh.P * sh.M == L->n;
+    if (sh.kernel == 6) return shared_op && shared_supported(dtype, sh) && shared_roll_ok(make_map(L), sh);
     if (sh.kernel != 0 || !fused_supported(dtype, sh)) return false;
     return !(sh.contig && fused_lds_bytes(dtype, sh) > 160 * 1024);
 }
@@ -623,7 +636,7 @@ int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int
         if ((sh.kernel == 1 || sh.kernel == 2 || sh.kernel == 6) && !shared_op)
             return fail(TDMA_EINVAL, "the shared-operator kernel needs shared coefficients without "
                         "a shift (M=%d P=%d S=%d)", sh.M, sh.P, 1 << sh.S_log2);
-        if ((sh.kernel == 3 || sh.kernel == 4) && !shifted_op)
+        if ((sh.kernel == 3 || sh.kernel == 4 || sh.kernel == 7) && !shifted_op)
             return fail(TDMA_EINVAL, "the shifted-operator kernel needs shared coefficients with "
                         "a shift (M=%d P=%d S=%d)", sh.M, sh.P, 1 << sh.S_log2);
         if (sh.kernel == 5 && !perrow_op)
@@ -641,8 +654,10 @@ int plan_uniform(DeviceCtx *ctx, const tdma_layout *L, const tdma_coeffs *C, int
         else if (perrow_op && !contig && default_perrow_shape(dtype, L->n, nsys, &ssh) &&
                  perrow_layout_ok(make_map(L), ssh))
             sh = ssh;
-        else if (!(shared_op && default_shared_shape(dtype, L->n, nsys, contig, &sh, true)) &&
-                 !default_shape(dtype, L->n, nsys, contig, &sh))
+        else if (shared_op && default_shared_shape(dtype, L->n, nsys, contig, &sh, true)) {
+            if (sh.kernel == 6 && !shared_roll_ok(make_map(L), sh))
+                default_shared_shape(dtype, L->n, nsys, contig, &sh, false);
+        } else if (!default_shape(dtype, L->n, nsys, contig, &sh))
             return fail(TDMA_EUNSUPPORTED, "n = %lld is too long for the fused path (use "
                         "tdma_solve_partitioned)", (long long)L->n);
     }
@@ -656,7 +671,7 @@ int launch_uniform(const TileShape &sh, const tdma_layout *L, const tdma_coeffs 
     if (m.nsys == 0) return TDMA_OK;
     const Coef coef = make_coef(C);
     hipError_t e;
-    if (sh.kernel == 3 || sh.kernel == 4)
+    if (sh.kernel == 3 || sh.kernel == 4 || sh.kernel == 7)
         e = launch_shift(dtype, m, coef, sh, d, x, err, st);
     else if (sh.kernel == 5)
         e = launch_perrow(dtype, m, coef, sh, d, x, err, st);
@@ -749,18 +764,21 @@ int tdma_solve_batched_tiled(const tdma_layout *layout, const tdma_coeffs *coeff
     while ((1 << sh.S_log2) < S) ++sh.S_log2;
     sh.contig = layout->row_stride == 1;
     sh.kernel = tile->kernel;
-    if (sh.kernel < 0 || sh.kernel > 6) return fail(TDMA_EINVAL, "unknown kernel %d", sh.kernel);
+    if (sh.kernel < 0 || sh.kernel > 7) return fail(TDMA_EINVAL, "unknown kernel %d", sh.kernel);
     if (sh.kernel == 0 && !fused_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported tile M=%d S=%d P=%d", sh.M, S, sh.P);
-    if ((sh.kernel == 3 || sh.kernel == 4) && !shift_supported(dtype, sh))
+    if ((sh.kernel == 3 || sh.kernel == 4 || sh.kernel == 7) && !shift_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported shifted-operator tile M=%d S=%d P=%d", sh.M, S, sh.P);
     if (sh.kernel == 5 && !perrow_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported per-row tile M=%d S=%d P=%d", sh.M, S, sh.P);
     if ((sh.kernel == 1 || sh.kernel == 2 || sh.kernel == 6) && !shared_supported(dtype, sh))
         return fail(TDMA_EINVAL, "unsupported shared-operator tile M=%d S=%d P=%d", sh.M, S, sh.P);
-    if (sh.kernel == 6 && (int64_t)sh.M * sh.P != layout->n)
-        return fail(TDMA_EINVAL, "kernel 6 needs partitions that cover n exactly (M=%d P=%d, n = %lld)",
+    if (sh.kernel == 7 && (int64_t)sh.M * sh.P != layout->n)
+        return fail(TDMA_EINVAL, "kernel 7 needs partitions that cover n exactly (M=%d P=%d, n = %lld)",
                     sh.M, sh.P, (long long)layout->n);
+    if (sh.kernel == 6 && !shared_roll_ok(make_map(layout), sh))
+        return fail(TDMA_EINVAL, "kernel 6 needs strided rows and partitions that cover n exactly "
+                    "(M=%d P=%d, n = %lld)", sh.M, sh.P, (long long)layout->n);
     if ((int64_t)sh.M * sh.P < layout->n) return fail(TDMA_EINVAL, "tile covers %lld rows < n = %lld",
                                                       (long long)sh.M * sh.P, (long long)layout->n);
     if (sh.kernel == 0 && sh.contig && fused_lds_bytes(dtype, sh) > 160 * 1024)

@@ -141,11 +141,14 @@ std::vector<TileShape> fused_candidates(int dtype, const tdma_layout *L, const t
             while ((int64_t)P * M < n) P <<= 1;
             if (P > 64) continue;
             for (int S_log2 = 0; S_log2 <= 6; ++S_log2) {
-                for (int kind : {1, 2}) {
+                for (int kind : {1, 2, 6}) {
+                    // the rolling form (6): strided rows, partitions covering n
+                    if (kind == 6 && (contig || (int64_t)P * M != n)) continue;
                     TileShape sh;
                     sh.kernel = kind; sh.M = M; sh.P = P; sh.S_log2 = S_log2; sh.contig = contig;
                     if ((1 << S_log2) * P < 64 && (int64_t)(1 << S_log2) < nsys) continue;
-                    if (shared_supported(dtype, sh)) out.push_back(sh);
+                    if (shared_supported(dtype, sh) && (kind != 6 || shared_roll_ok(make_map(L), sh)))
+                        out.push_back(sh);
                 }
             }
         }
@@ -161,8 +164,9 @@ std::vector<TileShape> fused_candidates(int dtype, const tdma_layout *L, const t
             while ((int64_t)P * M < n) P <<= 1;
             if (P > 64) continue;
             for (int S_log2 = 2; S_log2 <= 5; ++S_log2) {
-                for (int kind : {3, 4, 5}) {
+                for (int kind : {3, 4, 5, 7}) {
                     if ((kind == 5) != perrow_op) continue;
+                    if (kind == 7 && (int64_t)P * M != n) continue;
                     TileShape sh;
                     sh.kernel = kind; sh.M = M; sh.P = P; sh.S_log2 = S_log2; sh.contig = false;
                     const bool ok = kind == 5 ? perrow_supported(dtype, sh) && perrow_layout_ok(m, sh)

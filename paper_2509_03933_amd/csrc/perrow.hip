@@ -94,7 +94,7 @@ __device__ __forceinline__ void load_window(const RowArrays<T> &in, int64_t o0, 
 // tile's row 0 at no); the window holds rows 0..W-1 of the tile on entry
 // and rows 0..W-1 of the next tile on return.  Every thread of the block
 // calls it.
-template <typename T, int M, int W, bool FULL>
+template <typename T, int M, int W, bool FULL, int PQ>
 __device__ __forceinline__ void perrow_solve(double *XC, int S, int s, int p, int P, int P_log2,
                                              int jl, int64_t rs, const RowArrays<T> &in,
                                              Window<T, W> &win, int64_t o0, int64_t no, T *x,
@@ -175,7 +175,7 @@ __device__ __forceinline__ void perrow_solve(double *XC, int S, int s, int p, in
 
     // Stage B
     double xfd, xld;
-    iface_pcr(XC, S, s, p, P, P_log2, f, xfd, xld, bad);
+    iface_stage_b<PQ>(XC, S, s, p, P, P_log2, f, xfd, xld, bad);
 
     // Stage C, forward: e_j in place of delta_j
     const T xf = (T)xfd;
@@ -203,7 +203,7 @@ __device__ __forceinline__ void perrow_solve(double *XC, int S, int s, int p, in
 
 // Resident workgroups walk the tiles t0, t0 + G, ...; a lane past the last
 // system solves a copy of system 0's rows and stores nothing.
-template <typename T, int M, int W, bool FULL>
+template <typename T, int M, int W, bool FULL, int PQ>
 __global__ void __launch_bounds__((perrow_max_threads<T, M>()))
 k_perrow_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int32_t ntiles,
                 int *err) {
@@ -242,7 +242,7 @@ k_perrow_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2,
         const bool nok = w.k < nsys;
         const int64_t no = origin(w, nok);
         bool bad_t = false;
-        perrow_solve<T, M, W, FULL>(lds, S, s, p, P, P_log2, jl, rs, in, win, o0, no, x, ok, bad_t);
+        perrow_solve<T, M, W, FULL, PQ>(lds, S, s, p, P, P_log2, jl, rs, in, win, o0, no, x, ok, bad_t);
         bad |= bad_t && ok;
         t += gridDim.x;
         if (t >= ntiles) break;
@@ -252,9 +252,9 @@ k_perrow_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2,
     if (bad) atomicOr(err, 1);
 }
 
-template <typename T, int M, int W, bool FULL>
-hipError_t launch_pr(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d, void *x,
-                     int *err, hipStream_t st) {
+template <typename T, int M, int W, bool FULL, int PQ>
+hipError_t launch_prq(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d, void *x,
+                      int *err, hipStream_t st) {
     const int S = 1 << sh.S_log2;
     const int P_log2 = __builtin_ctz((unsigned)sh.P);
     const size_t lds = perrow_lds_bytes(sh);
@@ -264,15 +264,24 @@ hipError_t launch_pr(const SysMap &map, const Coef &coef, const TileShape &sh, c
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_perrow_stream<T, M, W, FULL>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_perrow_stream<T, M, W, FULL, PQ>,
                                                          sh.threads(), lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     const int64_t resident = (int64_t)cus * per_cu;
     const int64_t grid = ntiles < resident ? ntiles : resident;
-    hipLaunchKernelGGL((k_perrow_stream<T, M, W, FULL>), dim3((unsigned)grid), dim3(sh.threads()), lds,
+    hipLaunchKernelGGL((k_perrow_stream<T, M, W, FULL, PQ>), dim3((unsigned)grid), dim3(sh.threads()), lds,
                        st, map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, (int32_t)ntiles, err);
     return hipGetLastError();
+}
+
+// Stage B in its wavefront-shuffle form: the DPP form's extra registers cost
+// this kernel more in spills than its shorter interface solve saves (1024^3
+// per-row lines: 12.0 against 10.8 ms).
+template <typename T, int M, int W, bool FULL>
+hipError_t launch_pr(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d, void *x,
+                     int *err, hipStream_t st) {
+    return launch_prq<T, M, W, FULL, 0>(map, coef, sh, d, x, err, st);
 }
 
 template <typename T, int M, int W>

@@ -1343,6 +1343,13 @@ bool shared_supported(int dtype, const TileShape &sh) {
     return shared_lds_bytes(dtype, sh) <= 160 * 1024;
 }
 
+bool shared_roll_ok(const SysMap &map, const TileShape &sh) {
+    const int64_t S = (int64_t)1 << sh.S_log2;
+    const int64_t blocks = (map.nsys + S - 1) / S;
+    return !sh.contig && !map.offsets && !map.sys_list && !map.count &&
+           (int64_t)sh.P * sh.M == map.n && 2 * (blocks + 1) * S < ((int64_t)1 << 31);
+}
+
 hipError_t launch_shared(int dtype, const SysMap &map, const Coef &coef, const TileShape &sh,
                          const void *d, void *x, int *err, hipStream_t st) {
     const size_t lds = shared_lds_bytes(dtype, sh);

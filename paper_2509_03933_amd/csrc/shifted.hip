@@ -31,6 +31,15 @@
 // issued in bursts: 4.79 ms against 5.38 ms for whole-tile loads and stores,
 // and 4.98 ms for a second register set filled during the interface solve
 // (a set filled at the start of a tile measured 6.83 ms).
+//
+// Stage B is where every wave of the workgroup waits and no row moves; with
+// 16 or 32 partitions it runs in its DPP form (iface_pcr_rows: neighbour rows
+// as VALU operands, not LDS permutes): 4.8 -> 4.5 ms.  The width of a tile row
+// then decides the rest: a copy with this walk moves 128-byte rows at 0.55 of
+// HBM peak and 256-byte rows at 0.65, and a 32-system tile at 32 rows per
+// lane needs the whole register file when the pivots are kept beside the
+// right-hand sides.  The walk that recomputes them (kernel 7,
+// shift_solve_recomp) fits 32 systems in 1024 lanes: 4.0 ms, 0.53 of peak.
 #include <type_traits>
 
 #include "refine.h"
@@ -47,6 +56,9 @@ template <> struct Pair2<double> { using type = double2; };
 template <> struct Pair2<float> { using type = float2; };
 
 __host__ __device__ inline size_t al16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+// Interior rows per segment of the pivot-recomputing solve's backward pass.
+constexpr int kRecompSeg = 8;
 
 // LDS carve-up (byte offsets): the operator's rows per partition with a pitch
 // of M+1 rows (the partitions a wavefront reads at once then sit on different
@@ -110,7 +122,7 @@ struct LaneIo {
 // row M-1-j of the next tile (ascending order), which puts that tile in the
 // other layout (FL of the next call = 1 - FL).  Every thread of the block
 // calls it.
-template <typename T, int M, int FL, bool ROLL>
+template <typename T, int M, int FL, bool ROLL, int PQ>
 __device__ __forceinline__ void shift_solve(const char *base, const ShiftLds &L, int S, int s,
                                             int p, int P, int P_log2, T sh, T (&v)[M],
                                             const LaneIo<T> &io, bool &bad) {
@@ -187,7 +199,7 @@ __device__ __forceinline__ void shift_solve(const char *base, const ShiftLds &L,
 
     // Stage B
     double xfd, xld;
-    iface_pcr(XC, S, s, p, P, P_log2, f, xfd, xld, bad);
+    iface_stage_b<PQ>(XC, S, s, p, P, P_log2, f, xfd, xld, bad);
 
     // Stage C, forward: e_j in place of d_j
     const T xf = (T)xfd;
@@ -231,6 +243,149 @@ __device__ __forceinline__ void shift_solve(const char *base, const ShiftLds &L,
         v[slot(0)] = xf;
 }
 
+// The same solve (FP64, walk rolling on) holding one value per row: the
+// right-hand side, then e_j.  The pivot reciprocals are not kept from Stage
+// A but recomputed from the LDS rows and the shift: once in Stage C's forward
+// pass, which also records c_j g_j at the last row of every K-row segment of
+// the interior, and once more per segment in the backward pass, forward from
+// the segment's checkpoint into K registers that the substitution reads in
+// reverse.  Every recomputed value comes from the same operations as in
+// Stage A, so the results equal shift_solve's.  Three pivot recurrences per
+// row instead of one for M + M/K + K values per lane instead of 2M: at
+// M = 32 a lane's rows fit the 128 registers of a 1024-lane workgroup, and a
+// tile can be 32 FP64 systems (256-byte rows) wide.
+template <int M, int FL, int K, int PQ>
+__device__ __forceinline__ void shift_solve_recomp(const char *base, const ShiftLds &L, int S, int s,
+                                                   int p, int P, int P_log2, double sh,
+                                                   double (&v)[M], const LaneIo<double> &io,
+                                                   bool &bad) {
+    static_assert(M >= 4 && K >= 1, "a partition needs rows 0, M-1 and an interior");
+    using T = double;
+    using T2 = double2;
+    auto slot = [](int j) { return FL == 1 ? M - 1 - j : j; };
+    const int q0 = p * (M + 1);
+    const T2 *AB0 = reinterpret_cast<const T2 *>(base + L.ab);
+    const T2 *CM0 = reinterpret_cast<const T2 *>(base + L.cm);
+    const T2 *AB = AB0 + opaque(q0), *CM = CM0 + opaque(q0);
+    // Each group of four rows reads the operator rows through an offset that
+    // the compiler takes to depend on the running value of the recurrence, so
+    // the reads of later rows wait for the rows before them instead of all
+    // being issued at once into registers.
+    auto rows_group = [&](T dep) {
+        int q = q0;
+        asm volatile("" : "+v"(q) : "v"(dep));
+        AB = AB0 + q;
+        CM = CM0 + q;
+    };
+    double *XC = reinterpret_cast<double *>(const_cast<char *>(base) + L.xc);
+
+    // Stage A: as shift_solve, keeping no pivots
+    T2 ab = AB[0], cm = CM[0];
+    T piv = ab.y + cm.y * sh;
+    bad |= dev::bad_pivot(piv);
+    T gj = dev::recip(piv);
+    const T a0 = ab.x * gj, c0 = cm.x * gj, d0 = v[slot(0)] * gj;
+    ab = AB[1];
+    cm = CM[1];
+    piv = ab.y + cm.y * sh;
+    bad |= dev::bad_pivot(piv);
+    gj = dev::recip(piv);
+    T dh = v[slot(1)] * gj, ah = ab.x * gj, ch = cm.x * gj;
+    T pi = T(1), dt1 = dh, at1 = ah;
+#pragma unroll
+    for (int j = 2; j < M; ++j) {
+        if ((j & 3) == 0) rows_group(ch);
+        ab = AB[j];
+        cm = CM[j];
+        piv = (ab.y + cm.y * sh) - ab.x * ch;
+        bad |= dev::bad_pivot(piv);
+        gj = dev::recip(piv);
+        dh = (v[slot(j)] - ab.x * dh) * gj;
+        ah = -(ab.x * gj) * ah;
+        pi = -ch * pi;
+        ch = cm.x * gj;
+        if (j <= M - 2) {
+            dt1 += pi * dh;
+            at1 += pi * ah;
+        }
+        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    Iface f;
+    {
+        const double ct1 = -pi;
+        const double den = 1.0 - c0 * at1;
+        bad |= dev::bad_pivot(den);
+        const double rho = dev::recip(den);
+        f.fa = rho * a0;
+        f.fc = -rho * c0 * ct1;
+        f.fd = rho * (d0 - c0 * dt1);
+        f.la = ah;
+        f.lc = ch;
+        f.ld = dh;
+    }
+
+    // Stage B
+    double xfd, xld;
+    iface_stage_b<PQ>(XC, S, s, p, P, P_log2, f, xfd, xld, bad);
+
+    // the pivot of interior row j from c_{j-1} g_{j-1} (row 1 has none)
+    auto pivot = [&](int j, T2 abj, T2 cmj, T chp) {
+        return j == 1 ? abj.y + cmj.y * sh : (abj.y + cmj.y * sh) - abj.x * chp;
+    };
+    // Stage C, forward: e_j in place of d_j; ck[i] = c_j g_j at the last row
+    // of interior segment i (rows 1 + iK .. (i+1)K)
+    constexpr int NI = M - 2;
+    constexpr int NSEG = (NI + K - 1) / K;
+    T ck[NSEG];
+    T e = xfd, chp = T(0);
+#pragma unroll
+    for (int j = 1; j <= M - 2; ++j) {
+        if ((j & 3) == 1) rows_group(e);
+        const T2 abj = AB[j], cmj = CM[j];
+        const T g = dev::recip(pivot(j, abj, cmj, chp));
+        e = (v[slot(j)] - abj.x * e) * g;
+        v[slot(j)] = e;
+        chp = cmj.x * g;
+        if (j % K == 0) ck[j / K - 1] = chp;
+        if ((j & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+    }
+    // backward, one segment at a time from the last: its c_j g_j recomputed
+    // forward from the checkpoint, then x_j stored at once and, the walk
+    // rolling on, the register refilled with the next tile's row M-1-j
+    int64_t xo = io.xo + (int64_t)(M - 1) * io.rs;
+    int64_t no = io.no;
+    T xn = xld;
+    if (io.valid) __builtin_nontemporal_store(xn, io.x + xo);
+    v[slot(M - 1)] = __builtin_nontemporal_load(io.d + no);
+#pragma unroll
+    for (int i = NSEG - 1; i >= 0; --i) {
+        const int j0 = 1 + i * K, j1 = (i + 1) * K < M - 2 ? (i + 1) * K : M - 2;
+        T chs[K];
+        T c = i == 0 ? T(0) : ck[i - 1];
+        rows_group(xn);
+#pragma unroll
+        for (int j = j0; j <= j1; ++j) {
+            if (j > j0 && ((j - j0) & 3) == 0) rows_group(c);
+            const T2 abj = AB[j], cmj = CM[j];
+            c = cmj.x * dev::recip(pivot(j, abj, cmj, c));
+            chs[j - j0] = c;
+        }
+#pragma unroll
+        for (int j = j1; j >= j0; --j) {
+            T xj = v[slot(j)] - chs[j - j0] * xn;
+            xj = opaque(xj);
+            xo = opaque(xo - io.rs);
+            if (io.valid) __builtin_nontemporal_store(xj, io.x + xo);
+            no = opaque(no + io.rs);
+            v[slot(j)] = __builtin_nontemporal_load(io.d + no);
+            xn = xj;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (io.valid) __builtin_nontemporal_store((T)xfd, io.x + io.xo);
+    v[slot(0)] = __builtin_nontemporal_load(io.d + (no + io.rs));
+}
+
 // The lane's M rows of d (system base `sb` in elements, `valid` false past the
 // last system; a lane past the last system reads the start of the array).
 // The loads stop at row n-1 and the rows at or past n are zeroed.  Every
@@ -261,11 +416,14 @@ constexpr int shift_max_threads() { return (int)sizeof(T) * M >= 256 ? 512 : 102
 // tiles sharing lines run under one L2).  ROLL (P*M == n): the next tile's
 // right-hand sides are loaded row by row into the registers that Stage C
 // frees (shift_solve), alternating the register layout between tiles;
-// otherwise each tile is loaded whole at its start.
-template <typename T, int M, bool ROLL>
-__global__ void __launch_bounds__((shift_max_threads<T, M>()))
+// otherwise each tile is loaded whole at its start.  RC (FP64, ROLL): the
+// solve that recomputes its pivots (shift_solve_recomp), in workgroups of up
+// to 1024 lanes.
+template <typename T, int M, bool ROLL, bool RC, int PQ>
+__global__ void __launch_bounds__((RC ? 1024 : shift_max_threads<T, M>()))
 k_shift_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, int32_t ntiles,
                int *err) {
+    static_assert(!RC || (ROLL && std::is_same<T, double>::value), "RC: FP64, rolling walk");
     extern __shared__ double lds[];
     char *base = reinterpret_cast<char *>(lds);
     const int tid = threadIdx.x;
@@ -310,7 +468,10 @@ k_shift_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, 
             io.rs = rs;
             io.nrow = M;
             io.valid = ok;
-            shift_solve<T, M, F, true>(base, L, S, s, p, P, P_log2, sh, v, io, bad);
+            if constexpr (RC)
+                shift_solve_recomp<M, F, kRecompSeg, PQ>(base, L, S, s, p, P, P_log2, sh, v, io, bad);
+            else
+                shift_solve<T, M, F, true, PQ>(base, L, S, s, p, P, P_log2, sh, v, io, bad);
             b = nb;
             ok = nok;
             sh = nsh;
@@ -333,7 +494,7 @@ k_shift_stream(SysMap map, Coef coef, const T *d, T *x, int S_log2, int P_log2, 
             io.rs = rs;
             io.nrow = nrow;
             io.valid = ok;
-            shift_solve<T, M, 0, false>(base, L, S, s, p, P, P_log2, sh, v, io, bad);
+            shift_solve<T, M, 0, false, PQ>(base, L, S, s, p, P, P_log2, sh, v, io, bad);
             t += gridDim.x;
             if (t >= ntiles) break;
             w.advance(nsys0, step);
@@ -371,7 +532,7 @@ __host__ __device__ inline size_t shift_refine_lds(int M, int P, int S, size_t *
     return al16(g + (size_t)M * S * P * sizeof(float));
 }
 
-template <int M>
+template <int M, int PQ>
 __device__ __forceinline__ double shift_refine_tile(const char *base, const ShiftLds &L,
                                                     const float4 *R32, float *G, int S, int s, int p, int P,
                                                     int P_log2, double sh, const double (&dv)[M],
@@ -501,7 +662,7 @@ __device__ __forceinline__ double shift_refine_tile(const char *base, const Shif
         f.lc = lc;
         f.ld = (double)dh;
         double xf, xl;
-        iface_pcr(XC, S, s, p, P, P_log2, f, xf, xl, bad);
+        iface_stage_b<PQ>(XC, S, s, p, P, P_log2, f, xf, xl, bad);
         // Stage C (FP32) on the correction, added to x in FP64
         const float xff = (float)xf;
         float ee = xff;
@@ -577,7 +738,7 @@ __device__ __forceinline__ double shift_refine_tile(const char *base, const Shif
 // refinement on chip, then each row of x is stored and its register
 // refilled with the next tile's row of d.  Every lane folds its largest
 // ratio into the state once, at the end (one atomic per wavefront at most).
-template <int M, bool FULL>
+template <int M, bool FULL, int PQ>
 __global__ void __launch_bounds__((shift_max_threads<double, M>()))
 k_shift_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, int P_log2,
                int32_t ntiles, int iters, double tol, RefineState *state) {
@@ -631,7 +792,7 @@ k_shift_refine(SysMap map, Coef coef, const double *d, double *x, int S_log2, in
     }
     double rel = 0.0;
     for (;;) {
-        rel = fmax(rel, shift_refine_tile<M>(base, L, R32, G, S, s, p, P, P_log2, sh, dv, xv, iters, tol,
+        rel = fmax(rel, shift_refine_tile<M, PQ>(base, L, R32, G, S, s, p, P, P_log2, sh, dv, xv, iters, tol,
                                              ok, id, state));
         t += gridDim.x;
         const bool more = t < ntiles;
@@ -679,34 +840,54 @@ int64_t resident_of(K kernel, int threads, size_t lds) {
     return (int64_t)cus * per_cu;
 }
 
-template <typename T, int M, bool ROLL>
-hipError_t launch_t(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d, void *x,
-                    int *err, hipStream_t st) {
+template <typename T, int M, bool ROLL, bool RC, int PQ>
+hipError_t launch_tq(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d, void *x,
+                     int *err, hipStream_t st) {
     const int S = 1 << sh.S_log2;
     const int P_log2 = __builtin_ctz((unsigned)sh.P);
     const size_t lds = shift_layout(sizeof(T), M, sh.P, S).end;
     const int64_t ntiles = (map.nsys + S - 1) / S;
     if (ntiles == 0) return hipSuccess;
-    const int64_t resident = resident_of(k_shift_stream<T, M, ROLL>, sh.threads(), lds);
+    const int64_t resident = resident_of(k_shift_stream<T, M, ROLL, RC, PQ>, sh.threads(), lds);
     if (resident < 1) return hipErrorInvalidConfiguration;
     const int64_t grid = ntiles < resident ? ntiles : resident;
-    hipLaunchKernelGGL((k_shift_stream<T, M, ROLL>), dim3((unsigned)grid), dim3(sh.threads()), lds,
+    hipLaunchKernelGGL((k_shift_stream<T, M, ROLL, RC, PQ>), dim3((unsigned)grid), dim3(sh.threads()), lds,
                        st, map, coef, (const T *)d, (T *)x, sh.S_log2, P_log2, (int32_t)ntiles, err);
     return hipGetLastError();
+}
+
+// 16 and 32 partitions take the DPP form of Stage B (its partition count
+// fixed at compile time), other counts the wavefront-shuffle form.
+template <typename T, int M, bool ROLL, bool RC = false>
+hipError_t launch_t(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d, void *x,
+                    int *err, hipStream_t st) {
+    switch (sh.P) {
+        case 16: return launch_tq<T, M, ROLL, RC, 2>(map, coef, sh, d, x, err, st);
+        case 32: return launch_tq<T, M, ROLL, RC, 4>(map, coef, sh, d, x, err, st);
+    }
+    return launch_tq<T, M, ROLL, RC, 0>(map, coef, sh, d, x, err, st);
 }
 
 template <typename T, int M>
 hipError_t launch_m(const SysMap &map, const Coef &coef, const TileShape &sh, const void *d, void *x,
                     int *err, hipStream_t st) {
     // kernel 3 rolls the walk on when the partitions cover n exactly; kernel 4
-    // (and padded lengths) load each tile at its start
+    // (and padded lengths) load each tile at its start; kernel 7 (FP64, P*M =
+    // n) recomputes its pivots
+    if constexpr (std::is_same<T, double>::value && (M == 16 || M == 32)) {
+        if (sh.kernel == 7) {
+            if ((int64_t)sh.P * M != map.n) return hipErrorInvalidValue;
+            return launch_t<T, M, true, true>(map, coef, sh, d, x, err, st);
+        }
+    }
+    if (sh.kernel == 7) return hipErrorInvalidValue;
     const bool roll = sh.kernel == 3 && (int64_t)sh.P * M == map.n;
     return roll ? launch_t<T, M, true>(map, coef, sh, d, x, err, st)
                 : launch_t<T, M, false>(map, coef, sh, d, x, err, st);
 }
 
-template <int M, bool FULL>
-hipError_t launch_refine_m(const SysMap &map, const Coef &coef, const TileShape &sh, const double *d,
+template <int M, bool FULL, int PQ>
+hipError_t launch_refine_q(const SysMap &map, const Coef &coef, const TileShape &sh, const double *d,
                            double *x, int iters, double tol, RefineState *state, hipStream_t st) {
     const int S = 1 << sh.S_log2;
     const int P_log2 = __builtin_ctz((unsigned)sh.P);
@@ -714,12 +895,21 @@ hipError_t launch_refine_m(const SysMap &map, const Coef &coef, const TileShape 
     const size_t lds = shift_refine_lds(M, sh.P, S, &f32_off);
     const int64_t ntiles = (map.nsys + S - 1) / S;
     if (ntiles == 0) return hipSuccess;
-    const int64_t resident = resident_of(k_shift_refine<M, FULL>, sh.threads(), lds);
+    const int64_t resident = resident_of(k_shift_refine<M, FULL, PQ>, sh.threads(), lds);
     if (resident < 1) return hipErrorInvalidConfiguration;
     const int64_t grid = ntiles < resident ? ntiles : resident;
-    hipLaunchKernelGGL((k_shift_refine<M, FULL>), dim3((unsigned)grid), dim3(sh.threads()), lds, st, map,
+    hipLaunchKernelGGL((k_shift_refine<M, FULL, PQ>), dim3((unsigned)grid), dim3(sh.threads()), lds, st, map,
                        coef, d, x, sh.S_log2, P_log2, (int32_t)ntiles, iters, tol, state);
     return hipGetLastError();
+}
+
+// The precision form keeps the wavefront-shuffle Stage B: the DPP form's
+// extra registers beside its FP64 d and x rows cost more in spills than the
+// shorter interface solve saves (1024^3 Poisson lines: 12.3 against 11.5 ms).
+template <int M, bool FULL>
+hipError_t launch_refine_m(const SysMap &map, const Coef &coef, const TileShape &sh, const double *d,
+                           double *x, int iters, double tol, RefineState *state, hipStream_t st) {
+    return launch_refine_q<M, FULL, 0>(map, coef, sh, d, x, iters, tol, state, st);
 }
 
 }  // namespace
@@ -730,10 +920,11 @@ size_t shift_lds_bytes(int dtype, const TileShape &sh) {
 }
 
 bool shift_supported(int dtype, const TileShape &sh) {
-    if (sh.kernel != 3 && sh.kernel != 4) return false;
+    if (sh.kernel != 3 && sh.kernel != 4 && sh.kernel != 7) return false;
     if (sh.contig || sh.pdd) return false;
     if (sh.P < 1 || sh.P > 64 || (sh.P & (sh.P - 1)) != 0) return false;
-    const int maxt = dtype == TDMA_F64 && sh.M == 32 ? 512 : 1024;
+    if (sh.kernel == 7 && (dtype != TDMA_F64 || (sh.M != 16 && sh.M != 32))) return false;
+    const int maxt = dtype == TDMA_F64 && sh.M == 32 && sh.kernel != 7 ? 512 : 1024;
     if (sh.S_log2 < 0 || sh.threads() > maxt || sh.threads() < 1) return false;
     if (dtype == TDMA_F64 && sh.M != 8 && sh.M != 16 && sh.M != 32) return false;
     if (dtype == TDMA_F32 && sh.M != 8 && sh.M != 16 && sh.M != 32) return false;

@@ -42,7 +42,9 @@ struct TileShape {
                             // same loading each tile at its start (shifted.hip),
                             // 5: per-row coefficients, streaming (perrow.hip),
                             // 6: kernel 2 with one register set refilled as
-                            // Stage C stores (partitions covering n exactly)
+                            // Stage C stores (partitions covering n exactly),
+                            // 7: kernel 3 keeping only the right-hand sides and
+                            // recomputing the pivots (FP64, P*M = n)
     bool pdd = false;       // kernel 0 only: Stage B by the PDD approximation
     int threads() const { return (1 << S_log2) * P; }
 };
@@ -61,6 +63,9 @@ size_t fused_lds_bytes(int dtype, const TileShape &shape, bool shared_rows = fal
 hipError_t launch_shared(int dtype, const SysMap &map, const Coef &coef, const TileShape &shape,
                          const void *d, void *x, int *err_flag, hipStream_t stream);
 bool shared_supported(int dtype, const TileShape &shape);
+// whether the rolling form (kernel 6) runs this map: strided rows of a plain
+// uniform layout, P*M = n, 32-bit walk indices
+bool shared_roll_ok(const SysMap &map, const TileShape &shape);
 // lanes per block of the shared-operator kernels (kernel 2 with contiguous
 // rows: the form that streams them, which holds two tiles in registers)
 int shared_max_threads(int dtype, int M, int kernel, bool contig);

@@ -2,6 +2,7 @@
 // perrow.hip): the system walk of resident workgroups, the wavefront PCR of
 // the interface system, and a register barrier for the compiler.
 #pragma once
+#include <type_traits>
 #include "tile.hip.h"
 
 namespace tdma {
@@ -109,6 +110,128 @@ __device__ __forceinline__ void iface_pcr(double *XC, int S, int s, int p, int P
     __syncthreads();
     x_first = rd[s * pitch + 2 * p];
     x_last = rd[s * pitch + 2 * p + 1];
+}
+
+// The value of `v` in the lane M positions lower (SHR) / higher in the
+// caller's row of 16 lanes, zero when that lane lies outside the row: a DPP
+// row shift, a VALU operand modifier instead of an LDS permute.
+template <int M, bool SHR>
+__device__ __forceinline__ double row_shift(double v) {
+    static_assert(M >= 1 && M < 16, "a DPP row shift moves 1..15 lanes");
+    constexpr int ctrl = (SHR ? 0x110 : 0x100) + M;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, ctrl, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Stage B with every system's 2P interface rows on the 16 lanes of one DPP
+// row, Q = 2P/16 consecutive rows per lane (P = 8Q, Q = 2 or 4, so that the
+// S*P lanes of the workgroup cover the S*16 of the PCR): the PCR steps at
+// distance h take their neighbour rows from the lane itself or, across lane
+// boundaries, from the lanes h/Q (at least 1) away by DPP row shifts, whose
+// zero outside the row stands for the missing rows beyond the system's ends.
+// Against iface_pcr (two rows per lane, wavefront shuffles), every exchange
+// is a VALU operand instead of an LDS round trip, which shortens the
+// interface solve that all the workgroup's waves wait on.  The rows go
+// through LDS (XC, layout of iface_pcr) both ways.  Every thread of the
+// block calls it; threads past S*16 idle in the PCR.  Returns X_{2p} and
+// X_{2p+1} of the caller's system.
+template <int Q>
+__device__ __forceinline__ void iface_pcr_rows(double *XC, int S, int s, int p, const Iface &f,
+                                               double &x_first, double &x_last, bool &bad) {
+    static_assert(Q == 2 || Q == 4, "16 or 32 partitions");
+    constexpr int P = 8 * Q, R2 = 2 * P;
+    constexpr int pitch = R2 + 1;
+    double *ra = XC, *rc = XC + S * pitch, *rd = XC + 2 * S * pitch;
+    __syncthreads();   // the exchange is free (previous tile done reading it)
+    {
+        const int q = s * pitch + 2 * p;
+        ra[q] = f.fa; rc[q] = f.fc; rd[q] = f.fd;
+        ra[q + 1] = f.la; rc[q + 1] = f.lc; rd[q + 1] = f.ld;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int s2 = t >> 4, l = t & 15;
+    if (s2 < S) {
+        const int q2 = s2 * pitch + Q * l;
+        double a[Q], c[Q], d[Q];
+#pragma unroll
+        for (int e = 0; e < Q; ++e) {
+            a[e] = ra[q2 + e];
+            c[e] = rc[q2 + e];
+            d[e] = rd[q2 + e];
+        }
+        // one PCR step at distance H: row Q*l + e meets rows Q*l + e -+ H.
+        // At H >= Q the neighbours are row e of the lanes H/Q away, fetched
+        // just before row e is updated in place (every lane runs the same
+        // instructions, so the fetch sees the old values); below Q some are
+        // rows of the lane itself, taken from a copy of the old rows.
+        auto step = [&](auto hc) {
+            constexpr int H = decltype(hc)::value;
+            if constexpr (H >= Q) {
+                constexpr int L = H / Q;
+#pragma unroll
+                for (int e = 0; e < Q; ++e) {
+                    const double al = row_shift<L, true>(a[e]), cl = row_shift<L, true>(c[e]),
+                                 dl = row_shift<L, true>(d[e]);
+                    const double au = row_shift<L, false>(a[e]), cu = row_shift<L, false>(c[e]),
+                                 du = row_shift<L, false>(d[e]);
+                    pcr_step_row(a[e], c[e], d[e], al, cl, dl, au, cu, du, bad);
+                }
+            } else {
+                double oa[Q], oc[Q], od[Q];
+#pragma unroll
+                for (int e = 0; e < Q; ++e) {
+                    oa[e] = a[e]; oc[e] = c[e]; od[e] = d[e];
+                }
+#pragma unroll
+                for (int e = 0; e < Q; ++e) {
+                    double al, cl, dl, au, cu, du;
+                    if (e - H >= 0) {
+                        al = oa[e - H]; cl = oc[e - H]; dl = od[e - H];
+                    } else {
+                        al = row_shift<1, true>(oa[e - H + Q]);
+                        cl = row_shift<1, true>(oc[e - H + Q]);
+                        dl = row_shift<1, true>(od[e - H + Q]);
+                    }
+                    if (e + H < Q) {
+                        au = oa[e + H]; cu = oc[e + H]; du = od[e + H];
+                    } else {
+                        au = row_shift<1, false>(oa[e + H - Q]);
+                        cu = row_shift<1, false>(oc[e + H - Q]);
+                        du = row_shift<1, false>(od[e + H - Q]);
+                    }
+                    pcr_step_row(a[e], c[e], d[e], al, cl, dl, au, cu, du, bad);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        step(std::integral_constant<int, 1>{});
+        step(std::integral_constant<int, 2>{});
+        step(std::integral_constant<int, 4>{});
+        step(std::integral_constant<int, 8>{});
+        step(std::integral_constant<int, 16>{});
+        if constexpr (R2 > 32) step(std::integral_constant<int, 32>{});
+        // each lane overwrites only its own rows: no barrier needed before
+#pragma unroll
+        for (int e = 0; e < Q; ++e) rd[q2 + e] = d[e];
+    }
+    __syncthreads();
+    x_first = rd[s * pitch + 2 * p];
+    x_last = rd[s * pitch + 2 * p + 1];
+}
+
+// Stage B: with PQ = 2 or 4 (P = 8 PQ partitions, fixed at compile time) the
+// DPP form, else iface_pcr for any P.
+template <int PQ>
+__device__ __forceinline__ void iface_stage_b(double *XC, int S, int s, int p, int P, int P_log2,
+                                              const Iface &f, double &x_first, double &x_last,
+                                              bool &bad) {
+    if constexpr (PQ > 0)
+        iface_pcr_rows<PQ>(XC, S, s, p, f, x_first, x_last, bad);
+    else
+        iface_pcr(XC, S, s, p, P, P_log2, f, x_first, x_last, bad);
 }
 
 // A value the compiler cannot see through (it is then recomputed or

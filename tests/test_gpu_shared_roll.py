@@ -85,3 +85,14 @@ def test_needs_exact_cover():
     with pytest.raises(tdma.TdmaError):
         tdma.solve_batched_tiled(p.layout, coeffs, td, torch.empty_like(td), M=16, S=16, P=16,
                                  kernel=6)
+
+
+def test_refuses_contiguous_rows():
+    """Kernel 6 walks strided rows only; contiguous rows are refused."""
+    import paper_2509_03933_amd as tdma
+    px, _, _ = configs.sweeps(64, 4, 4)
+    a, b, c, d = parity.host_problem(px)
+    coeffs = parity.device_coeffs(px, a, b, c, torch.float64)
+    (td,) = parity.to_device([d], torch.float64)
+    with pytest.raises(tdma.TdmaError):
+        tdma.solve_batched_tiled(px.layout, coeffs, td, torch.empty_like(td), M=16, S=16, P=4, kernel=6)

@@ -2,9 +2,11 @@
 plus a per-system diagonal shift on strided layouts: the FFT-Poisson lines)
 against the oracle, through tdma_solve_batched and tdma_solve_batched_tiled.
 
-kernel 3 walks the tiles with two register sets, kernel 4 with one; both
-keep d and the pivot reciprocals per row and re-solve the partition interior
-from d in Stage C.  Shapes cover P*M == n (no padding) and padded lengths,
+kernel 3 walks the tiles loading the next tile's rows as the current one is
+stored, kernel 4 loads each tile at its start; both keep d and the pivot
+reciprocals per row and re-solve the partition interior from d in Stage C.
+Kernel 7 (FP64, partitions covering n) keeps d alone and recomputes the
+pivots in Stage C, in workgroups of up to 1024 lanes.  Shapes cover P*M == n (no padding) and padded lengths,
 tile widths from one to 32 systems, a last tile that is only partly filled,
 M = 8, 16 (and 32 in FP32), FP32, and in-place solves."""
 import dataclasses
@@ -51,9 +53,12 @@ SHAPES_1024 = [dict(M=16, S=16, P=64, kernel=3), dict(M=16, S=16, P=64, kernel=4
                dict(M=16, S=8, P=64, kernel=3), dict(M=16, S=1, P=64, kernel=4),
                dict(M=16, S=4, P=64, kernel=3), dict(M=32, S=16, P=32, kernel=3),
                dict(M=32, S=16, P=32, kernel=4), dict(M=32, S=8, P=32, kernel=3),
-               dict(M=32, S=2, P=64, kernel=3)]
+               dict(M=32, S=2, P=64, kernel=3), dict(M=32, S=32, P=32, kernel=7),
+               dict(M=32, S=16, P=32, kernel=7), dict(M=16, S=16, P=64, kernel=7),
+               dict(M=32, S=4, P=32, kernel=7), dict(M=16, S=1, P=64, kernel=7)]
 SHAPES_512 = [dict(M=8, S=16, P=64, kernel=3), dict(M=16, S=32, P=32, kernel=3),
-              dict(M=16, S=16, P=32, kernel=4), dict(M=8, S=2, P=64, kernel=4)]
+              dict(M=16, S=16, P=32, kernel=4), dict(M=8, S=2, P=64, kernel=4),
+              dict(M=16, S=32, P=32, kernel=7)]
 _ids = lambda s: "k%d_M%d_S%d_P%d" % (s["kernel"], s["M"], s["S"], s["P"])
 
 
@@ -117,7 +122,31 @@ def test_fp32(shape):
     assert err.max() <= parity.TOL_F32, err.max()
 
 
-@pytest.mark.parametrize("kernel", [3, 4])
+def test_same_results_recomputed_pivots():
+    """Kernel 7 recomputes the pivots of kernel 3 with the same operations
+    (and walks 32-system tiles): identical results, many tiles per
+    workgroup, a partly filled last tile."""
+    p = _shifted(61, 37, 1024)
+    _, x3 = _solve(p, dict(M=32, S=16, P=32, kernel=3))
+    _, x7 = _solve(p, dict(M=32, S=32, P=32, kernel=7))
+    assert np.array_equal(x3, x7)
+
+
+def test_recomputed_pivots_rules():
+    """Kernel 7 takes FP64 with partitions covering n, at most 1024 lanes."""
+    import paper_2509_03933_amd as tdma
+    for p, shape, tt in [(_shifted(8, 8, 1000), dict(M=32, S=16, P=32), torch.float64),
+                         (_shifted(8, 8, 1024), dict(M=32, S=32, P=32), torch.float32),
+                         (_shifted(8, 8, 1024), dict(M=16, S=32, P=64), torch.float64)]:
+        a, b, c, d = parity.host_problem(p)
+        coeffs = parity.device_coeffs(p, a, b, c, tt)
+        (td,) = parity.to_device([d], tt)
+        with pytest.raises(tdma.TdmaError) as ei:
+            tdma.solve_batched_tiled(p.layout, coeffs, td, torch.empty_like(td), kernel=7, **shape)
+        assert ei.value.status == tdma.EINVAL
+
+
+@pytest.mark.parametrize("kernel", [3, 4, 7])
 def test_in_place(kernel):
     """x aliases d: a tile reads all its rows before it writes any."""
     p = _shifted(16, 16, 256)
