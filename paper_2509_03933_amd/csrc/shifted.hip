@@ -253,7 +253,9 @@ __device__ __forceinline__ void shift_solve(const char *base, const ShiftLds &L,
 // Stage A, so the results equal shift_solve's.  Three pivot recurrences per
 // row instead of one for M + M/K + K values per lane instead of 2M: at
 // M = 32 a lane's rows fit the 128 registers of a 1024-lane workgroup, and a
-// tile can be 32 FP64 systems (256-byte rows) wide.
+// tile can be 32 FP64 systems (256-byte rows) wide.  The partitions cover n
+// exactly, so every row is a system row (m_j = 1: the shift is added as is)
+// and a row's operator reads are (a_j, b_j) and c_j, 24 of the 32 bytes.
 template <int M, int FL, int K, int PQ>
 __device__ __forceinline__ void shift_solve_recomp(const char *base, const ShiftLds &L, int S, int s,
                                                    int p, int P, int P_log2, double sh,
@@ -281,13 +283,13 @@ __device__ __forceinline__ void shift_solve_recomp(const char *base, const Shift
 
     // Stage A: as shift_solve, keeping no pivots
     T2 ab = AB[0], cm = CM[0];
-    T piv = ab.y + cm.y * sh;
+    T piv = ab.y + sh;
     bad |= dev::bad_pivot(piv);
     T gj = dev::recip(piv);
     const T a0 = ab.x * gj, c0 = cm.x * gj, d0 = v[slot(0)] * gj;
     ab = AB[1];
     cm = CM[1];
-    piv = ab.y + cm.y * sh;
+    piv = ab.y + sh;
     bad |= dev::bad_pivot(piv);
     gj = dev::recip(piv);
     T dh = v[slot(1)] * gj, ah = ab.x * gj, ch = cm.x * gj;
@@ -297,7 +299,7 @@ __device__ __forceinline__ void shift_solve_recomp(const char *base, const Shift
         if ((j & 3) == 0) rows_group(ch);
         ab = AB[j];
         cm = CM[j];
-        piv = (ab.y + cm.y * sh) - ab.x * ch;
+        piv = (ab.y + sh) - ab.x * ch;
         bad |= dev::bad_pivot(piv);
         gj = dev::recip(piv);
         dh = (v[slot(j)] - ab.x * dh) * gj;
@@ -330,7 +332,7 @@ __device__ __forceinline__ void shift_solve_recomp(const char *base, const Shift
 
     // the pivot of interior row j from c_{j-1} g_{j-1} (row 1 has none)
     auto pivot = [&](int j, T2 abj, T2 cmj, T chp) {
-        return j == 1 ? abj.y + cmj.y * sh : (abj.y + cmj.y * sh) - abj.x * chp;
+        return j == 1 ? abj.y + sh : (abj.y + sh) - abj.x * chp;
     };
     // Stage C, forward: e_j in place of d_j; ck[i] = c_j g_j at the last row
     // of interior segment i (rows 1 + iK .. (i+1)K)

@@ -58,7 +58,8 @@ SHAPES_1024 = [dict(M=16, S=16, P=64, kernel=3), dict(M=16, S=16, P=64, kernel=4
                dict(M=32, S=4, P=32, kernel=7), dict(M=16, S=1, P=64, kernel=7)]
 SHAPES_512 = [dict(M=8, S=16, P=64, kernel=3), dict(M=16, S=32, P=32, kernel=3),
               dict(M=16, S=16, P=32, kernel=4), dict(M=8, S=2, P=64, kernel=4),
-              dict(M=16, S=32, P=32, kernel=7)]
+              dict(M=16, S=32, P=32, kernel=7), dict(M=32, S=32, P=16, kernel=7),
+              dict(M=32, S=16, P=16, kernel=3), dict(M=32, S=4, P=16, kernel=4)]
 _ids = lambda s: "k%d_M%d_S%d_P%d" % (s["kernel"], s["M"], s["S"], s["P"])
 
 
@@ -86,6 +87,20 @@ def test_padded_lengths_fp64(nz, kernel, M):
         P *= 2
     err, _ = _solve(p, dict(M=M, S=16, P=P, kernel=kernel))
     assert err.max() <= parity.TOL_F64, (nz, err.max())
+
+
+def test_default_plan_n512_lines():
+    """Lines of 512 rows: the built-in plan takes 32 rows per lane, 16
+    partitions and 32-system tiles (the interface solve in its DPP form)."""
+    p = configs.poisson(40, 30, 512)
+    err, x = _solve(p)
+    for s in np.nonzero(err > parity.TOL_F64)[0]:
+        if s == 0:
+            continue   # mode (0, 0) carries a placeholder shift in the bulk call
+        sa, sb, sc, sd = configs.system_inputs(p, int(s))
+        ok, e64, eld, eorc = parity.conditioned_error(x[p.layout.sys_rows(int(s))], sa, sb, sc, sd,
+                                                      parity.TOL_F64)
+        assert ok, (int(s), e64, eld, eorc)
 
 
 def test_default_plan_poisson_lines():
