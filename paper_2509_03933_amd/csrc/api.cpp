@@ -295,9 +295,9 @@ bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileS
 // M = 32, else 1024); the rolling walk (kernel 3).  In FP64 with 32 rows per
 // lane and 16 or 32 partitions covering n, the walk that recomputes its
 // pivots (kernel 7) with S = 32 (256-byte rows).  Measured on the 1024^3
-// Poisson lines in FP64: kernel 7 with 32 x 32 partitions x 32 rows 4.0 ms;
+// Poisson lines in FP64: kernel 7 with 32 x 32 partitions x 32 rows 3.9 ms;
 // kernel 3 with 16 x 32 x 32 4.5 ms, 16 x 64 x 16 6.0 ms, 8 x 32 x 32 7.3 ms;
-// on 1024^2 x 512 lines kernel 7 with 32 x 16 x 32 1.90 ms, kernel 3 with
+// on 1024^2 x 512 lines kernel 7 with 32 x 16 x 32 1.87 ms, kernel 3 with
 // 16 x 16 x 32 2.54 ms.
 static bool default_shift_shape(int dtype, int64_t n, int64_t nsys, TileShape *out) {
     const int Ms[] = {32, 16, 8};

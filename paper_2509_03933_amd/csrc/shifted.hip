@@ -39,7 +39,7 @@
 // HBM peak and 256-byte rows at 0.65, and a 32-system tile at 32 rows per
 // lane needs the whole register file when the pivots are kept beside the
 // right-hand sides.  The walk that recomputes them (kernel 7,
-// shift_solve_recomp) fits 32 systems in 1024 lanes: 4.0 ms, 0.53 of peak.
+// shift_solve_recomp) fits 32 systems in 1024 lanes: 3.9 ms, 0.55 of peak.
 #include <type_traits>
 
 #include "refine.h"
