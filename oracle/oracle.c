@@ -7,9 +7,9 @@
  * baseline use it.  It shares no code with the GPU library.
  *
  * What it computes: x = A^{-1} d for every system, where A is tridiagonal
- * with sub-diagonal a, diagonal b and super-diagonal c (the problem statement
- * "Ax = d, N times; input a, b, c, d; output x" of the paper's Algorithms 1
- * and 2).  The divide-and-conquer method of the paper (Sec. 2.1: decoupled
+ * with sub-diagonal a, diagonal b and super-diagonal c (the problem of the
+ * paper's Algorithms 1 and 2: N independent systems, from the three diagonals
+ * and the right-hand side to the solution).  The divide-and-conquer method of the paper (Sec. 2.1: decoupled
  * solve, reduced interface solve, correction x = x~ - Y y) is a direct method
  * that reaches exactly this x in exact arithmetic, so the oracle is that
  * definition computed by the textbook Thomas algorithm (LU factorisation

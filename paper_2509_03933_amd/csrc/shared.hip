@@ -282,26 +282,18 @@ __device__ __forceinline__ void shared_tables(const Coef &coef, int64_t n, const
 // Otherwise a wavefront shuffle (the caller's own value when out of range).
 template <int DL, bool DPP>
 __device__ __forceinline__ double lane_below(double v, int lane) {
-    if constexpr (DPP && DL < 16) {
-        const long long b = __double_as_longlong(v);
-        const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x110 + DL, 0xF, 0xF, true);
-        const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x110 + DL, 0xF, 0xF, true);
-        return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-    } else {
+    if constexpr (DPP && DL < 16)
+        return row_shift<DL, true>(v);
+    else
         return __shfl(v, lane >= DL ? lane - DL : lane);
-    }
 }
 
 template <int DL, bool DPP>
 __device__ __forceinline__ double lane_above(double v, int lane) {
-    if constexpr (DPP && DL < 16) {
-        const long long b = __double_as_longlong(v);
-        const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x100 + DL, 0xF, 0xF, true);
-        const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x100 + DL, 0xF, 0xF, true);
-        return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-    } else {
+    if constexpr (DPP && DL < 16)
+        return row_shift<DL, false>(v);
+    else
         return __shfl(v, lane + DL < 64 ? lane + DL : lane);
-    }
 }
 
 // The four neighbour values of one PCR step at distance DL: rows 2p and
