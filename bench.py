@@ -603,7 +603,7 @@ def bench_sweeps(args):
 def bench_ragged(args):
     """The 10,000 ragged systems alone (32..8192 rows, log-uniform lengths,
     per-row coefficients, contiguous rows): tdma_solve_batched, whose plan
-    buckets the systems by length and solves all buckets in one launch (a
+    buckets the systems by length and solves all buckets in two launches (a
     tile list); every system checked against the oracle in the oracle leg."""
     import numpy as np
     import torch
@@ -626,7 +626,8 @@ def bench_ragged(args):
                            "unknowns": unknowns, "entry_point": "tdma_solve_batched"},
                 "max_rel_err_vs_oracle": None,
                 "roofline": roofline(40 * unknowns, ms, "k_fused_tiles", "k_fused_tiles_ragged10000_f64",
-                                     note="one launch: the plan's tile list, longest systems first")}, checks
+                                     note="one solve: two launches of the plan's tile list (512- and 256-lane "
+                                          "blocks), longest systems first; bytes and time per solve")}, checks
 
 
 def bench_plain(args):

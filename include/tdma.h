@@ -104,10 +104,10 @@ typedef struct tdma_coeffs {
  * dtype: TDMA_F64 (FP64 storage and sweeps) or TDMA_F32 (FP32 storage and
  * sweeps, FP64 interface solve).  The partition count and tile shape come
  * from the autotune cache if it holds this shape, else a built-in rule.
- * A ragged batch is one launch: its systems are grouped by the partition
- * count they need and the groups cut into tiles of one block each (a plan
- * built on the first call with these offsets and cached); with b_shift it
- * takes one launch per group.
+ * A ragged batch with per-row coefficients is one launch per block size (at
+ * most two): its systems are grouped by the partition count they need and the
+ * groups cut into tiles of one block each (a plan built on the first call
+ * with these offsets and cached); otherwise it takes one launch per group.
  * A ragged layout on a stream that the caller is capturing into a graph is
  * refused with TDMA_EUNSUPPORTED (its plan tables are allocated and cached
  * by the library); tdma_graph_create records ragged solves instead.

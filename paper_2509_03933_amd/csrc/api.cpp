@@ -377,6 +377,14 @@ static bool default_perrow_shape(int dtype, int64_t n, int64_t nsys, TileShape *
 // covers len / M.  With the four per-row arrays loaded at once and staged
 // without bank conflicts, 16 rows per lane measured faster than 8 on the
 // longest systems (6,144 rows: 118 against 143 us for 1,245 systems).
+// Smallest block of the ragged tile list (lanes), the default min_block of
+// build_ragged_plan.  On the 10,000 systems of 32..8192 rows (FP64) alone:
+// blocks of 512 lanes throughout 248 us, 256 and 512 227 us, 128, 256 and
+// 512 242 us (each block size is a launch of its own).  Beside the
+// 768x512x1536 sweeps in a graph the 256-lane blocks take CUs from the
+// sweeps (graph 6.79 -> 6.86 ms), so graphs build their plans with 512-lane
+// blocks only.
+
 static void ragged_bucket(int dtype, int64_t len, int *M_out, int *P_out) {
     const int M = dtype == TDMA_F64 ? 16 : (len <= 6144 ? 32 : 16);
     const int64_t P = (len + M - 1) / M;
@@ -386,7 +394,7 @@ static void ragged_bucket(int dtype, int64_t len, int *M_out, int *P_out) {
     *P_out = (int)std::min<int64_t>(Pb, 1 << 30);
 }
 
-int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out) {
+int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out, int min_block) {
     const int64_t nsys = L->nsys0;
     std::map<std::pair<int, int>, std::vector<int32_t>> buckets;   // (M, P) -> systems
     for (int64_t k = 0; k < nsys; ++k) {
@@ -418,23 +426,37 @@ int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out) {
         all.insert(all.end(), kv.second.begin(), kv.second.end());
         rp.buckets.push_back(b);
     }
-    // the single-launch form: per rows-per-lane class, tiles of every bucket
-    // (longest systems first) whose S*P lanes fill a block of the class's
-    // largest size
+    // the tile-list form: per rows-per-lane class, tiles of every bucket
+    // (longest systems first) whose S*P lanes fill a block of
+    // max(min_block, P) lanes: smaller blocks let two run on a CU at once,
+    // one block's loads beside the other's arithmetic (one launch per block
+    // size)
     std::vector<RaggedTile> tiles;
-    std::vector<int> Ms;
-    for (const RaggedBucket &b : rp.buckets)
-        if (std::find(Ms.begin(), Ms.end(), b.shape.M) == Ms.end()) Ms.push_back(b.shape.M);
+    auto block_of = [&](int M, int P) {
+        const int maxt = fused_max_threads(dtype, M);
+        return std::min(maxt, std::max(min_block > 0 ? min_block : maxt, P));
+    };
+    std::vector<std::pair<int, int>> classes;   // (M, block lanes), largest blocks first
+    for (const RaggedBucket &b : rp.buckets) {
+        const std::pair<int, int> c{b.shape.M, block_of(b.shape.M, b.shape.P)};
+        if (std::find(classes.begin(), classes.end(), c) == classes.end()) classes.push_back(c);
+    }
+    std::sort(classes.begin(), classes.end(),
+              [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+                  return x.first != y.first ? x.first < y.first : x.second > y.second;
+              });
     bool groups_ok = true;
-    for (int M : Ms) {
+    for (const auto &cl : classes) {
+        const int M = cl.first;
         if (!fused_tiles_supported(dtype, M)) { groups_ok = false; break; }
         RaggedGroup g;
         g.M = M;
-        g.threads = fused_max_threads(dtype, M);
+        g.threads = cl.second;
         g.first_tile = (int64_t)tiles.size();
         std::vector<const RaggedBucket *> bs;
         for (const RaggedBucket &b : rp.buckets)
-            if (b.shape.M == M) bs.push_back(&b);
+            if (b.shape.M == M && block_of(M, b.shape.P) == cl.second) bs.push_back(&b);
+        if (bs.empty()) continue;
         std::sort(bs.begin(), bs.end(),
                   [](const RaggedBucket *x, const RaggedBucket *y) { return x->shape.P > y->shape.P; });
         for (const RaggedBucket *b : bs) {

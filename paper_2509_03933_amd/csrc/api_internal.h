@@ -33,8 +33,9 @@ struct RaggedPlan {
     int64_t *d_offsets = nullptr;
     int32_t *d_list = nullptr;
     std::vector<RaggedBucket> buckets;
-    // per-row coefficients: every bucket of one M in one launch (tile list,
-    // longest systems first); empty when a tile would not fit
+    // per-row coefficients: the buckets of one M and one block size in one
+    // launch (tile list, longest systems first); empty when a tile would not
+    // fit
     std::vector<RaggedGroup> groups;
     RaggedTile *d_tiles = nullptr;
 };
@@ -71,7 +72,10 @@ int validate(const tdma_layout *L, const tdma_coeffs *C, int dtype, const void *
 SysMap make_map(const tdma_layout *L);
 Coef make_coef(const tdma_coeffs *C);
 bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *out);
-int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out);
+// min_block: the smallest block of the per-row tile list (lanes): 256 for a
+// batch solved on its own (two blocks share a CU), the kernel's largest block
+// (0 = that) for a batch that runs beside other work, as in a graph.
+int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out, int min_block = 256);
 void free_ragged_plan(RaggedPlan *rp);
 int plan_ragged(DeviceCtx *ctx, const tdma_layout *L, int dtype, const RaggedPlan **out);
 // The buckets of a ragged plan on st and up to naux streams aux at once

@@ -89,7 +89,7 @@ extern "C" int tdma_graph_create(const tdma_work_item *items, int nitems, int dt
             pl.ragged = true;
             if (it.layout.nsys0 == 0) { pl.empty = true; continue; }
             RaggedPlan rp;
-            rc = build_ragged_plan(&it.layout, dtype, &rp);
+            rc = build_ragged_plan(&it.layout, dtype, &rp, 0);   // beside the chain: full blocks
             if (rc != TDMA_OK) break;
             pl.ragged_index = (int)g->ragged.size();
             g->ragged.push_back(rp);
