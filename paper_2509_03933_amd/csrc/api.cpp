@@ -377,14 +377,6 @@ static bool default_perrow_shape(int dtype, int64_t n, int64_t nsys, TileShape *
 // covers len / M.  With the four per-row arrays loaded at once and staged
 // without bank conflicts, 16 rows per lane measured faster than 8 on the
 // longest systems (6,144 rows: 118 against 143 us for 1,245 systems).
-// Smallest block of the ragged tile list (lanes), the default min_block of
-// build_ragged_plan.  On the 10,000 systems of 32..8192 rows (FP64) alone:
-// blocks of 512 lanes throughout 248 us, 256 and 512 227 us, 128, 256 and
-// 512 242 us (each block size is a launch of its own).  Beside the
-// 768x512x1536 sweeps in a graph the 256-lane blocks take CUs from the
-// sweeps (graph 6.79 -> 6.86 ms), so graphs build their plans with 512-lane
-// blocks only.
-
 static void ragged_bucket(int dtype, int64_t len, int *M_out, int *P_out) {
     const int M = dtype == TDMA_F64 ? 16 : (len <= 6144 ? 32 : 16);
     const int64_t P = (len + M - 1) / M;
@@ -394,6 +386,12 @@ static void ragged_bucket(int dtype, int64_t len, int *M_out, int *P_out) {
     *P_out = (int)std::min<int64_t>(Pb, 1 << 30);
 }
 
+// min_block, the smallest block of the per-row tile list (lanes): on the
+// 10,000 systems of 32..8192 rows (FP64) alone, blocks of 512 lanes
+// throughout 248 us, 256 and 512 227 us, 128, 256 and 512 242 us (each block
+// size is a launch of its own); beside the 768x512x1536 sweeps in a graph
+// the 256-lane blocks take CUs from the sweeps (graph 6.79 -> 6.86 ms), so
+// graphs build their plans with 512-lane blocks only.
 int build_ragged_plan(const tdma_layout *L, int dtype, RaggedPlan *out, int min_block) {
     const int64_t nsys = L->nsys0;
     std::map<std::pair<int, int>, std::vector<int32_t>> buckets;   // (M, P) -> systems
