@@ -234,10 +234,13 @@ bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *o
 // system's interface rows fit one wavefront), M rows per lane from
 // {16, 32, 8, 12, 24}, the one that pads the system least (P*M - n; 12 and
 // 24 fit the 3*2^k lengths exactly, measured 5-16% faster than padding them
-// to 16 or 32), the earlier in that order on ties.  Strided layouts take
+// to 16 or 32); on ties the earlier in that order for strided layouts, the
+// larger M (fewer partitions) for contiguous rows.  Strided layouts take
 // S = 32 systems per tile (measured best on the 256^3 ADI sweep in FP64 and
-// FP32), contiguous rows S = 8 and at least 256 lanes (best on x-lines of
-// n = 384 and 768); both as far as the lanes and LDS allow.  A streaming
+// FP32), contiguous rows S = 16 and at least 256 lanes; both as far as the
+// lanes and LDS allow.  Contiguous x-lines of n = 768 (FP64): 24 rows x 32
+// partitions x 16 systems 1.94 ms, 12 x 64 x 8 2.26 ms, 24 x 32 x 8 2.68 ms;
+// n = 384: 24 x 16 x 16 0.248 ms, 12 x 32 x 8 0.279 ms.  A streaming
 // block holds its CU's LDS for the whole launch, so the whole 160 KB is
 // available to it.  allow_roll admits the rolling form (kernel 6) below; the
 // streamed copy keeps the two-set shape, whose lane bound its kernel shares.
@@ -255,14 +258,15 @@ bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileS
         sh.M = M;
         sh.P = (int)P;
         sh.contig = contig;
-        int S_log2 = contig ? ilog2_floor(std::max<int64_t>(8, 256 / P)) : 5;
+        int S_log2 = contig ? ilog2_floor(std::max<int64_t>(16, 256 / P)) : 5;
         const int maxt = shared_max_threads(dtype, M, sh.kernel, contig);
         while (S_log2 > 0 && ((int64_t)1 << S_log2) * P > maxt) --S_log2;
         while (S_log2 > 0 && ((int64_t)1 << (S_log2 - 1)) >= nsys) --S_log2;
         sh.S_log2 = S_log2;
         while (sh.S_log2 > 0 && shared_lds_bytes(dtype, sh) > 160 * 1024) --sh.S_log2;
         if (!shared_supported(dtype, sh)) continue;
-        if (!found || (int64_t)sh.P * sh.M < (int64_t)best.P * best.M) {
+        const int64_t pad = (int64_t)sh.P * sh.M, best_pad = found ? (int64_t)best.P * best.M : 0;
+        if (!found || pad < best_pad || (contig && pad == best_pad && sh.M > best.M)) {
             best = sh;
             found = true;
         }
