@@ -234,8 +234,11 @@ bool default_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileShape *o
 // system's interface rows fit one wavefront), M rows per lane from
 // {16, 32, 8, 12, 24}, the one that pads the system least (P*M - n; 12 and
 // 24 fit the 3*2^k lengths exactly, measured 5-16% faster than padding them
-// to 16 or 32); on ties the earlier in that order for strided layouts, the
-// larger M (fewer partitions) for contiguous rows.  Strided layouts take
+// to 16 or 32); on ties, for strided layouts the one with at most 16
+// partitions (whose interface exchange is DPP row shifts; y-lines of
+// n = 512: 32 rows x 16 partitions 1.84 ms, 16 x 32 1.97-1.99 ms), then the
+// earlier in that order, for contiguous rows the larger M (fewer
+// partitions).  Strided layouts take
 // S = 32 systems per tile (measured best on the 256^3 ADI sweep in FP64 and
 // FP32), contiguous rows S = 16 and at least 256 lanes; both as far as the
 // lanes and LDS allow.  Contiguous x-lines of n = 768 (FP64): 24 rows x 32
@@ -266,7 +269,8 @@ bool default_shared_shape(int dtype, int64_t n, int64_t nsys, bool contig, TileS
         while (sh.S_log2 > 0 && shared_lds_bytes(dtype, sh) > 160 * 1024) --sh.S_log2;
         if (!shared_supported(dtype, sh)) continue;
         const int64_t pad = (int64_t)sh.P * sh.M, best_pad = found ? (int64_t)best.P * best.M : 0;
-        if (!found || pad < best_pad || (contig && pad == best_pad && sh.M > best.M)) {
+        const bool tie_wins = contig ? sh.M > best.M : (sh.P <= 16 && best.P > 16);
+        if (!found || pad < best_pad || (pad == best_pad && tie_wins)) {
             best = sh;
             found = true;
         }
