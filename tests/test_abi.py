@@ -103,6 +103,31 @@ def test_tiled_validation(tdma):
     assert tiled(16, 64, 16) == tdma.EINVAL   # 1024 lanes with M = 16 exceeds the 512 bound
 
 
+def test_tiled_kernel_rules(tdma):
+    """The walking kernels' shape rules are checked on the host, before any
+    device call: strided lines of 1024 rows, a shared operator with a shift
+    (kernels 3, 4, 7) or without (kernel 6)."""
+    lib = tdma.lib()
+    strided = tdma._Layout(1024, 8, 1, 8, 1, 0, None)
+    contig = tdma._Layout(1024, 8, 1, 1, 1024, 0, None)
+    shifted = tdma._Coeffs(1, 3, 4, 5, 6)
+    shared = tdma._Coeffs(1, 3, 4, 5, None)
+
+    def tiled(L, C, M, S, P, kernel, dtype=tdma.F64):
+        t = tdma._Tile(M, S, P, kernel)
+        return lib.tdma_solve_batched_tiled(ctypes.byref(L), ctypes.byref(C), dtype, ctypes.c_void_p(1),
+                                            ctypes.c_void_p(2), ctypes.byref(t), None)
+    EINVAL = tdma.EINVAL
+    assert tiled(strided, shifted, 32, 32, 32, 8) == EINVAL               # no kernel 8
+    assert tiled(strided, shifted, 32, 32, 32, 7, tdma.F32) == EINVAL     # kernel 7: FP64 only
+    assert tiled(strided, shifted, 32, 32, 16, 7) == EINVAL               # 512 rows < n
+    assert tiled(strided, shifted, 16, 32, 64, 7) == EINVAL               # 2048 lanes
+    assert tiled(strided, shifted, 8, 32, 128, 7) == EINVAL               # M 8, 128 partitions
+    assert tiled(strided, shifted, 32, 32, 32, 3) == EINVAL               # kernel 3: 512 lanes at M = 32
+    assert tiled(contig, shared, 16, 16, 64, 6) == EINVAL                 # kernel 6: strided rows only
+    assert tiled(tdma._Layout(1000, 8, 1, 8, 1, 0, None), shared, 16, 16, 64, 6) == EINVAL  # M*P != n
+
+
 def test_binding_bounds_checks(tdma):
     """A layout reaching past a tensor is refused before any device call."""
     torch = pytest.importorskip("torch")
