@@ -736,7 +736,7 @@ def oracle_errors(checks):
 
 def host_threads():
     """Host threads the oracle leg uses: the CPUs this process may run on,
-    at most 16 (a one-GPU machine's share)."""
+    at most 16 (the host share of one GPU on an 8-GPU node's CPUs)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
